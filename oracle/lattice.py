@@ -1,0 +1,123 @@
+"""Lattice descriptors (velocity sets, weights, moment matrices).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Velocity sets and weights follow Sec. 3.1, Eqs. (3-5) (D1Q3), (3-7) (D2Q5) and
+(3-10) (D3Q7), in the paper's direction order.  Velocities are in lattice units
+(c = dx/dt = 1; the scale invariance M0^-1 Lambda M0 = M^-1 Lambda M after
+Eq. (3-14) makes the C_d factor irrelevant).
+
+The moment matrix M0 is given by the paper only for D2Q5 (Eq. (3-14)).  For
+D1Q3 and D3Q7 we use matrices built the same way: row 0 is the conserved zeroth
+moment, then one row per first-order moment (the velocity components), then
+second-order rows.  Every row is either even or odd under k -> opposite(k).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Lattice:
+    name: str
+    d: int                 # spatial dimension
+    c: np.ndarray          # (q, 3) integer velocities (unused axes are 0)
+    w: np.ndarray          # (q,) weights omega_k
+    M0: np.ndarray         # (q, q) moment matrix
+    row_order: tuple       # moment order of each row of M0: 0, 1 or 2
+
+    @property
+    def q(self) -> int:
+        return len(self.w)
+
+    @property
+    def opposite(self) -> np.ndarray:
+        """Index kbar with c_kbar = -c_k (used by the bounce-back rules, Sec. 4)."""
+        opp = np.empty(self.q, dtype=np.int64)
+        for k in range(self.q):
+            hit = [j for j in range(self.q) if np.array_equal(self.c[j], -self.c[k])]
+            assert len(hit) == 1
+            opp[k] = hit[0]
+        return opp
+
+    @property
+    def cs2(self) -> float:
+        """Lattice sound speed squared, sum_k w_k c_kx^2.
+
+        The Chapman-Enskog analysis of Sec. 3.2 is carried out on D2Q5, where the
+        second moment of the weights is c^2/3 (Eqs. (3-22), (3-26), (3-27)).  On a
+        general lattice the same derivation produces sum_k w_k c_kx^2 in that
+        place: 1/3 on D1Q3 and D2Q5, 1/4 on D3Q7.
+        """
+        return float(np.sum(self.w * self.c[:, 0] ** 2))
+
+
+def _vel(rows):
+    c = np.zeros((len(rows), 3), dtype=np.int64)
+    for k, r in enumerate(rows):
+        c[k, : len(r)] = r
+    return c
+
+
+# Eq. (3-5): D1Q3, w = (2/3, 1/6, 1/6), c = (0, 1, -1).
+D1Q3 = Lattice(
+    name="D1Q3",
+    d=1,
+    c=_vel([(0,), (1,), (-1,)]),
+    w=np.array([2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0]),
+    M0=np.array(
+        [
+            [1.0, 1.0, 1.0],    # zeroth moment
+            [0.0, 1.0, -1.0],   # c_x
+            [-2.0, 1.0, 1.0],   # second order (even), orthogonal to row 0
+        ]
+    ),
+    row_order=(0, 1, 2),
+)
+
+# Eq. (3-7): D2Q5, w = (1/3, 1/6 x4); directions (0,0), (1,0), (0,1), (-1,0), (0,-1).
+# M0 is Eq. (3-14) with c = 1.
+D2Q5 = Lattice(
+    name="D2Q5",
+    d=2,
+    c=_vel([(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1)]),
+    w=np.array([1.0 / 3.0] + [1.0 / 6.0] * 4),
+    M0=np.array(
+        [
+            [1.0, 1.0, 1.0, 1.0, 1.0],
+            [0.0, 1.0, 0.0, -1.0, 0.0],
+            [0.0, 0.0, 1.0, 0.0, -1.0],
+            [0.0, 1.0, -1.0, 1.0, -1.0],
+            [-4.0, 1.0, 1.0, 1.0, 1.0],
+        ]
+    ),
+    row_order=(0, 1, 1, 2, 2),
+)
+
+# Eq. (3-10): D3Q7, w = (1/4, 1/8 x6); directions 0, +x, -x, +y, -y, +z, -z.
+D3Q7 = Lattice(
+    name="D3Q7",
+    d=3,
+    c=_vel([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]),
+    w=np.array([1.0 / 4.0] + [1.0 / 8.0] * 6),
+    M0=np.array(
+        [
+            [1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0],
+            [0.0, 1.0, -1.0, 0.0, 0.0, 0.0, 0.0],
+            [0.0, 0.0, 0.0, 1.0, -1.0, 0.0, 0.0],
+            [0.0, 0.0, 0.0, 0.0, 0.0, 1.0, -1.0],
+            [-6.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0],
+            [0.0, 2.0, 2.0, -1.0, -1.0, -1.0, -1.0],
+            [0.0, 0.0, 0.0, 1.0, 1.0, -1.0, -1.0],
+        ]
+    ),
+    row_order=(0, 1, 1, 1, 2, 2, 2),
+)
+
+LATTICES = {"D1Q3": D1Q3, "D2Q5": D2Q5, "D3Q7": D3Q7}
+
+
+def get(name: str) -> Lattice:
+    return LATTICES[name]
