@@ -1,0 +1,243 @@
+"""Benchmark of the fused Maxwell-Stefan lattice Boltzmann sweep on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload ternary_2d|quaternary_3d|ternary_1d]
+                    [--no-cpu-baseline] [--no-extras]
+
+Default workload: 2D ternary mixture on a 4096^2 D2Q5 lattice in FP32
+(periodic, smooth random field, random D_ij), K = 2000 steps timed after W
+warm-up steps.  One step is one fused collide-and-stream launch over every
+node (propagation with face rules, moments, the local Maxwell-Stefan solve,
+relaxation, store).  Prints one JSON line:
+
+  value        MLUPS = nodes * (N - 1) * K / seconds / 1e6 (node-component updates)
+  roofline     HBM roofline of the sweep kernel: algorithmic bytes per launch
+               (2 q (N-1) bytes-per-value per node: every distribution read
+               once and written once) over the average launch duration
+               measured with HIP events on the sweep's stream
+  cpu_baseline the FP64 numpy oracle on a bounded sample of the same workload
+  extras       the 3D quaternary workload and the other kernels, timed the same way
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+Q = {"D1Q3": 3, "D2Q5": 5, "D3Q7": 7}
+KERNEL_SOURCES = ["paper_1808_06787_amd/csrc/msd_device.h", "paper_1808_06787_amd/csrc/msd_kernels.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None if
+    absent or taken on a different version of the kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_workload(name: str):
+    import workloads
+
+    if name == "ternary_2d":
+        return workloads.ternary_2d()
+    if name == "quaternary_3d":
+        return workloads.quaternary_3d()
+    if name == "ternary_1d":
+        return workloads.ternary_1d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_sweep(w, steps: int, warmup: int, launch=None):
+    """Run warm-up then `steps` timed steps; returns (seconds, sim)."""
+    import torch
+
+    from paper_1808_06787_amd.sim import Sim
+
+    sim = Sim(w.lattice, w.D, w.shape, w.precision, bc=w.bc, relax=w.relax)
+    if launch:
+        sim.set_launch(**launch)
+    sim.init(torch.from_numpy(w.xi0))
+    sim.step(warmup)
+    stream = sim.stream
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3, sim
+
+
+def sweep_record(w, seconds, steps):
+    m = w.N - 1
+    q = Q[w.lattice]
+    s = 4 if w.precision == "f32" else 8
+    nodes = w.nodes
+    mlups = nodes * m * steps / seconds / 1e6
+    bytes_per_launch = nodes * m * 2 * q * s
+    per_launch = seconds / steps
+    achieved = bytes_per_launch / per_launch / 1e9
+    return mlups, bytes_per_launch, per_launch, achieved
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle (unchanged) on a bounded sub-grid of the workload, single thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import lbm
+
+    d = len(w.shape)
+    cap = {1: 1 << 30, 2: 512, 3: 96}[d]
+    sub = tuple(min(cap, n) for n in w.shape)
+    sl = tuple(slice(0, n) for n in sub[::-1])
+    xi0 = w.xi0[(slice(None),) + sl]
+    xi0 = xi0 / xi0.sum(axis=0, keepdims=True)
+    p = lbm.Problem(w.lattice, w.D, sub, bc=w.bc)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        f = lbm.init(p, xi0)
+        f = lbm.step(p, f)        # warm-up
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget_s:
+            f = lbm.step(p, f)
+            n += 1
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    nodes = int(np.prod(sub))
+    return {
+        "value": nodes * (w.N - 1) * n / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{'x'.join(map(str, sub))} sub-grid of the same field, {n} steps, FP64 numpy, 1 thread",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ternary_2d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--block-x", type=int, default=0)
+    ap.add_argument("--block-y", type=int, default=0)
+    ap.add_argument("--nontemporal", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sweep would shard by slabs with halo exchange; not implemented)", file=sys.stderr)
+        raise SystemExit(2)
+    import torch
+
+    from paper_1808_06787_amd import lib
+
+    lib()   # fail loudly if the HIP library is missing
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    steps = args.steps if args.steps is not None else w.steps
+    launch = dict(block_x=args.block_x, block_y=args.block_y, xcd_remap=args.xcd_remap,
+                  nontemporal=args.nontemporal)
+    print(f"# workload {w.name}: {w.lattice} N={w.N} shape={w.shape} {w.precision}; "
+          f"warmup {args.warmup}, timing {steps} steps", file=sys.stderr, flush=True)
+    seconds, sim = time_sweep(w, steps, args.warmup, launch)
+    mlups, bpl, per_launch, achieved = sweep_record(w, seconds, steps)
+    _, _, _, bad = sim.diagnostics(raise_on_diverged=False)
+    used_launch = sim.get_launch()
+    sim.close()
+    del sim
+    traffic = load_traffic(w.name)
+    out = {
+        "metric": "MLUPS (node-component updates per second) of the fused collide-and-stream sweep",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_launch * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.precision == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": w.lattice, "n_species": w.N, "extents": list(w.shape),
+                   "faces": [list(b) for b in w.bc], "precision": w.precision, "launch": used_launch},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bpl,
+        },
+        "nonfinite": bad,
+    }
+    print(f"# {w.name}: {mlups:.0f} MLUPS, {per_launch * 1e3:.4f} ms/step, {achieved:.0f} GB/s "
+          f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)", file=sys.stderr, flush=True)
+    extras = {}
+    if not args.no_extras and args.workload == "ternary_2d":
+        w3 = make_workload("quaternary_3d")
+        s3, sim3 = time_sweep(w3, w3.steps, 5)
+        sim3.close()
+        m3, b3, p3, a3 = sweep_record(w3, s3, w3.steps)
+        extras["quaternary_3d_d3q7_512^3_f32"] = {
+            "MLUPS": round(m3, 1), "ms_per_step": round(p3 * 1e3, 4), "steps": w3.steps,
+            "GB_per_s": round(a3, 1), "hbm_frac": round(a3 / HBM_PEAK_GBS, 4)}
+        print(f"# {w3.name}: {m3:.0f} MLUPS, {a3:.0f} GB/s ({100 * a3 / HBM_PEAK_GBS:.1f}%)",
+              file=sys.stderr, flush=True)
+        del w3
+        w1 = make_workload("ternary_1d")
+        s1, sim1 = time_sweep(w1, w1.steps, 0)
+        sim1.close()
+        m1 = w1.nodes * (w1.N - 1) * w1.steps / s1 / 1e6
+        extras["ternary_1d_d1q3_256_f64"] = {"MLUPS": round(m1, 2), "steps_per_s": round(w1.steps / s1, 1),
+                                             "seconds": round(s1, 5)}
+        print(f"# {w1.name}: {m1:.1f} MLUPS, {w1.steps / s1:.0f} steps/s", file=sys.stderr, flush=True)
+    if extras:
+        out["extras"] = extras
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * msd.h - C ABI of the MI355X lattice Boltzmann solver for Maxwell-Stefan
+ * diffusion in N-component mixtures.
+ *
+ * Method: Chai, Guo, Wang & Shi, "Maxwell-Stefan theory based lattice
+ * Boltzmann model for diffusion in multicomponent mixtures".  Every quantity
+ * crossing this boundary is in lattice units (dx = dt = 1; physical D_ij map
+ * to D_ij dt / dx^2, Sec. 3.1 after Eq. (3-11)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Species 1..N of the paper are 0..N-1 here.  Species N-1 (the paper's n)
+ *   is the eliminated one (Sec. 2, Eq. (2-8a)); only m = N-1 species carry
+ *   distributions (Sec. 3.1, Eq. (3-2)).
+ * - Node fields ("planes") are dense arrays of nx*ny*nz values with x fastest,
+ *   then y, then z.  A multi-plane buffer holds its planes back to back.
+ * - Pointers named d_* are device pointers (HIP device memory on the GPU the
+ *   handle was created on); h_* are host pointers.  The library never
+ *   allocates device memory: all device storage is a caller-owned workspace.
+ * - Work is enqueued on the HIP stream given at creation (a hipStream_t passed
+ *   as void*; NULL is the default stream) and is asynchronous unless the
+ *   entry point says it synchronises.
+ * - Every int-returning call returns MSD_OK (0) or a negative status; a
+ *   thread-local description of the last failure is in msd_last_error().
+ * - A handle must not be used from two host threads at once.
+ */
+#ifndef MSD_H
+#define MSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define MSD_API __attribute__((visibility("default")))
+#else
+#define MSD_API
+#endif
+
+#define MSD_ABI_VERSION 1
+#define MSD_MAX_SPECIES 8
+
+/* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10). */
+enum msd_lattice { MSD_D1Q3 = 1, MSD_D2Q5 = 2, MSD_D3Q7 = 3 };
+
+/* Storage and arithmetic precision of the sweep (bytes per value). */
+enum msd_precision { MSD_F32 = 4, MSD_F64 = 8 };
+
+/* Second-order relaxation: MSD_RELAX_PAPER is Eq. (3-16) (lambda_2^ii =
+ * 8(lambda_1^ii - 2)/(lambda_1^ii - 8), off-diagonal lambda_2^ij = lambda_1^ij);
+ * MSD_RELAX_SRT sets every relaxation parameter to lambda_1 (the single-
+ * relaxation-time special case named after Eq. (3-14)). */
+enum msd_relax { MSD_RELAX_PAPER = 0, MSD_RELAX_SRT = 1 };
+
+/* Face conditions, Sec. 4: half-way bounce-back gives zero flux, half-way
+ * anti-bounce-back holds a Dirichlet mole fraction.  Periodic faces come in
+ * pairs. */
+enum msd_bc { MSD_BC_PERIODIC = 0, MSD_BC_ZERO_FLUX = 1, MSD_BC_DIRICHLET = 2 };
+
+enum msd_status {
+  MSD_OK = 0,
+  MSD_EINVAL = -1,      /* bad lattice, extents, species count, faces or pointer */
+  MSD_EDIFF = -2,       /* D not symmetric or an off-diagonal D_ij <= 0 (Sec. 2, after Eq. (2-7)) */
+  MSD_ECOMP = -3,       /* a composition (wall or reference) off the simplex */
+  MSD_ERELAX = -4,      /* unknown relaxation rule */
+  MSD_EHIP = -5,        /* a HIP runtime call failed; msd_last_error() has its text */
+  MSD_EDIVERGED = -6,   /* diagnostics found non-finite mole fractions */
+  MSD_ENOMEM = -7,      /* workspace smaller than msd_workspace_bytes() */
+  MSD_EABI = -8,        /* problem.abi != MSD_ABI_VERSION */
+  MSD_ESTATE = -9       /* call not valid in the handle's current state */
+};
+
+/* The problem as the paper states it: lattice, N, the Maxwell-Stefan
+ * diffusivities D_ij, relaxation rule, faces and (optionally) the
+ * linearised-theory reference composition.  All host arrays are read during
+ * msd_create / msd_workspace_bytes only and stay owned by the caller. */
+typedef struct msd_problem {
+  int32_t abi;              /* MSD_ABI_VERSION */
+  int32_t lattice;          /* enum msd_lattice */
+  int32_t n_species;        /* N, 2 .. MSD_MAX_SPECIES */
+  int32_t precision;        /* enum msd_precision */
+  int64_t nx, ny, nz;       /* extents; unused dimensions must be 1; nx*ny*nz < 2^31 */
+  const double* D;          /* N*N row-major, symmetric, D_ij > 0 for i != j; diagonal ignored */
+  const double* xi_wall;    /* 6*N row-major face values [x_lo, x_hi, y_lo, y_hi, z_lo, z_hi][N],
+                               read for Dirichlet faces only; may be NULL if none */
+  const double* xi_ref;     /* N values; used when linearized != 0 */
+  double c_t;               /* total molar concentration in J = -c_t D~ grad xi (Eq. (2-12)); > 0 */
+  int32_t relax;            /* enum msd_relax */
+  int32_t linearized;       /* 0: B(xi) at the local composition (Eq. (2-10));
+                               1: B frozen at xi_ref (linearised theory, constant D~) */
+  int32_t bc[6];            /* enum msd_bc for faces x_lo, x_hi, y_lo, y_hi, z_lo, z_hi */
+  int32_t reserved[2];      /* must be 0 */
+} msd_problem;
+
+typedef struct msd_sim msd_sim;
+typedef struct msd_batch msd_batch;
+
+/* ---------------------------------------------------------------------------
+ * Single mixture
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace msd_create needs for this problem (two ping-pong
+ * distribution buffers of m*q planes each, padded, plus reduction scratch).
+ * Returns 0 and sets *status (if non-NULL) on an invalid problem. */
+MSD_API size_t msd_workspace_bytes(const msd_problem* problem, int32_t* status);
+
+/* Validate the problem, lay out the workspace d_ws (>= msd_workspace_bytes,
+ * 256-byte aligned, caller-owned, must outlive the handle) and return a host
+ * handle in *out.  No kernel is launched.  Errors: EABI, EINVAL, EDIFF, ECOMP,
+ * ERELAX, ENOMEM. */
+MSD_API int msd_create(const msd_problem* problem, void* d_ws, size_t ws_bytes, void* stream, msd_sim** out);
+
+/* Replace the stream used by later calls. */
+MSD_API int msd_set_stream(msd_sim* sim, void* stream);
+
+/* Initialise f_k^i(x, 0) = w_k xi_i(x, 0) (Sec. 4, initialisation; Eq. (3-3)) and
+ * reset the time to 0.  d_xi0 holds N (or at least N-1) planes in precision
+ * xi0_precision (MSD_F32 or MSD_F64); planes beyond N-1 are not read, since
+ * xi of the eliminated species follows from Eq. (2-3b). */
+MSD_API int msd_init(msd_sim* sim, const void* d_xi0, int32_t xi0_precision);
+
+/* Advance nsteps >= 0 time steps of Eq. (3-13): at every node, collision in
+ * moment space with the Maxwell-Stefan relaxation matrices (Eqs. (2-10),
+ * (2-11), (3-26), (3-16)) fused with propagation and the face rules of Sec. 4.
+ * Asynchronous. */
+MSD_API int msd_step(msd_sim* sim, int64_t nsteps);
+
+/* Number of steps taken since msd_init (or the value given to msd_restore). */
+MSD_API int64_t msd_time(const msd_sim* sim);
+
+/* Write the observables of the pre-collision state at the current time:
+ *   d_xi   : N planes, xi_i = sum_k f_k^i (Eq. (3-15)) and xi_N = 1 - sum (Eq. (2-3b));
+ *   d_J    : m*d planes [species][component x,y,z], J = -c_t D~ grad xi (Eq. (2-12)),
+ *            or NULL;
+ *   d_grad : m*d planes, grad xi from the non-equilibrium first moments
+ *            (Eq. (3-27), with the lattice's sound speed squared), or NULL.
+ * out_precision (MSD_F32 / MSD_F64) is the element type of all outputs. */
+MSD_API int msd_read_moments(msd_sim* sim, int32_t out_precision, void* d_xi, void* d_J, void* d_grad);
+
+/* Conservation diagnostics of the current state, computed on the device with
+ * a deterministic two-pass reduction in FP64 and copied to the host (this
+ * call synchronises the stream): per-species totals sum_x xi_i (constant for
+ * periodic and zero-flux faces, Eq. (2-1)), per-species minimum and maximum
+ * (arrays of N; may be NULL) and the number of non-finite mole fractions.
+ * Returns MSD_EDIVERGED when that number is non-zero. */
+MSD_API int msd_diagnostics(msd_sim* sim, double* h_mass, double* h_min, double* h_max, int64_t* h_nonfinite);
+
+/* Checkpoint / restart: the state is the m*q planes of distributions of the
+ * current buffer; msd_state_bytes is its size.  msd_save copies it (device to
+ * device, asynchronous) into d_dst and returns the time in *h_step;
+ * msd_restore copies it back and sets the time. */
+MSD_API size_t msd_state_bytes(const msd_sim* sim);
+MSD_API int msd_save(const msd_sim* sim, void* d_dst, int64_t* h_step);
+MSD_API int msd_restore(msd_sim* sim, const void* d_src, int64_t step);
+
+/* Free the host handle (the workspace stays the caller's). */
+MSD_API int msd_destroy(msd_sim* sim);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning of the single-mixture sweep
+ * ------------------------------------------------------------------------- */
+
+/* block_x * block_y threads per workgroup (block_x a multiple of 64, product
+ * <= 256; 0 = library default); xcd_remap = 1 maps consecutive tiles to one
+ * of the eight XCDs so that neighbouring rows share an L2; lds_resident = 1
+ * allows the single-workgroup kernel that keeps a small domain in LDS for all
+ * steps of one msd_step call (used only when the domain fits). */
+typedef struct msd_launch {
+  int32_t block_x;
+  int32_t block_y;
+  int32_t xcd_remap;
+  int32_t lds_resident;
+  int32_t nontemporal;      /* 1: streaming stores bypass the caches */
+  int32_t reserved[3];
+} msd_launch;
+
+MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);
+MSD_API int msd_get_launch(const msd_sim* sim, msd_launch* launch);
+
+/* ---------------------------------------------------------------------------
+ * Errors and version
+ * ------------------------------------------------------------------------- */
+
+MSD_API const char* msd_strerror(int status);
+MSD_API const char* msd_last_error(void);
+MSD_API int msd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSD_H */

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/msd.h.
+
+Loading fails loudly if the HIP library has not been built: there is no
+fallback implementation of the sweep in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmsd.so")
+
+ABI_VERSION = 1
+MAX_SPECIES = 8
+
+D1Q3, D2Q5, D3Q7 = 1, 2, 3
+F32, F64 = 4, 8
+RELAX_PAPER, RELAX_SRT = 0, 1
+BC_PERIODIC, BC_ZERO_FLUX, BC_DIRICHLET = 0, 1, 2
+
+OK = 0
+STATUS = {
+    0: "MSD_OK", -1: "MSD_EINVAL", -2: "MSD_EDIFF", -3: "MSD_ECOMP", -4: "MSD_ERELAX",
+    -5: "MSD_EHIP", -6: "MSD_EDIVERGED", -7: "MSD_ENOMEM", -8: "MSD_EABI", -9: "MSD_ESTATE",
+}
+
+
+class MsdProblem(C.Structure):
+    _fields_ = [
+        ("abi", C.c_int32),
+        ("lattice", C.c_int32),
+        ("n_species", C.c_int32),
+        ("precision", C.c_int32),
+        ("nx", C.c_int64),
+        ("ny", C.c_int64),
+        ("nz", C.c_int64),
+        ("D", C.POINTER(C.c_double)),
+        ("xi_wall", C.POINTER(C.c_double)),
+        ("xi_ref", C.POINTER(C.c_double)),
+        ("c_t", C.c_double),
+        ("relax", C.c_int32),
+        ("linearized", C.c_int32),
+        ("bc", C.c_int32 * 6),
+        ("reserved", C.c_int32 * 2),
+    ]
+
+
+class MsdLaunch(C.Structure):
+    _fields_ = [
+        ("block_x", C.c_int32),
+        ("block_y", C.c_int32),
+        ("xcd_remap", C.c_int32),
+        ("lds_resident", C.c_int32),
+        ("nontemporal", C.c_int32),
+        ("reserved", C.c_int32 * 3),
+    ]
+
+
+class MsdError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({detail})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library {LIB_PATH} is missing; build it with "
+            "`python -m paper_1808_06787_amd.build` (no CPU fallback exists)"
+        )
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "msd_abi_version": (C.c_int, []),
+        "msd_last_error": (C.c_char_p, []),
+        "msd_strerror": (C.c_char_p, [C.c_int]),
+        "msd_workspace_bytes": (sz, [P(MsdProblem), P(i32)]),
+        "msd_create": (C.c_int, [P(MsdProblem), vp, sz, vp, P(vp)]),
+        "msd_set_stream": (C.c_int, [vp, vp]),
+        "msd_set_launch": (C.c_int, [vp, P(MsdLaunch)]),
+        "msd_get_launch": (C.c_int, [vp, P(MsdLaunch)]),
+        "msd_init": (C.c_int, [vp, vp, i32]),
+        "msd_step": (C.c_int, [vp, i64]),
+        "msd_time": (i64, [vp]),
+        "msd_read_moments": (C.c_int, [vp, i32, vp, vp, vp]),
+        "msd_diagnostics": (C.c_int, [vp, P(C.c_double), P(C.c_double), P(C.c_double), P(i64)]),
+        "msd_state_bytes": (sz, [vp]),
+        "msd_save": (C.c_int, [vp, vp, P(i64)]),
+        "msd_restore": (C.c_int, [vp, vp, i64]),
+        "msd_destroy": (C.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if L.msd_abi_version() != ABI_VERSION:
+        raise RuntimeError("libmsd ABI version mismatch; rebuild the library")
+    _lib = L
+    return L
+
+
+def check(status: int, what: str) -> int:
+    if status != OK:
+        detail = lib().msd_last_error().decode(errors="replace")
+        raise MsdError(status, what, detail)
+    return status

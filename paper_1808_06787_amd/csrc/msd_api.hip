@@ -1,0 +1,427 @@
+// C ABI of the solver (include/msd.h): validation, workspace layout, time
+// stepping and read-out.  Host code here only checks arguments, lays out the
+// caller's workspace and launches kernels; all arithmetic of the method runs
+// on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/msd.h"
+#include "msd_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(MSD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int lattice_q(int lat) { return lat == MSD_D1Q3 ? 3 : (lat == MSD_D2Q5 ? 5 : 7); }
+int lattice_d(int lat) { return lat == MSD_D1Q3 ? 1 : (lat == MSD_D2Q5 ? 2 : 3); }
+
+constexpr int kDiagBlocksMax = 1024;
+
+struct Layout {
+  int64_t nodes = 0, plane = 0;
+  size_t consts_off = 0, partials_off = 0, diag_out_off = 0, half_off[2] = {0, 0};
+  size_t half_bytes = 0, total = 0;
+  int diag_blocks = 0;
+};
+
+int validate(const msd_problem* p) {
+  if (!p) return fail(MSD_EINVAL, "problem is NULL");
+  if (p->abi != MSD_ABI_VERSION) return fail(MSD_EABI, "problem.abi = %d, library ABI = %d", p->abi, MSD_ABI_VERSION);
+  if (p->lattice != MSD_D1Q3 && p->lattice != MSD_D2Q5 && p->lattice != MSD_D3Q7)
+    return fail(MSD_EINVAL, "unknown lattice %d", p->lattice);
+  if (p->n_species < 2 || p->n_species > MSD_MAX_SPECIES)
+    return fail(MSD_EINVAL, "n_species = %d outside [2, %d]", p->n_species, MSD_MAX_SPECIES);
+  if (p->precision != MSD_F32 && p->precision != MSD_F64) return fail(MSD_EINVAL, "unknown precision %d", p->precision);
+  const int d = lattice_d(p->lattice);
+  const int64_t ext[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (ext[a] < 1) return fail(MSD_EINVAL, "extent %d is %lld", a, (long long)ext[a]);
+    if (a >= d && ext[a] != 1) return fail(MSD_EINVAL, "extent %d must be 1 on a %dD lattice", a, d);
+    if (ext[a] > (int64_t)1 << 30) return fail(MSD_EINVAL, "extent %d too large", a);
+  }
+  if (p->nx * p->ny * p->nz >= ((int64_t)1 << 31)) return fail(MSD_EINVAL, "more than 2^31 - 1 nodes");
+  if (p->reserved[0] || p->reserved[1]) return fail(MSD_EINVAL, "reserved fields must be 0");
+  if (!p->D) return fail(MSD_EINVAL, "D is NULL");
+  const int N = p->n_species;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (i == j) continue;
+      const double v = p->D[i * N + j];
+      if (!(v > 0.0) || !std::isfinite(v)) return fail(MSD_EDIFF, "D[%d][%d] = %g is not positive", i, j, v);
+      if (v != p->D[j * N + i]) return fail(MSD_EDIFF, "D is not symmetric at (%d, %d)", i, j);
+    }
+  if (!(p->c_t > 0.0) || !std::isfinite(p->c_t)) return fail(MSD_EINVAL, "c_t = %g must be positive", p->c_t);
+  if (p->relax != MSD_RELAX_PAPER && p->relax != MSD_RELAX_SRT) return fail(MSD_ERELAX, "unknown relax %d", p->relax);
+  bool need_wall = false;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
+    for (int s = 0; s < 2; ++s) {
+      const int b = p->bc[2 * a + s];
+      if (b != MSD_BC_PERIODIC && b != MSD_BC_ZERO_FLUX && b != MSD_BC_DIRICHLET)
+        return fail(MSD_EINVAL, "unknown face condition %d", b);
+      if (a >= d && b != MSD_BC_PERIODIC) return fail(MSD_EINVAL, "faces of unused axis %d must be periodic", a);
+      if (b == MSD_BC_DIRICHLET) need_wall = true;
+    }
+    if ((lo == MSD_BC_PERIODIC) != (hi == MSD_BC_PERIODIC))
+      return fail(MSD_EINVAL, "periodic faces on axis %d must come in pairs", a);
+  }
+  auto on_simplex = [N](const double* x) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+      if (!std::isfinite(x[i])) return false;
+      s += x[i];
+    }
+    return std::fabs(s - 1.0) <= 1e-9;
+  };
+  if (need_wall) {
+    if (!p->xi_wall) return fail(MSD_EINVAL, "Dirichlet faces need xi_wall");
+    for (int f = 0; f < 6; ++f)
+      if (p->bc[f] == MSD_BC_DIRICHLET && !on_simplex(p->xi_wall + f * N))
+        return fail(MSD_ECOMP, "wall composition of face %d does not sum to 1", f);
+  }
+  if (p->linearized) {
+    if (!p->xi_ref) return fail(MSD_EINVAL, "linearized needs xi_ref");
+    if (!on_simplex(p->xi_ref)) return fail(MSD_ECOMP, "xi_ref does not sum to 1");
+  }
+  return MSD_OK;
+}
+
+Layout layout_for(const msd_problem* p) {
+  Layout L;
+  const int m = p->n_species - 1, q = lattice_q(p->lattice), s = p->precision;
+  L.nodes = p->nx * p->ny * p->nz;
+  // Planes are padded to a multiple of 64 values plus 64 more, so that the
+  // m*q concurrent plane streams do not start at power-of-two strides.
+  L.plane = (L.nodes + 63) / 64 * 64 + 64;
+  L.diag_blocks = (int)std::min<int64_t>(kDiagBlocksMax, (L.nodes + 255) / 256);
+  size_t off = 0;
+  L.consts_off = off;
+  off = align_up(off + msd::kConstsBytes, 256);
+  L.partials_off = off;
+  off = align_up(off + sizeof(double) * (size_t)L.diag_blocks * (3 * p->n_species + 1), 256);
+  L.diag_out_off = off;
+  off = align_up(off + sizeof(double) * (3 * MSD_MAX_SPECIES + 1), 256);
+  L.half_bytes = align_up((size_t)m * q * (size_t)L.plane * s, 256);
+  L.half_off[0] = off;
+  off += L.half_bytes;
+  L.half_off[1] = off;
+  off += L.half_bytes;
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct msd_sim {
+  msd_problem prob;          // pointers inside are not kept
+  msd::Problem kp;           // kernel copy of the problem
+  Layout L;
+  int m = 0, q = 0, d = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;               // which half holds the state
+  int64_t t = 0;
+  bool initialised = false;
+  msd_launch launch{};
+};
+
+namespace {
+
+msd::LaunchArgs base_args(const msd_sim* s) {
+  msd::LaunchArgs a;
+  a.p = s->kp;
+  a.lattice = s->prob.lattice;
+  a.m = s->m;
+  a.prec = s->prob.precision;
+  a.stream = s->stream;
+  a.consts = s->ws + s->L.consts_off;
+  a.n_species = s->prob.n_species;
+  a.block_x = s->launch.block_x;
+  a.block_y = s->launch.block_y;
+  a.xcd_remap = s->launch.xcd_remap;
+  a.nontemporal = s->launch.nontemporal;
+  return a;
+}
+
+hipError_t dispatch(msd::Op op, const msd::LaunchArgs& a) {
+  switch (a.lattice) {
+    case MSD_D1Q3: return msd::dispatch<1>(op, a);
+    case MSD_D2Q5: return msd::dispatch<2>(op, a);
+    case MSD_D3Q7: return msd::dispatch<3>(op, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+void default_launch(const msd_problem* p, msd_launch* l) {
+  std::memset(l, 0, sizeof(*l));
+  const int64_t nx = p->nx;
+  l->block_x = (int)std::min<int64_t>(256, (nx + 63) / 64 * 64);
+  l->block_y = std::max(1, (int)std::min<int64_t>(256 / l->block_x, p->ny));
+  l->xcd_remap = 1;
+  l->lds_resident = 1;
+  l->nontemporal = 0;
+}
+
+bool use_lds(const msd_sim* s) {
+  if (!s->launch.lds_resident) return false;
+  const int64_t cap = msd::lds_resident_max_nodes(s->m, s->q, s->prob.precision);
+  return s->L.nodes <= cap && s->L.nodes <= 4096;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msd_abi_version(void) { return MSD_ABI_VERSION; }
+
+const char* msd_last_error(void) { return g_last_error.c_str(); }
+
+const char* msd_strerror(int status) {
+  switch (status) {
+    case MSD_OK: return "ok";
+    case MSD_EINVAL: return "invalid argument";
+    case MSD_EDIFF: return "invalid diffusivity matrix";
+    case MSD_ECOMP: return "composition off the simplex";
+    case MSD_ERELAX: return "invalid relaxation rule";
+    case MSD_EHIP: return "HIP runtime error";
+    case MSD_EDIVERGED: return "non-finite mole fractions";
+    case MSD_ENOMEM: return "workspace too small";
+    case MSD_EABI: return "ABI version mismatch";
+    case MSD_ESTATE: return "call not valid in this state";
+    default: return "unknown status";
+  }
+}
+
+size_t msd_workspace_bytes(const msd_problem* problem, int32_t* status) {
+  const int st = validate(problem);
+  if (status) *status = st;
+  if (st != MSD_OK) return 0;
+  return layout_for(problem).total;
+}
+
+int msd_create(const msd_problem* problem, void* d_ws, size_t ws_bytes, void* stream, msd_sim** out) {
+  if (!out) return fail(MSD_EINVAL, "out is NULL");
+  *out = nullptr;
+  const int st = validate(problem);
+  if (st != MSD_OK) return st;
+  const Layout L = layout_for(problem);
+  if (!d_ws) return fail(MSD_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(MSD_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(MSD_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  msd_sim* s = new (std::nothrow) msd_sim();
+  if (!s) return fail(MSD_EINVAL, "host allocation failed");
+  s->prob = *problem;
+  s->prob.D = nullptr;
+  s->prob.xi_wall = nullptr;
+  s->prob.xi_ref = nullptr;
+  s->L = L;
+  s->m = problem->n_species - 1;
+  s->q = lattice_q(problem->lattice);
+  s->d = lattice_d(problem->lattice);
+  s->ws = static_cast<char*>(d_ws);
+  s->stream = static_cast<hipStream_t>(stream);
+  msd::Problem& kp = s->kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.nx = (int32_t)problem->nx;
+  kp.ny = (int32_t)problem->ny;
+  kp.nz = (int32_t)problem->nz;
+  kp.relax = problem->relax;
+  kp.linearized = problem->linearized ? 1 : 0;
+  for (int f = 0; f < 6; ++f) kp.bc[f] = problem->bc[f];
+  kp.plane = L.plane;
+  kp.c_t = problem->c_t;
+  const int N = problem->n_species;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) kp.D[i][j] = (i == j) ? 1.0 : problem->D[i * N + j];
+  for (int f = 0; f < 6; ++f)
+    for (int i = 0; i < N; ++i)
+      kp.wall[f][i] = (problem->bc[f] == MSD_BC_DIRICHLET) ? problem->xi_wall[f * N + i] : 0.0;
+  if (problem->linearized)
+    for (int i = 0; i < N; ++i) kp.xi_ref[i] = problem->xi_ref[i];
+  default_launch(problem, &s->launch);
+  *out = s;
+  return MSD_OK;
+}
+
+int msd_set_stream(msd_sim* s, void* stream) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  s->stream = static_cast<hipStream_t>(stream);
+  return MSD_OK;
+}
+
+int msd_set_launch(msd_sim* s, const msd_launch* l) {
+  if (!s || !l) return fail(MSD_EINVAL, "NULL argument");
+  msd_launch v = *l;
+  if (v.block_x == 0 && v.block_y == 0) {
+    msd_launch d;
+    default_launch(&s->prob, &d);
+    v.block_x = d.block_x;
+    v.block_y = d.block_y;
+  }
+  if (v.block_x < 64 || v.block_x % 64 || v.block_y < 1 || v.block_x * v.block_y > 256)
+    return fail(MSD_EINVAL, "block %d x %d: block_x must be a positive multiple of 64, product <= 256", v.block_x,
+                v.block_y);
+  s->launch = v;
+  return MSD_OK;
+}
+
+int msd_get_launch(const msd_sim* s, msd_launch* l) {
+  if (!s || !l) return fail(MSD_EINVAL, "NULL argument");
+  *l = s->launch;
+  return MSD_OK;
+}
+
+int msd_init(msd_sim* s, const void* d_xi0, int32_t xi0_precision) {
+  if (!s || !d_xi0) return fail(MSD_EINVAL, "NULL argument");
+  if (xi0_precision != MSD_F32 && xi0_precision != MSD_F64) return fail(MSD_EINVAL, "xi0_precision %d", xi0_precision);
+  msd::LaunchArgs a = base_args(s);
+  a.consts_out = s->ws + s->L.consts_off;
+  hipError_t e = dispatch(msd::Op::Constants, a);
+  if (e != hipSuccess) return hip_fail(e, "constants kernel");
+  a.xi0 = d_xi0;
+  a.in_prec = xi0_precision;
+  s->cur = 0;
+  a.dst = s->ws + s->L.half_off[0];
+  e = dispatch(msd::Op::Init, a);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  s->t = 0;
+  s->initialised = true;
+  return MSD_OK;
+}
+
+int msd_step(msd_sim* s, int64_t nsteps) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  if (!s->initialised) return fail(MSD_ESTATE, "msd_step before msd_init");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return MSD_OK;
+  msd::LaunchArgs a = base_args(s);
+  if (use_lds(s)) {
+    a.src = s->ws + s->L.half_off[s->cur];
+    a.dst = s->ws + s->L.half_off[1 - s->cur];
+    a.pull = s->t > 0 ? 1 : 0;
+    a.nsteps = nsteps;
+    const hipError_t e = dispatch(msd::Op::StepLds, a);
+    if (e != hipSuccess) return hip_fail(e, "LDS-resident step kernel");
+    s->cur = 1 - s->cur;
+    s->t += nsteps;
+    return MSD_OK;
+  }
+  for (int64_t n = 0; n < nsteps; ++n) {
+    a.src = s->ws + s->L.half_off[s->cur];
+    a.dst = s->ws + s->L.half_off[1 - s->cur];
+    a.pull = s->t > 0 ? 1 : 0;
+    const hipError_t e = dispatch(msd::Op::Step, a);
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+    s->cur = 1 - s->cur;
+    s->t += 1;
+  }
+  return MSD_OK;
+}
+
+int64_t msd_time(const msd_sim* s) { return s ? s->t : -1; }
+
+int msd_read_moments(msd_sim* s, int32_t out_precision, void* d_xi, void* d_J, void* d_grad) {
+  if (!s || !d_xi) return fail(MSD_EINVAL, "NULL argument");
+  if (!s->initialised) return fail(MSD_ESTATE, "read before msd_init");
+  if (out_precision != MSD_F32 && out_precision != MSD_F64) return fail(MSD_EINVAL, "out_precision %d", out_precision);
+  msd::LaunchArgs a = base_args(s);
+  a.src = s->ws + s->L.half_off[s->cur];
+  a.pull = s->t > 0 ? 1 : 0;
+  a.out_prec = out_precision;
+  a.out_xi = d_xi;
+  a.out_J = d_J;
+  a.out_grad = d_grad;
+  const hipError_t e = dispatch(msd::Op::Read, a);
+  if (e != hipSuccess) return hip_fail(e, "read kernel");
+  return MSD_OK;
+}
+
+int msd_diagnostics(msd_sim* s, double* h_mass, double* h_min, double* h_max, int64_t* h_nonfinite) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  if (!s->initialised) return fail(MSD_ESTATE, "diagnostics before msd_init");
+  msd::LaunchArgs a = base_args(s);
+  a.src = s->ws + s->L.half_off[s->cur];
+  a.pull = s->t > 0 ? 1 : 0;
+  a.partials = reinterpret_cast<double*>(s->ws + s->L.partials_off);
+  a.diag_out = reinterpret_cast<double*>(s->ws + s->L.diag_out_off);
+  a.diag_blocks = s->L.diag_blocks;
+  hipError_t e = dispatch(msd::Op::DiagPartial, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics kernel");
+  e = dispatch(msd::Op::DiagFinal, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics reduction kernel");
+  const int N = s->prob.n_species;
+  double host[3 * MSD_MAX_SPECIES + 1];
+  e = hipMemcpyAsync(host, a.diag_out, sizeof(double) * (3 * N + 1), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics synchronise");
+  for (int i = 0; i < N; ++i) {
+    if (h_mass) h_mass[i] = host[i];
+    if (h_min) h_min[i] = host[N + i];
+    if (h_max) h_max[i] = host[2 * N + i];
+  }
+  const int64_t bad = (int64_t)host[3 * N];
+  if (h_nonfinite) *h_nonfinite = bad;
+  if (bad) return fail(MSD_EDIVERGED, "%lld non-finite mole fractions", (long long)bad);
+  return MSD_OK;
+}
+
+size_t msd_state_bytes(const msd_sim* s) {
+  if (!s) return 0;
+  return (size_t)s->m * s->q * (size_t)s->L.plane * s->prob.precision;
+}
+
+int msd_save(const msd_sim* s, void* d_dst, int64_t* h_step) {
+  if (!s || !d_dst) return fail(MSD_EINVAL, "NULL argument");
+  if (!s->initialised) return fail(MSD_ESTATE, "save before msd_init");
+  const hipError_t e = hipMemcpyAsync(d_dst, s->ws + s->L.half_off[s->cur], msd_state_bytes(s),
+                                      hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "save copy");
+  if (h_step) *h_step = s->t;
+  return MSD_OK;
+}
+
+int msd_restore(msd_sim* s, const void* d_src, int64_t step) {
+  if (!s || !d_src) return fail(MSD_EINVAL, "NULL argument");
+  if (step < 0) return fail(MSD_EINVAL, "step < 0");
+  if (!s->initialised) {
+    // constants are produced by msd_init; a restore needs them as well
+    return fail(MSD_ESTATE, "restore before msd_init");
+  }
+  const hipError_t e = hipMemcpyAsync(s->ws + s->L.half_off[s->cur], d_src, msd_state_bytes(s),
+                                      hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "restore copy");
+  s->t = step;
+  return MSD_OK;
+}
+
+int msd_destroy(msd_sim* s) {
+  delete s;
+  return MSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+// Device building blocks of the Maxwell-Stefan MRT lattice Boltzmann sweep.
+//
+// Per node the sweep needs, for the m = N-1 evolved species:
+//   xi_i = sum_k f_k^i                                     (Eq. (3-15))
+//   B(xi)                                                  (Eq. (2-10))
+//   K = (I + (a/2) B)^-1,  a = cs2 dt                      (see below)
+//   Lambda_1 = 2 (I - K)                                   (Eq. (3-26) with D~ = B^-1)
+//   Lambda_2 = Lambda_1 with the diagonal of Eq. (3-16)
+//   relaxation of Eq. (3-13a) and the back-transform.
+//
+// Two algebraic rewrites make this cheap and exact up to rounding:
+// (1) Eq. (3-26) gives Lambda_1 = (D~/a + I/2)^-1 = a (I + (a/2) B)^-1 B
+//     = 2 (I - K): one small inverse per node instead of two.
+// (2) On D1Q3, D2Q5 and D3Q7 every moment row is either odd or even under
+//     k -> opposite(k), first-order rows are exactly the odd ones, and the
+//     conserved row has m - m^eq = 0.  The moment-space relaxation
+//     M^-1 Lambda M (f - f^eq) therefore equals
+//         Lambda_1 odd(f - f^eq) + Lambda_2 even(f - f^eq)
+//     with odd/even the antisymmetric/symmetric parts over opposite pairs,
+//     whatever moment matrix is used.  With Lambda_2 = Lambda_1 + diag(delta):
+//         f^+_k = w_k xi + (2K - I)(f_k - w_k xi) - delta * even_k.
+// The flux follows the same way: with grad xi = -(1/a) Lambda_1 m1
+// (Eq. (3-27)) and J = -c_t D~ grad xi (Eq. (2-12)), J = c_t K m1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msd {
+
+constexpr int kMaxSpecies = 8;
+constexpr int BC_PERIODIC = 0, BC_ZERO_FLUX = 1, BC_DIRICHLET = 2;
+
+// ---------------------------------------------------------------------------
+// Lattices (Sec. 3.1).  Direction k moves along axis(k) by sgn(k) (0 for rest).
+// ---------------------------------------------------------------------------
+template <int LAT> struct Lattice;
+
+// Eq. (3-5): c = (0, 1, -1), w = (2/3, 1/6, 1/6).
+template <> struct Lattice<1> {
+  static constexpr int D = 1, Q = 3;
+  __host__ __device__ static constexpr int axis(int k) { return k == 0 ? -1 : 0; }
+  __host__ __device__ static constexpr int sgn(int k) { return k == 0 ? 0 : (k == 1 ? 1 : -1); }
+  __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : 3 - k; }
+  __host__ __device__ static constexpr double w(int k) { return k == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+  static constexpr double cs2 = 1.0 / 3.0;
+};
+
+// Eq. (3-7): directions (0,0), (1,0), (0,1), (-1,0), (0,-1); w = (1/3, 1/6 x4).
+template <> struct Lattice<2> {
+  static constexpr int D = 2, Q = 5;
+  __host__ __device__ static constexpr int axis(int k) { return k == 0 ? -1 : ((k - 1) & 1); }
+  __host__ __device__ static constexpr int sgn(int k) { return k == 0 ? 0 : (k <= 2 ? 1 : -1); }
+  __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : (k <= 2 ? k + 2 : k - 2); }
+  __host__ __device__ static constexpr double w(int k) { return k == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
+  static constexpr double cs2 = 1.0 / 3.0;
+};
+
+// Eq. (3-10): directions 0, +x, -x, +y, -y, +z, -z; w = (1/4, 1/8 x6).
+// Its second moment is sum_k w_k c_kx^2 = 1/4, which replaces the D2Q5 factor
+// c^2/3 of Eqs. (3-22), (3-26) and (3-27).
+template <> struct Lattice<3> {
+  static constexpr int D = 3, Q = 7;
+  __host__ __device__ static constexpr int axis(int k) { return k == 0 ? -1 : (k - 1) / 2; }
+  __host__ __device__ static constexpr int sgn(int k) { return k == 0 ? 0 : ((k & 1) ? 1 : -1); }
+  __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : ((k & 1) ? k + 1 : k - 1); }
+  __host__ __device__ static constexpr double w(int k) { return k == 0 ? 0.25 : 0.125; }
+  static constexpr double cs2 = 0.25;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel parameters (passed by value in the kernel argument segment).
+// Host arrays of the problem are copied in verbatim; every derived quantity
+// (1/D_ij, relaxation matrices, ...) is computed on the device.
+// ---------------------------------------------------------------------------
+struct Problem {
+  int32_t nx, ny, nz;
+  int32_t relax;          // 0 paper rule (Eq. (3-16)), 1 SRT
+  int32_t linearized;     // 1: B at xi_ref
+  int32_t bc[6];          // x_lo, x_hi, y_lo, y_hi, z_lo, z_hi
+  int64_t plane;          // elements between consecutive planes of a buffer
+  double c_t;
+  double D[kMaxSpecies][kMaxSpecies];
+  double wall[6][kMaxSpecies];
+  double xi_ref[kMaxSpecies];
+};
+
+// ---------------------------------------------------------------------------
+// Small dense inverse of A = I + (a/2) B.  The eigenvalues of B are real and
+// positive for compositions on the simplex, so A is never singular; its
+// off-diagonal entries can exceed the diagonal, hence the pivoting for m >= 4.
+// ---------------------------------------------------------------------------
+template <int M, typename T>
+__device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M]) {
+  if constexpr (M == 1) {
+    K[0][0] = T(1) / A[0][0];
+  } else if constexpr (M == 2) {
+    const T inv = T(1) / (A[0][0] * A[1][1] - A[0][1] * A[1][0]);
+    K[0][0] = A[1][1] * inv;
+    K[0][1] = -A[0][1] * inv;
+    K[1][0] = -A[1][0] * inv;
+    K[1][1] = A[0][0] * inv;
+  } else if constexpr (M == 3) {
+    const T c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    const T c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const T c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const T inv = T(1) / (A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02);
+    K[0][0] = c00 * inv;
+    K[1][0] = c01 * inv;
+    K[2][0] = c02 * inv;
+    K[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * inv;
+    K[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * inv;
+    K[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * inv;
+    K[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * inv;
+    K[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * inv;
+    K[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * inv;
+  } else {
+    // Gauss-Jordan on [A | I] with partial pivoting; row swaps are done with
+    // selects so that every index stays compile-time (registers only).
+    T W[M][2 * M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        W[i][j] = A[i][j];
+        W[i][M + j] = (i == j) ? T(1) : T(0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+#pragma unroll
+      for (int r = c + 1; r < M; ++r) {
+        const bool sw = fabs(W[r][c]) > fabs(W[c][c]);
+#pragma unroll
+        for (int j = 0; j < 2 * M; ++j) {
+          const T a = W[c][j], b = W[r][j];
+          W[c][j] = sw ? b : a;
+          W[r][j] = sw ? a : b;
+        }
+      }
+      const T inv = T(1) / W[c][c];
+#pragma unroll
+      for (int j = 0; j < 2 * M; ++j) W[c][j] *= inv;
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        if (r == c) continue;
+        const T fac = W[r][c];
+#pragma unroll
+        for (int j = 0; j < 2 * M; ++j) W[r][j] -= fac * W[c][j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j < M; ++j) K[i][j] = W[i][M + j];
+  }
+}
+
+// K = (I + (a/2) B(xb))^-1 with B of Eq. (2-10) at composition xb (m values;
+// the eliminated species is 1 - sum).  With xi_N = 1 - sum_{k<N} xi_k,
+//   B_ii = R_iN + sum_{k != i, k < N} xi_k (R_ik - R_iN),  B_ij = -xi_i (R_ij - R_iN)
+// where R = 1/D (sigma_ij of Eq. (2-6)).
+template <int M, typename T>
+__device__ __forceinline__ void ms_inverse(const T (&xb)[M], const T (&R)[M][M + 1], T half_a,
+                                           T (&K)[M][M]) {
+  T A[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T diag = R[i][M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      if (k == i) continue;
+      const T s = R[i][k] - R[i][M];
+      diag += xb[k] * s;
+      A[i][k] = -half_a * xb[i] * s;
+    }
+    A[i][i] = T(1) + half_a * diag;
+  }
+  invert_small<M, T>(A, K);
+}
+
+// Collision of one node in place: f[i][k] <- f^+ (Eq. (3-13a) + back-transform).
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T (&R)[M][M + 1],
+                                             const T (&xref)[M], bool linearized, bool srt) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  T xi[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = f[i][0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) s += f[i][k];
+    xi[i] = s;
+  }
+  T xb[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) xb[i] = linearized ? xref[i] : xi[i];
+  T K[M][M];
+  ms_inverse<M, T>(xb, R, T(0.5 * L::cs2), K);
+
+  // G = 2K - I; delta_i = lambda_2^ii - lambda_1^ii with lambda_1^ii = 2 (1 - K_ii).
+  T G[M][M], delta[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) G[i][j] = T(2) * K[i][j] - (i == j ? T(1) : T(0));
+    const T l1 = T(2) - T(2) * K[i][i];
+    delta[i] = srt ? T(0) : (T(8) * (l1 - T(2)) / (l1 - T(8)) - l1);
+  }
+
+  T neq[M][Q];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) neq[i][k] = f[i][k] - T(L::w(k)) * xi[i];
+
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int kb = L::opp(k);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T acc = T(L::w(k)) * xi[i];
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc += G[i][j] * neq[j][k];
+      const T even = (k == kb) ? neq[i][k] : T(0.5) * (neq[i][k] + neq[i][kb]);
+      f[i][k] = acc - delta[i] * even;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node addressing and pull propagation with the face rules of Sec. 4.
+// ---------------------------------------------------------------------------
+struct NodePos {
+  int32_t c[3];     // coordinates
+  int64_t idx;      // linear index (x fastest)
+};
+
+template <int LAT>
+__device__ __forceinline__ int64_t axis_stride(const Problem& p, int a) {
+  return a == 0 ? int64_t(1) : (a == 1 ? int64_t(p.nx) : int64_t(p.nx) * p.ny);
+}
+
+__device__ __forceinline__ int32_t extent(const Problem& p, int a) {
+  return a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
+}
+
+// f_k^i(x, t) for all i of one direction k: the post-collision value of the
+// source node x - c_k, or at a wall face
+//   zero flux:  f_kbar^+(x)            (half-way bounce-back)
+//   Dirichlet: -f_kbar^+(x) + 2 w_kbar xi_b   (half-way anti-bounce-back)
+// `src` is the post-collision buffer; plane(i, k) is at src + (i*Q + k)*plane.
+template <int LAT, int M, typename T, typename Ptr>
+__device__ __forceinline__ void pull_direction(const Problem& p, Ptr src, const NodePos& n, int k,
+                                               T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M]) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const int a = L::axis(k);
+  if (a < 0) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+    return;
+  }
+  const int s = L::sgn(k);
+  const int32_t ext = extent(p, a);
+  const int64_t st = axis_stride<LAT>(p, a);
+  const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
+  const int face = 2 * a + (s > 0 ? 0 : 1);
+  const int kind = edge ? p.bc[face] : BC_PERIODIC;
+  if (kind == BC_PERIODIC) {
+    const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+  } else {
+    const int kb = L::opp(k);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T back = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
+      out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+    }
+  }
+}
+
+template <int LAT, int M, typename T, typename Ptr>
+__device__ __forceinline__ void gather_node(const Problem& p, Ptr src, const NodePos& n, bool pull,
+                                            T (&f)[M][Lattice<LAT>::Q], const T (&wall)[6][M]) {
+  constexpr int Q = Lattice<LAT>::Q;
+  if (!pull) {
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) f[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) pull_direction<LAT, M, T>(p, src, n, k, f, wall);
+}
+
+}  // namespace msd

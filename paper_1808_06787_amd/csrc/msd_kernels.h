@@ -1,0 +1,440 @@
+// Kernels of the sweep, templated on lattice, number of evolved species and
+// precision, plus the per-lattice dispatch.  Included by one translation unit
+// per lattice.
+//
+// Storage: every distribution buffer holds m*q planes of `plane` values
+// (plane >= nodes, padded), plane (i, k) at offset (i*q + k)*plane.  A buffer
+// holds post-collision values f^+(x, t-1) at the node that produced them
+// (pull layout); only right after msd_init does it hold the pre-collision
+// f(x, 0), which the first sweep reads without propagation (pull = 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "msd_launch.h"
+
+namespace msd {
+
+// ---------------------------------------------------------------------------
+// Tiling: a 1D grid of tiles of block_x * block_y nodes in one z-plane.  With
+// XCD remapping, the hardware's round-robin of workgroups over the 8 XCDs is
+// undone so that each XCD walks a contiguous range of tiles (neighbouring
+// rows, whose lines the +-y pulls re-read, then sit in the same L2).
+// ---------------------------------------------------------------------------
+struct Tiling {
+  uint32_t tiles_x, tiles_y, tiles;
+  uint32_t remap;
+};
+
+__device__ __forceinline__ uint32_t logical_tile(const Tiling& t) {
+  const uint32_t L = blockIdx.x;
+  if (!t.remap) return L;
+  const uint32_t q = t.tiles >> 3, r = t.tiles & 7u, x = L & 7u;
+  return x * q + (x < r ? x : r) + (L >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_value(T* p, T v, int nontemporal) {
+  if (nontemporal)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <int M, typename T>
+struct NodeConsts {
+  T R[M][M + 1];
+  T wall[6][M];
+  T xref[M];
+};
+
+template <int M, typename T>
+__device__ __forceinline__ void load_consts(const Consts<T>* __restrict__ c, NodeConsts<M, T>& nc) {
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= M; ++j) nc.R[i][j] = c->R[i][j];
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+#pragma unroll
+    for (int i = 0; i < M; ++i) nc.wall[f][i] = c->wall[f][i];
+#pragma unroll
+  for (int i = 0; i < M; ++i) nc.xref[i] = c->xref[i];
+}
+
+// ---------------------------------------------------------------------------
+// Setup: reciprocal diffusivities and face data in the sweep's precision.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_constants(Problem p, int n_species, Consts<T>* out) {
+  const int t = threadIdx.x;
+  if (t < kMaxSpecies * kMaxSpecies) {
+    const int i = t / kMaxSpecies, j = t % kMaxSpecies;
+    out->R[i][j] = (i != j && i < n_species && j < n_species) ? T(1.0 / p.D[i][j]) : T(0);
+  }
+  if (t < 6 * kMaxSpecies) out->wall[t / kMaxSpecies][t % kMaxSpecies] = T(p.wall[t / kMaxSpecies][t % kMaxSpecies]);
+  if (t < kMaxSpecies) out->xref[t] = T(p.xi_ref[t]);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation f_k^i(x, 0) = w_k xi_i(x, 0) (Sec. 4, Eq. (3-3)).
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T, typename TI>
+__global__ __launch_bounds__(256) void k_init(Problem p, const TI* __restrict__ xi0, T* __restrict__ dst) {
+  using L = Lattice<LAT>;
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nodes) return;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const T xi = T(xi0[(int64_t)i * nodes + idx]);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) dst[(int64_t)(i * L::Q + k) * p.plane + idx] = T(L::w(k)) * xi;
+  }
+}
+
+__device__ __forceinline__ bool tile_node(const Problem& p, const Tiling& tl, NodePos& n) {
+  const uint32_t tile = logical_tile(tl);
+  const uint32_t tx = tile % tl.tiles_x;
+  const uint32_t rest = tile / tl.tiles_x;
+  const uint32_t ty = rest % tl.tiles_y;
+  const uint32_t tz = rest / tl.tiles_y;
+  n.c[0] = (int32_t)(tx * blockDim.x + threadIdx.x);
+  n.c[1] = (int32_t)(ty * blockDim.y + threadIdx.y);
+  n.c[2] = (int32_t)tz;
+  if (n.c[0] >= p.nx || n.c[1] >= p.ny) return false;
+  n.idx = n.c[0] + (int64_t)p.nx * (n.c[1] + (int64_t)p.ny * n.c[2]);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// One fused time step: pull-propagate (with face rules), collide, store.
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T>
+__global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ src, T* __restrict__ dst,
+                                               const Consts<T>* __restrict__ cst, int pull, Tiling tl,
+                                               int nontemporal) {
+  constexpr int Q = Lattice<LAT>::Q;
+  NodePos n;
+  if (!tile_node(p, tl, n)) return;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  T f[M][Q];
+  gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall);
+  collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) store_value(dst + (int64_t)(i * Q + k) * p.plane + n.idx, f[i][k], nontemporal);
+}
+
+// ---------------------------------------------------------------------------
+// Small domains: one workgroup keeps both ping-pong copies in LDS and runs all
+// requested steps in one launch (launch latency would otherwise dominate).
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T>
+__global__ __launch_bounds__(256) void k_step_lds(Problem p, const T* __restrict__ src, T* __restrict__ dst,
+                                                   const Consts<T>* __restrict__ cst, int first_pull,
+                                                   int64_t nsteps) {
+  constexpr int Q = Lattice<LAT>::Q;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  T* A = reinterpret_cast<T*>(smem_raw);
+  T* B = A + (int64_t)M * Q * nodes;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  for (int64_t e = threadIdx.x; e < (int64_t)M * Q * nodes; e += blockDim.x) {
+    const int64_t pl = e / nodes, j = e % nodes;
+    A[e] = src[pl * p.plane + j];
+  }
+  __syncthreads();
+  Problem lp = p;
+  lp.plane = nodes;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const bool pull = (s > 0) || (first_pull != 0);
+    for (int64_t j = threadIdx.x; j < nodes; j += blockDim.x) {
+      NodePos n;
+      n.idx = j;
+      n.c[0] = (int32_t)(j % p.nx);
+      const int64_t r = j / p.nx;
+      n.c[1] = (int32_t)(r % p.ny);
+      n.c[2] = (int32_t)(r / p.ny);
+      T f[M][Q];
+      gather_node<LAT, M, T>(lp, (const T*)A, n, pull, f, nc.wall);
+      collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) B[(int64_t)(i * Q + k) * nodes + j] = f[i][k];
+    }
+    __syncthreads();
+    T* t = A;
+    A = B;
+    B = t;
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)M * Q * nodes; e += blockDim.x) {
+    const int64_t pl = e / nodes, j = e % nodes;
+    dst[pl * p.plane + j] = A[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Observables at the current time (Eqs. (3-15), (2-3b), (3-27), (2-12)):
+// xi (N planes), J = c_t K m1 and grad xi = -(2/a)(I - K) m1 (m*d planes each).
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T, typename TO>
+__global__ __launch_bounds__(256) void k_read(Problem p, const T* __restrict__ src,
+                                               const Consts<T>* __restrict__ cst, int pull, Tiling tl,
+                                               TO* __restrict__ oxi, TO* __restrict__ oJ, TO* __restrict__ og) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q, DD = L::D;
+  NodePos n;
+  if (!tile_node(p, tl, n)) return;
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  T f[M][Q];
+  gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall);
+  T xi[M], m1[M][DD];
+  T tot = T(0);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = f[i][0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) s += f[i][k];
+    xi[i] = s;
+    tot += s;
+#pragma unroll
+    for (int d = 0; d < DD; ++d) m1[i][d] = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) m1[i][L::axis(k)] += (L::sgn(k) > 0) ? f[i][k] : -f[i][k];
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) oxi[(int64_t)i * nodes + n.idx] = TO(xi[i]);
+  oxi[(int64_t)M * nodes + n.idx] = TO(T(1) - tot);
+  if (!oJ && !og) return;
+  T xb[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) xb[i] = p.linearized ? nc.xref[i] : xi[i];
+  T K[M][M];
+  ms_inverse<M, T>(xb, nc.R, T(0.5 * L::cs2), K);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int d = 0; d < DD; ++d) {
+      T km = T(0);
+#pragma unroll
+      for (int j = 0; j < M; ++j) km += K[i][j] * m1[j][d];
+      const int64_t o = (int64_t)(i * DD + d) * nodes + n.idx;
+      if (oJ) oJ[o] = TO(T(p.c_t) * km);
+      if (og) og[o] = TO(-(T(2) / T(L::cs2)) * (m1[i][d] - km));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: per-workgroup partial sums (FP64), minima, maxima and non-finite
+// counts over all N species, then a single-workgroup pass in fixed order.
+// Partial layout per workgroup: [N sums][N minima][N maxima][1 count].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+constexpr int kDiagThreads = 256;
+
+template <int LAT, int M, typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Problem p, const T* __restrict__ src,
+                                                              const Consts<T>* __restrict__ cst, int pull,
+                                                              double* __restrict__ partials) {
+  constexpr int Q = Lattice<LAT>::Q, N = M + 1, W = 3 * N + 1;
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  double sum[N], mn[N], mx[N], bad = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    sum[i] = 0.0;
+    mn[i] = __builtin_huge_val();
+    mx[i] = -__builtin_huge_val();
+  }
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nodes; j += (int64_t)gridDim.x * blockDim.x) {
+    NodePos n;
+    n.idx = j;
+    n.c[0] = (int32_t)(j % p.nx);
+    const int64_t r = j / p.nx;
+    n.c[1] = (int32_t)(r % p.ny);
+    n.c[2] = (int32_t)(r / p.ny);
+    T f[M][Q];
+    gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall);
+    double tot = 0.0;
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+      double x;
+      if (i < M) {
+        T s = f[i][0];
+#pragma unroll
+        for (int k = 1; k < Q; ++k) s += f[i][k];
+        x = (double)s;
+        tot += x;
+      } else {
+        x = 1.0 - tot;
+      }
+      if (__builtin_isfinite(x)) {
+        sum[i] += x;
+        mn[i] = fmin(mn[i], x);
+        mx[i] = fmax(mx[i], x);
+      } else {
+        bad += 1.0;
+      }
+    }
+  }
+  __shared__ double red[kDiagThreads / 64][3 * kMaxSpecies + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double a = wave_sum(sum[i]), b = wave_min(mn[i]), c = wave_max(mx[i]);
+    if (lane == 0) {
+      red[wv][i] = a;
+      red[wv][N + i] = b;
+      red[wv][2 * N + i] = c;
+    }
+  }
+  const double bb = wave_sum(bad);
+  if (lane == 0) red[wv][3 * N] = bb;
+  __syncthreads();
+  if (threadIdx.x < W) {
+    const int e = threadIdx.x;
+    double v = red[0][e];
+    for (int w = 1; w < kDiagThreads / 64; ++w) {
+      const double u = red[w][e];
+      if (e < N || e == 3 * N)
+        v += u;
+      else if (e < 2 * N)
+        v = fmin(v, u);
+      else
+        v = fmax(v, u);
+    }
+    partials[(int64_t)blockIdx.x * W + e] = v;
+  }
+}
+
+// Templated on the lattice only so that each per-lattice unit owns its copy.
+template <int LAT>
+__global__ void k_diag_final(const double* __restrict__ partials, int blocks, int N, double* __restrict__ out) {
+  const int W = 3 * N + 1;
+  const int e = threadIdx.x;
+  if (e >= W) return;
+  double v = partials[e];
+  for (int b = 1; b < blocks; ++b) {
+    const double u = partials[(int64_t)b * W + e];
+    if (e < N || e == 3 * N)
+      v += u;
+    else if (e < 2 * N)
+      v = fmin(v, u);
+    else
+      v = fmax(v, u);
+  }
+  out[e] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+inline Tiling make_tiling(const LaunchArgs& a) {
+  Tiling t;
+  t.tiles_x = (uint32_t)((a.p.nx + a.block_x - 1) / a.block_x);
+  t.tiles_y = (uint32_t)((a.p.ny + a.block_y - 1) / a.block_y);
+  t.tiles = t.tiles_x * t.tiles_y * (uint32_t)a.p.nz;
+  t.remap = a.xcd_remap ? 1u : 0u;
+  return t;
+}
+
+template <int LAT, int M, typename T>
+hipError_t run(Op op, const LaunchArgs& a) {
+  const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
+  const int64_t nodes = (int64_t)a.p.nx * a.p.ny * a.p.nz;
+  switch (op) {
+    case Op::Constants:
+      hipLaunchKernelGGL(k_constants<T>, dim3(1), dim3(64), 0, a.stream, a.p, a.n_species,
+                         static_cast<Consts<T>*>(a.consts_out));
+      break;
+    case Op::Init: {
+      const dim3 grid((unsigned)((nodes + 255) / 256));
+      if (a.in_prec == 8)
+        hipLaunchKernelGGL((k_init<LAT, M, T, double>), grid, dim3(256), 0, a.stream, a.p,
+                           static_cast<const double*>(a.xi0), static_cast<T*>(a.dst));
+      else
+        hipLaunchKernelGGL((k_init<LAT, M, T, float>), grid, dim3(256), 0, a.stream, a.p,
+                           static_cast<const float*>(a.xi0), static_cast<T*>(a.dst));
+      break;
+    }
+    case Op::Step: {
+      const Tiling tl = make_tiling(a);
+      hipLaunchKernelGGL((k_step<LAT, M, T>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream, a.p,
+                         static_cast<const T*>(a.src), static_cast<T*>(a.dst), cst, a.pull, tl, a.nontemporal);
+      break;
+    }
+    case Op::StepLds: {
+      const int threads = (int)(nodes < 256 ? ((nodes + 63) / 64) * 64 : 256);
+      const size_t shmem = 2 * sizeof(T) * (size_t)M * Lattice<LAT>::Q * (size_t)nodes;
+      hipLaunchKernelGGL((k_step_lds<LAT, M, T>), dim3(1), dim3(threads), shmem, a.stream, a.p,
+                         static_cast<const T*>(a.src), static_cast<T*>(a.dst), cst, a.pull, a.nsteps);
+      break;
+    }
+    case Op::Read: {
+      const Tiling tl = make_tiling(a);
+      if (a.out_prec == 8)
+        hipLaunchKernelGGL((k_read<LAT, M, T, double>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream,
+                           a.p, static_cast<const T*>(a.src), cst, a.pull, tl, static_cast<double*>(a.out_xi),
+                           static_cast<double*>(a.out_J), static_cast<double*>(a.out_grad));
+      else
+        hipLaunchKernelGGL((k_read<LAT, M, T, float>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream,
+                           a.p, static_cast<const T*>(a.src), cst, a.pull, tl, static_cast<float*>(a.out_xi),
+                           static_cast<float*>(a.out_J), static_cast<float*>(a.out_grad));
+      break;
+    }
+    case Op::DiagPartial:
+      hipLaunchKernelGGL((k_diag_partial<LAT, M, T>), dim3(a.diag_blocks), dim3(kDiagThreads), 0, a.stream, a.p,
+                         static_cast<const T*>(a.src), cst, a.pull, a.partials);
+      break;
+    case Op::DiagFinal:
+      hipLaunchKernelGGL(k_diag_final<LAT>, dim3(1), dim3(64), 0, a.stream, a.partials, a.diag_blocks, M + 1,
+                         a.diag_out);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int LAT, int M>
+hipError_t run_prec(Op op, const LaunchArgs& a) {
+  return a.prec == 8 ? run<LAT, M, double>(op, a) : run<LAT, M, float>(op, a);
+}
+
+template <int LAT>
+hipError_t dispatch(Op op, const LaunchArgs& a) {
+  switch (a.m) {
+    case 1: return run_prec<LAT, 1>(op, a);
+    case 2: return run_prec<LAT, 2>(op, a);
+    case 3: return run_prec<LAT, 3>(op, a);
+    case 4: return run_prec<LAT, 4>(op, a);
+    case 5: return run_prec<LAT, 5>(op, a);
+    case 6: return run_prec<LAT, 6>(op, a);
+    case 7: return run_prec<LAT, 7>(op, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace msd

@@ -1,0 +1,68 @@
+// Host-side launch interface between the C ABI layer and the per-lattice
+// kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "msd_device.h"
+
+namespace msd {
+
+enum class Op { Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal };
+
+// Constants block written once per problem by the setup kernel and read by
+// every sweep kernel through uniform (scalar-cache) loads: R = 1/D (m rows of
+// N entries), Dirichlet face values and the linearisation composition, in the
+// sweep's precision.
+template <typename T>
+struct Consts {
+  T R[kMaxSpecies][kMaxSpecies];
+  T wall[6][kMaxSpecies];
+  T xref[kMaxSpecies];
+};
+constexpr size_t kConstsBytes = 1024;   // >= sizeof(Consts<double>) = 960
+static_assert(sizeof(Consts<double>) <= kConstsBytes, "constants block too small");
+
+struct LaunchArgs {
+  Problem p;
+  int lattice = 0, m = 0, prec = 4;
+  hipStream_t stream = nullptr;
+  // sweep
+  const void* src = nullptr;
+  void* dst = nullptr;
+  const void* consts = nullptr;
+  void* consts_out = nullptr;
+  int pull = 1;
+  int block_x = 256, block_y = 1;
+  int xcd_remap = 1;
+  int nontemporal = 0;
+  int64_t nsteps = 1;        // StepLds: steps done inside one launch
+  // init
+  const void* xi0 = nullptr;
+  int in_prec = 8;
+  // read-out
+  void* out_xi = nullptr;
+  void* out_J = nullptr;
+  void* out_grad = nullptr;
+  int out_prec = 8;
+  // diagnostics
+  double* partials = nullptr;
+  double* diag_out = nullptr;
+  int diag_blocks = 0;
+  int n_species = 0;
+};
+
+// Largest domain (nodes) the single-workgroup LDS-resident sweep accepts for a
+// given m, q and value size: two copies of m*q values per node in <= 64 KiB.
+inline int64_t lds_resident_max_nodes(int m, int q, int bytes) {
+  return (64 * 1024) / (2 * (int64_t)m * q * bytes);
+}
+
+template <int LAT>
+hipError_t dispatch(Op op, const LaunchArgs& a);
+
+extern template hipError_t dispatch<1>(Op, const LaunchArgs&);
+extern template hipError_t dispatch<2>(Op, const LaunchArgs&);
+extern template hipError_t dispatch<3>(Op, const LaunchArgs&);
+
+}  // namespace msd

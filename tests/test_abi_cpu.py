@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point that include/msd.h declares, its structures have the layout
+the binding assumes, and argument validation returns the documented codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1808_06787_amd import _ffi as F
+from paper_1808_06787_amd.sim import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        names.update(re.findall(r"^MSD_API\s+[\w\s\*]+?\b(msd_\w+)\s*\(", text, flags=re.M))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert len(names) >= 17
+    lib = C.CDLL(F.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol():
+    F.lib()
+    for n in _declared_symbols():
+        assert getattr(F.lib(), n).restype is not None or n == "msd_destroy", n
+
+
+def test_struct_layouts():
+    assert C.sizeof(F.MsdProblem) == 112
+    assert F.MsdProblem.c_t.offset == 64
+    assert F.MsdProblem.bc.offset == 80
+    assert C.sizeof(F.MsdLaunch) == 32
+    assert F.lib().msd_abi_version() == F.ABI_VERSION
+
+
+def _ws(p):
+    st = C.c_int32(123)
+    n = F.lib().msd_workspace_bytes(C.byref(p), C.byref(st))
+    return n, st.value
+
+
+def test_workspace_size_model():
+    D = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.3, 1.0]])
+    p, keep = make_problem("D2Q5", D, (100, 37), "f32")
+    n, st = _ws(p)
+    assert st == 0
+    plane = (100 * 37 + 63) // 64 * 64 + 64
+    # two halves of m*q planes plus < 1 MiB of constants and reduction scratch
+    assert 2 * 2 * 5 * plane * 4 <= n < 2 * 2 * 5 * plane * 4 + (1 << 20)
+
+
+@pytest.mark.parametrize(
+    "mutate,code",
+    [
+        (lambda p: setattr(p, "abi", 99), -8),
+        (lambda p: setattr(p, "lattice", 7), -1),
+        (lambda p: setattr(p, "n_species", 1), -1),
+        (lambda p: setattr(p, "n_species", 9), -1),
+        (lambda p: setattr(p, "precision", 2), -1),
+        (lambda p: setattr(p, "nz", 2), -1),
+        (lambda p: setattr(p, "nx", 0), -1),
+        (lambda p: setattr(p, "c_t", -1.0), -1),
+        (lambda p: setattr(p, "relax", 5), -4),
+        (lambda p: p.bc.__setitem__(0, 1), -1),      # periodic paired with zero flux
+        (lambda p: p.bc.__setitem__(4, 1), -1),      # z faces on a 2D lattice
+        (lambda p: p.bc.__setitem__(0, 9), -1),
+    ],
+)
+def test_validation_codes(mutate, code):
+    D = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.3, 1.0]])
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32")
+    mutate(p)
+    n, st = _ws(p)
+    assert n == 0 and st == code
+    assert F.lib().msd_last_error()
+
+
+def test_diffusivity_and_composition_validation():
+    bad = np.array([[1, 0.1, 0.2], [0.1, 1, -0.3], [0.2, -0.3, 1.0]])
+    p, keep = make_problem("D2Q5", bad, (16, 8), "f32")
+    assert _ws(p) == (0, -2)
+    asym = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.31, 1.0]])
+    p, keep = make_problem("D2Q5", asym, (16, 8), "f32")
+    assert _ws(p) == (0, -2)
+    D = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.3, 1.0]])
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32", xi_ref=[0.2, 0.2, 0.2])
+    assert _ws(p) == (0, -3)
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32", bc=(("dirichlet", "dirichlet"), ("periodic", "periodic")),
+                           xi_wall={(0, 0): [0.5, 0.5, 0.0], (0, 1): [0.5, 0.6, 0.0]})
+    assert _ws(p) == (0, -3)
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32", bc=(("dirichlet", "dirichlet"), ("periodic", "periodic")))
+    assert _ws(p) == (0, -1)
+
+
+def test_create_rejects_small_or_misaligned_workspace_without_touching_it():
+    D = np.array([[1, 0.1], [0.1, 1.0]])
+    p, keep = make_problem("D1Q3", D, (64,), "f64")
+    n, st = _ws(p)
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 40)       # never dereferenced: validation fails first
+    assert F.lib().msd_create(C.byref(p), fake, C.c_size_t(n - 1), None, C.byref(h)) == -7
+    assert F.lib().msd_create(C.byref(p), C.c_void_p((1 << 40) + 8), C.c_size_t(n), None, C.byref(h)) == -1
+    assert not h.value
+    assert F.lib().msd_step(None, 1) == -1
+    assert F.lib().msd_strerror(-7) == b"workspace too small"

@@ -1,0 +1,166 @@
+"""Parity of the HIP sweep (through the C ABI) with the FP64 oracle.
+
+Grids are ragged (no extent a multiple of the tile) and span several tiles;
+every lattice, N from 2 to 8, both precisions, every face kind, both
+relaxation rules and the linearised mode are covered.  Tolerances: FP64 1e-12
+relative on mole fractions; FP32 1e-5 absolute (see gpu_cases.PREC_TOL).
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import (assert_parity, gpu_run, oracle_problem, oracle_run, rand_D, rand_field,
+                       smooth_field)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"D1Q3": (301,), "D2Q5": (97, 45), "D3Q7": (37, 19, 11)}
+WALLS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3}
+
+
+def _bc(lattice, kinds):
+    d = WALLS[lattice]
+    return tuple(kinds[a % len(kinds)] for a in range(d))
+
+
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_periodic_and_zero_flux(lattice, N, precision):
+    rng = np.random.default_rng(1000 + 10 * N + len(lattice))
+    D = rand_D(rng, N)
+    shape = SHAPES[lattice]
+    bc = _bc(lattice, [("zero_flux", "zero_flux"), ("periodic", "periodic")])
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 60
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc), xi0, steps)
+    gpu = gpu_run(lattice, D, shape, precision, xi0, steps, bc=bc)
+    err = assert_parity(gpu, orc, precision, f"{lattice} N={N} {precision}")
+    print(f"{lattice} N={N} {precision}: max |dxi| = {err:.3e}")
+
+
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("relax", ["paper", "srt"])
+def test_dirichlet_faces(lattice, precision, relax):
+    rng = np.random.default_rng(77)
+    N = 3
+    D = rand_D(rng, N)
+    shape = SHAPES[lattice]
+    bc = _bc(lattice, [("dirichlet", "zero_flux"), ("periodic", "periodic"), ("dirichlet", "dirichlet")])
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = rand_field(rng, N, shape[::-1])
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax), xi0, 40)
+    gpu = gpu_run(lattice, D, shape, precision, xi0, 40, bc=bc, xi_wall=walls, relax=relax)
+    assert_parity(gpu, orc, precision, f"{lattice} dirichlet {precision} {relax}")
+
+
+@pytest.mark.parametrize("N", [6, 7, 8])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_many_species(N, precision):
+    rng = np.random.default_rng(500 + N)
+    D = rand_D(rng, N, 0.05, 0.3)
+    shape = (70, 33)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.05)
+    orc = oracle_run(oracle_problem("D2Q5", D, shape), xi0, 30)
+    gpu = gpu_run("D2Q5", D, shape, precision, xi0, 30)
+    assert_parity(gpu, orc, precision, f"N={N} {precision}")
+
+
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("relax", ["paper", "srt"])
+def test_linearised_mode(lattice, relax):
+    rng = np.random.default_rng(31)
+    N = 4
+    D = rand_D(rng, N)
+    shape = SHAPES[lattice]
+    xref = np.array([0.1, 0.2, 0.3, 0.4])
+    xi0 = smooth_field(rng, N, shape[::-1], 0.05)
+    orc = oracle_run(oracle_problem(lattice, D, shape, relax=relax, xi_ref=xref), xi0, 50)
+    gpu = gpu_run(lattice, D, shape, "f64", xi0, 50, relax=relax, xi_ref=xref)
+    assert_parity(gpu, orc, "f64", f"{lattice} linearised {relax}")
+
+
+def test_c_t_scales_flux_only():
+    rng = np.random.default_rng(3)
+    D = rand_D(rng, 3)
+    xi0 = smooth_field(rng, 3, (40, 64), 0.1)
+    a = gpu_run("D2Q5", D, (64, 40), "f64", xi0, 20)
+    b = gpu_run("D2Q5", D, (64, 40), "f64", xi0, 20, c_t=2.5)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_allclose(b[1], 2.5 * a[1], rtol=1e-14, atol=1e-18)
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_launch_configurations_are_bitwise_identical():
+    """Tiling, XCD remapping and store hints change scheduling only."""
+    rng = np.random.default_rng(4)
+    D = rand_D(rng, 4)
+    shape = (203, 67)
+    xi0 = smooth_field(rng, 4, shape[::-1], 0.1)
+    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=dict(block_x=256, block_y=1, xcd_remap=0))
+    for launch in (dict(block_x=64, block_y=4), dict(block_x=128, block_y=2, nontemporal=1),
+                   dict(block_x=192, block_y=1, xcd_remap=1), dict(block_x=64, block_y=1, xcd_remap=1)):
+        got = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=launch)
+        for a, b in zip(ref, got):
+            np.testing.assert_array_equal(a, b, err_msg=str(launch))
+
+
+def test_split_step_calls_equal_one_call():
+    rng = np.random.default_rng(5)
+    D = rand_D(rng, 3)
+    shape = (50, 31, 9)
+    xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
+    a = gpu_run("D3Q7", D, shape, "f64", xi0, 30)
+    b = gpu_run("D3Q7", D, shape, "f64", xi0, 30, split=[1, 0, 7, 22])
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_lds_resident_path_matches_global_path(precision):
+    rng = np.random.default_rng(6)
+    D = rand_D(rng, 3)
+    xi0 = smooth_field(rng, 3, (256,), 0.2)
+    lds = gpu_run("D1Q3", D, (256,), precision, xi0, 500, launch=dict(lds_resident=1))
+    glob = gpu_run("D1Q3", D, (256,), precision, xi0, 500, launch=dict(lds_resident=0))
+    orc = oracle_run(oracle_problem("D1Q3", D, (256,)), xi0, 500)
+    assert_parity(lds, orc, precision, "lds")
+    assert_parity(glob, orc, precision, "global")
+    tol = 1e-13 if precision == "f64" else 1e-6
+    np.testing.assert_allclose(lds[0], glob[0], rtol=0, atol=tol)
+
+
+def test_ternary_1d_workload_full_length():
+    """The 1D ternary step workload (D1Q3, 256 nodes, FP64, 10,000 steps) in full."""
+    import workloads
+
+    w = workloads.ternary_1d()
+    orc = oracle_run(oracle_problem(w.lattice, w.D, w.shape, bc=w.bc), w.xi0, w.steps)
+    gpu = gpu_run(w.lattice, w.D, w.shape, w.precision, w.xi0, w.steps, bc=w.bc)
+    assert_parity(gpu, orc, "f64", w.name)
+
+
+@pytest.mark.parametrize("shape", [(1,), (2,), (1, 1), (1, 5), (3, 1, 2)])
+def test_degenerate_extents(shape):
+    lattice = {1: "D1Q3", 2: "D2Q5", 3: "D3Q7"}[len(shape)]
+    rng = np.random.default_rng(8)
+    D = rand_D(rng, 3)
+    xi0 = rand_field(rng, 3, shape[::-1])
+    orc = oracle_run(oracle_problem(lattice, D, shape), xi0, 9)
+    for launch in (dict(lds_resident=1), dict(lds_resident=0)):
+        gpu = gpu_run(lattice, D, shape, "f64", xi0, 9, launch=launch)
+        assert_parity(gpu, orc, "f64", f"{shape} {launch}")
+
+
+def test_zero_steps_reads_initial_state():
+    rng = np.random.default_rng(9)
+    D = rand_D(rng, 4)
+    xi0 = rand_field(rng, 4, (13, 17))
+    orc = oracle_run(oracle_problem("D2Q5", D, (17, 13)), xi0, 0)
+    gpu = gpu_run("D2Q5", D, (17, 13), "f64", xi0, 0)
+    assert_parity(gpu, orc, "f64", "t=0")
+    np.testing.assert_allclose(gpu[0], xi0, rtol=0, atol=1e-15)
