@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Everything is FP64 numpy, vectorised over nodes, following the paper's order
 of operations with no fusion: moments -> B -> D~ = B^-1 -> Lambda_1 (Eq. (3-26))
--> Lambda_2 (Eq. (3-16)) -> moment-space relaxation (Eq. (3-13a)) ->
-back-transform -> propagation with the boundary rules of Sec. 4 (Eq. (3-13b)).
+-> Lambda_2 (Eq. (3-16)) -> moment-space relaxation of the non-equilibrium part
+and back-transform (Eq. (3-2)) -> propagation with the boundary rules of Sec. 4
+(Eq. (3-13b)).
 
 Array conventions
 -----------------
@@ -148,12 +149,16 @@ def relaxation_matrices(prob: Problem, xi: np.ndarray):
 # ----------------------------------------------------------------------------
 
 def collide(prob: Problem, f: np.ndarray) -> np.ndarray:
-    """Post-collision distributions f^+ = M0^-1 m^+ (Eq. (3-13); Eq. (3-1a) form with M0).
+    """Post-collision distributions in the form of the evolution equation (3-2)/(3-1a):
 
-    m^i = M0 f^i, m^{i,eq} = M0 f^{i,eq} with f^{i,eq}_k = w_k xi_i (Eqs. (3-3), (3-11)),
-    m^{i,+} = m^i - sum_j Lambda^{ij} (m^j - m^{j,eq}) with the diagonal relaxation
-    Lambda^{ij} = diag(lambda_0^ij, lambda_1^ij, ..., lambda_2^ij, ...) of Eq. (3-14b):
-    every first-order row uses Lambda_1 and every second-order row Lambda_2.
+        f^{i,+} = f^i - sum_j M0^-1 Lambda^{ij} M0 (f^j - f^{j,eq}),   f^{j,eq}_k = w_k xi_j (Eq. (3-3))
+
+    with the diagonal relaxation Lambda^{ij} = diag(lambda_0^ij, lambda_1^ij, ..., lambda_2^ij, ...)
+    of Eq. (3-14b): every first-order row of M0 uses Lambda_1, every second-order row
+    Lambda_2.  The zeroth (conserved) moment of f - f^eq is zero exactly, since
+    m_0 = sum_k f_k = xi (Eq. (3-15)) = m_0^eq (Eq. (m0A)); it is set to that exact value
+    rather than to its floating-point residual, which would otherwise feed a systematic
+    rounding drift of the species totals into every step.
     """
     lat = prob.lat
     xi = mole_fractions(f)
@@ -165,16 +170,13 @@ def collide(prob: Problem, f: np.ndarray) -> np.ndarray:
         L0 = np.full_like(L1, prob.lambda0)
     per_order = {0: L0, 1: L1, 2: L2}
 
-    M0 = lat.M0
-    mom = np.einsum("rk,ik...->ir...", M0, f)
-    meq_unit = M0 @ lat.w                       # M0 applied to (w_0, ..., w_{q-1})
-    meq = meq_unit[(None, slice(None)) + (None,) * lat.d] * xi_e[:, None]
-    dm = mom - meq
-    mpost = mom.copy()
+    feq = lat.w[(None, slice(None)) + (None,) * lat.d] * xi_e[:, None]
+    dm = np.einsum("rk,ik...->ir...", lat.M0, f - feq)       # m - m^eq (Eq. (3-11))
+    dm[:, 0] = 0.0                                           # conserved moment
+    relaxed = np.empty_like(dm)
     for r in range(lat.q):
-        Lr = per_order[lat.row_order[r]]
-        mpost[:, r] -= np.einsum("...ij,j...->i...", Lr, dm[:, r])
-    return np.einsum("kr,ir...->ik...", np.linalg.inv(M0), mpost)
+        relaxed[:, r] = np.einsum("...ij,j...->i...", per_order[lat.row_order[r]], dm[:, r])
+    return f - np.einsum("kr,ir...->ik...", np.linalg.inv(lat.M0), relaxed)
 
 
 def stream(prob: Problem, fpost: np.ndarray) -> np.ndarray:

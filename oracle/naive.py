@@ -99,11 +99,13 @@ def step(prob, f):
         _, _, L1, L2 = _node_matrices(prob, xi_all)
         L0 = L1 if prob.relax == _ms.RELAX_SRT else [[prob.lambda0] * m for _ in range(m)]
         per = {0: L0, 1: L1, 2: L2}
-        mom = [[sum(M0[r][k] * fn[i][k] for k in range(q)) for r in range(q)] for i in range(m)]
-        meq = [[sum(M0[r][k] * lat.w[k] * xi[i] for k in range(q)) for r in range(q)] for i in range(m)]
-        mp = [[mom[i][r] - sum(per[order[r]][i][j] * (mom[j][r] - meq[j][r]) for j in range(m))
-               for r in range(q)] for i in range(m)]
-        fpost[node] = [[sum(M0inv[k][r] * mp[i][r] for r in range(q)) for k in range(q)] for i in range(m)]
+        # Eq. (3-2): f+ = f - M0^-1 Lambda M0 (f - f^eq); the conserved moment of
+        # f - f^eq is exactly zero (Eq. (3-15)).
+        neq = [[fn[i][k] - lat.w[k] * xi[i] for k in range(q)] for i in range(m)]
+        dm = [[0.0 if r == 0 else sum(M0[r][k] * neq[i][k] for k in range(q)) for r in range(q)] for i in range(m)]
+        rel = [[sum(per[order[r]][i][j] * dm[j][r] for j in range(m)) for r in range(q)] for i in range(m)]
+        fpost[node] = [[fn[i][k] - sum(M0inv[k][r] * rel[i][r] for r in range(q)) for k in range(q)]
+                       for i in range(m)]
     opp = lat.opposite
     out = {}
     for node in f:
