@@ -159,7 +159,10 @@ def main():
     ap.add_argument("--block-x", type=int, default=0)
     ap.add_argument("--block-y", type=int, default=0)
     ap.add_argument("--nontemporal", type=int, default=0)
-    ap.add_argument("--xcd-remap", type=int, default=1)
+    ap.add_argument("--xcd-remap", type=int, default=None)
+    ap.add_argument("--vec", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -171,10 +174,19 @@ def main():
 
     lib()   # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)          # reads and writes copy_probe_mib MiB once each
+        torch.cuda.synchronize()
+        print(f"# copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written",
+              file=sys.stderr, flush=True)
+        del a, b
     w = make_workload(args.workload)
     steps = args.steps if args.steps is not None else w.steps
     launch = dict(block_x=args.block_x, block_y=args.block_y, xcd_remap=args.xcd_remap,
-                  nontemporal=args.nontemporal)
+                  nontemporal=args.nontemporal, vec=args.vec)
     print(f"# workload {w.name}: {w.lattice} N={w.N} shape={w.shape} {w.precision}; "
           f"warmup {args.warmup}, timing {steps} steps", file=sys.stderr, flush=True)
     seconds, sim = time_sweep(w, steps, args.warmup, launch)

@@ -92,7 +92,9 @@ typedef struct msd_problem {
   int32_t linearized;       /* 0: B(xi) at the local composition (Eq. (2-10));
                                1: B frozen at xi_ref (linearised theory, constant D~) */
   int32_t bc[6];            /* enum msd_bc for faces x_lo, x_hi, y_lo, y_hi, z_lo, z_hi */
-  int32_t reserved[2];      /* must be 0 */
+  int32_t plane_pad;        /* extra values between consecutive distribution planes: a multiple
+                               of 64, >= 0 (0 = planes of the node count rounded up to 64) */
+  int32_t reserved;         /* must be 0 */
 } msd_problem;
 
 typedef struct msd_sim msd_sim;
@@ -173,8 +175,13 @@ typedef struct msd_launch {
   int32_t block_y;
   int32_t xcd_remap;
   int32_t lds_resident;
-  int32_t nontemporal;      /* 1: streaming stores bypass the caches */
-  int32_t reserved[3];
+  int32_t nontemporal;      /* bit mask of streaming (non-temporal) hints: 1 stores, 2 loads of
+                               unshifted and y/z-shifted planes, 4 loads of x-shifted planes */
+  int32_t vec;              /* nodes per thread of the vectorised sweep: 1, 2 or 4 (aligned
+                               vector accesses; used when nx % vec == 0, else the largest
+                               power of two dividing nx); 0 (default) selects the general
+                               one-node-per-thread kernel */
+  int32_t reserved[2];
 } msd_launch;
 
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);

@@ -42,7 +42,8 @@ class MsdProblem(C.Structure):
         ("relax", C.c_int32),
         ("linearized", C.c_int32),
         ("bc", C.c_int32 * 6),
-        ("reserved", C.c_int32 * 2),
+        ("plane_pad", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -53,7 +54,8 @@ class MsdLaunch(C.Structure):
         ("xcd_remap", C.c_int32),
         ("lds_resident", C.c_int32),
         ("nontemporal", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("vec", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 

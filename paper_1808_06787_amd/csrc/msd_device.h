@@ -18,7 +18,7 @@
 //         Lambda_1 odd(f - f^eq) + Lambda_2 even(f - f^eq)
 //     with odd/even the antisymmetric/symmetric parts over opposite pairs,
 //     whatever moment matrix is used.  With Lambda_2 = Lambda_1 + diag(delta):
-//         f^+_k = w_k xi + (2K - I)(f_k - w_k xi) - delta * even_k.
+//         f^+_k = f_k - Lambda_1 (f_k - w_k xi) - delta * even_k.
 // The flux follows the same way: with grad xi = -(1/a) Lambda_1 m1
 // (Eq. (3-27)) and J = -c_t D~ grad xi (Eq. (2-12)), J = c_t K m1.
 #pragma once
@@ -199,32 +199,42 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T
   T K[M][M];
   ms_inverse<M, T>(xb, R, T(0.5 * L::cs2), K);
 
-  // G = 2K - I; delta_i = lambda_2^ii - lambda_1^ii with lambda_1^ii = 2 (1 - K_ii).
-  T G[M][M], delta[M];
+  // Lambda_1 = 2 (I - K); delta_i = lambda_2^ii - lambda_1^ii (zero in SRT mode).
+  T L1[M][M], delta[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) G[i][j] = T(2) * K[i][j] - (i == j ? T(1) : T(0));
-    const T l1 = T(2) - T(2) * K[i][i];
+    for (int j = 0; j < M; ++j) L1[i][j] = (i == j ? T(2) : T(0)) - T(2) * K[i][j];
+    const T l1 = L1[i][i];
     delta[i] = srt ? T(0) : (T(8) * (l1 - T(2)) / (l1 - T(8)) - l1);
   }
 
+  // Non-equilibrium parts f_k - w_k xi.  The rest population's part closes the
+  // sum to zero (exact in real arithmetic since sum_k w_k = 1), so the rounded
+  // weights cannot bias the species totals step after step.
   T neq[M][Q];
 #pragma unroll
-  for (int i = 0; i < M; ++i)
+  for (int i = 0; i < M; ++i) {
+    T s = T(0);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) neq[i][k] = f[i][k] - T(L::w(k)) * xi[i];
+    for (int k = 1; k < Q; ++k) {
+      neq[i][k] = f[i][k] - T(L::w(k)) * xi[i];
+      s += neq[i][k];
+    }
+    neq[i][0] = -s;
+  }
 
+  // f^+_k = f_k - Lambda_1 neq_k - delta * even_k   (Lambda_2 = Lambda_1 + diag(delta))
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int kb = L::opp(k);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      T acc = T(L::w(k)) * xi[i];
+      T acc = T(0);
 #pragma unroll
-      for (int j = 0; j < M; ++j) acc += G[i][j] * neq[j][k];
+      for (int j = 0; j < M; ++j) acc += L1[i][j] * neq[j][k];
       const T even = (k == kb) ? neq[i][k] : T(0.5) * (neq[i][k] + neq[i][kb]);
-      f[i][k] = acc - delta[i] * even;
+      f[i][k] = f[i][k] - acc - delta[i] * even;
     }
   }
 }
@@ -246,22 +256,33 @@ __device__ __forceinline__ int32_t extent(const Problem& p, int a) {
   return a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
 }
 
+// Load with an optional non-temporal (streaming) hint.
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, bool nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+// Bits of the non-temporal mask of a sweep launch.
+constexpr int NT_STORE = 1, NT_LOAD_ALIGNED = 2, NT_LOAD_SHIFTED = 4;
+
 // f_k^i(x, t) for all i of one direction k: the post-collision value of the
 // source node x - c_k, or at a wall face
 //   zero flux:  f_kbar^+(x)            (half-way bounce-back)
 //   Dirichlet: -f_kbar^+(x) + 2 w_kbar xi_b   (half-way anti-bounce-back)
 // `src` is the post-collision buffer; plane(i, k) is at src + (i*Q + k)*plane.
-template <int LAT, int M, typename T, typename Ptr>
-__device__ __forceinline__ void pull_direction(const Problem& p, Ptr src, const NodePos& n, int k,
-                                               T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M]) {
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void pull_direction(const Problem& p, const T* src, const NodePos& n, int k,
+                                               T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M], int nt) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
   const int a = L::axis(k);
+  const bool nt_al = (nt & NT_LOAD_ALIGNED) != 0;
   if (a < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+    for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + n.idx, nt_al);
     return;
   }
+  const bool nt_sh = (a == 0) ? (nt & NT_LOAD_SHIFTED) != 0 : nt_al;
   const int s = L::sgn(k);
   const int32_t ext = extent(p, a);
   const int64_t st = axis_stride<LAT>(p, a);
@@ -271,30 +292,31 @@ __device__ __forceinline__ void pull_direction(const Problem& p, Ptr src, const 
   if (kind == BC_PERIODIC) {
     const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+    for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + off, nt_sh);
   } else {
     const int kb = L::opp(k);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      const T back = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
+      const T back = ld(src + (int64_t)(i * Q + kb) * p.plane + n.idx, nt_al);
       out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
     }
   }
 }
 
-template <int LAT, int M, typename T, typename Ptr>
-__device__ __forceinline__ void gather_node(const Problem& p, Ptr src, const NodePos& n, bool pull,
-                                            T (&f)[M][Lattice<LAT>::Q], const T (&wall)[6][M]) {
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void gather_node(const Problem& p, const T* src, const NodePos& n, bool pull,
+                                            T (&f)[M][Lattice<LAT>::Q], const T (&wall)[6][M], int nt = 0) {
   constexpr int Q = Lattice<LAT>::Q;
   if (!pull) {
+    const bool nt_al = (nt & NT_LOAD_ALIGNED) != 0;
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
-      for (int k = 0; k < Q; ++k) f[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+      for (int k = 0; k < Q; ++k) f[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + n.idx, nt_al);
     return;
   }
 #pragma unroll
-  for (int k = 0; k < Q; ++k) pull_direction<LAT, M, T>(p, src, n, k, f, wall);
+  for (int k = 0; k < Q; ++k) pull_direction<LAT, M, T>(p, src, n, k, f, wall, nt);
 }
 
 }  // namespace msd

@@ -120,12 +120,184 @@ __global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ s
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
   T f[M][Q];
-  gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall);
+  gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
   collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
-    for (int k = 0; k < Q; ++k) store_value(dst + (int64_t)(i * Q + k) * p.plane + n.idx, f[i][k], nontemporal);
+    for (int k = 0; k < Q; ++k)
+      store_value(dst + (int64_t)(i * Q + k) * p.plane + n.idx, f[i][k], nontemporal & NT_STORE);
+}
+
+// ---------------------------------------------------------------------------
+// Vectorised sweep: each thread owns V consecutive x-nodes of one row and moves
+// them with aligned V-wide loads and stores; plane offsets are 32-bit so that
+// every access is (uniform plane base) + (per-lane offset).  The +-x neighbours
+// of a thread's segment come from the adjacent lanes by a shuffle; only the
+// first / last lane of a wave, and the lanes at a row end, load them.
+// Requires block_x % 64 == 0 (a wave is one row segment), nx % V == 0 and
+// plane * sizeof(T) < 2^32.
+// ---------------------------------------------------------------------------
+template <typename T, int V>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(V)));
+};
+
+template <typename T, int V>
+__device__ __forceinline__ typename VecOf<T, V>::type vload(const T* base, uint32_t idx, bool nt) {
+  const auto* p = reinterpret_cast<const typename VecOf<T, V>::type*>(reinterpret_cast<const char*>(base) +
+                                                                      idx * (uint32_t)sizeof(T));
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T>
+__device__ __forceinline__ T sload(const T* base, uint32_t idx, bool nt) {
+  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T* base, uint32_t idx, typename VecOf<T, V>::type v, int nontemporal) {
+  auto* p = reinterpret_cast<typename VecOf<T, V>::type*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T));
+  if (nontemporal)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <int LAT, int M, typename T, int V>
+__global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict__ src, T* __restrict__ dst,
+                                                  const Consts<T>* __restrict__ cst, int pull, Tiling tl,
+                                                  int nontemporal) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  using VT = typename VecOf<T, V>::type;
+  const uint32_t tile = logical_tile(tl);
+  const uint32_t tx = tile % tl.tiles_x;
+  const uint32_t rest = tile / tl.tiles_x;
+  const uint32_t ty = rest % tl.tiles_y;
+  const uint32_t tz = rest / tl.tiles_y;
+  const int32_t x0 = (int32_t)((tx * blockDim.x + threadIdx.x) * V);
+  const int32_t y = (int32_t)(ty * blockDim.y + threadIdx.y);
+  const int32_t z = (int32_t)tz;
+  if (x0 >= p.nx || y >= p.ny) return;
+  const uint32_t nx = (uint32_t)p.nx;
+  const uint32_t idx0 = (uint32_t)x0 + nx * ((uint32_t)y + (uint32_t)p.ny * (uint32_t)z);
+  const int lane = (int)(threadIdx.x & 63u);
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  const bool nt_al = (nontemporal & NT_LOAD_ALIGNED) != 0;
+  const bool nt_sh = (nontemporal & NT_LOAD_SHIFTED) != 0;
+
+  T f[V][M][Q];
+  if (!pull) {
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const VT v = vload<T, V>(src + (size_t)(i * Q + k) * p.plane, idx0, nt_al);
+#pragma unroll
+        for (int j = 0; j < V; ++j) f[j][i][k] = v[j];
+      }
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int a = L::axis(k);
+      const int s = L::sgn(k);
+      const int kb = L::opp(k);
+      const int face = 2 * (a < 0 ? 0 : a) + (s > 0 ? 0 : 1);
+      if (a < 0) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const VT v = vload<T, V>(src + (size_t)(i * Q + k) * p.plane, idx0, nt_al);
+#pragma unroll
+          for (int j = 0; j < V; ++j) f[j][i][k] = v[j];
+        }
+      } else if (a > 0) {
+        // y or z: the whole segment pulls from one neighbouring row (wave-uniform)
+        const uint32_t ext = (uint32_t)(a == 1 ? p.ny : p.nz);
+        const uint32_t st = a == 1 ? nx : nx * (uint32_t)p.ny;
+        const uint32_t coord = (uint32_t)(a == 1 ? y : z);
+        const bool edge = (s > 0) ? (coord == 0) : (coord == ext - 1);
+        const int kind = edge ? p.bc[face] : BC_PERIODIC;
+        if (kind == BC_PERIODIC) {
+          const uint32_t off = edge ? (s > 0 ? idx0 + (ext - 1) * st : idx0 - (ext - 1) * st)
+                                    : (s > 0 ? idx0 - st : idx0 + st);
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            const VT v = vload<T, V>(src + (size_t)(i * Q + k) * p.plane, off, nt_al);
+#pragma unroll
+            for (int j = 0; j < V; ++j) f[j][i][k] = v[j];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            const VT v = vload<T, V>(src + (size_t)(i * Q + kb) * p.plane, idx0, nt_al);
+            const T wb = T(2.0 * L::w(kb)) * nc.wall[face][i];
+#pragma unroll
+            for (int j = 0; j < V; ++j) f[j][i][k] = (kind == BC_ZERO_FLUX) ? v[j] : wb - v[j];
+          }
+        }
+      } else {
+        // x: own aligned vector, one value from the neighbouring lane
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const T* pk = src + (size_t)(i * Q + k) * p.plane;
+          const VT v = vload<T, V>(pk, idx0, nt_sh);
+          if (s > 0) {
+            const T from_lane = __shfl_up(v[V - 1], 1, 64);
+            T left;
+            if (x0 == 0) {
+              const int kind = p.bc[0];
+              if (kind == BC_PERIODIC) {
+                left = sload(pk, idx0 + nx - 1, nt_sh);
+              } else {
+                const T back = sload(src + (size_t)(i * Q + kb) * p.plane, idx0, nt_sh);
+                left = (kind == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[0][i] - back;
+              }
+            } else if (lane == 0) {
+              left = sload(pk, idx0 - 1, nt_sh);
+            } else {
+              left = from_lane;
+            }
+            f[0][i][k] = left;
+#pragma unroll
+            for (int j = 1; j < V; ++j) f[j][i][k] = v[j - 1];
+          } else {
+            const T from_lane = __shfl_down(v[0], 1, 64);
+            T right;
+            if ((uint32_t)x0 + V == nx) {
+              const int kind = p.bc[1];
+              if (kind == BC_PERIODIC) {
+                right = sload(pk, idx0 + V - nx, nt_sh);
+              } else {
+                const T back = sload(src + (size_t)(i * Q + kb) * p.plane, idx0 + V - 1, nt_sh);
+                right = (kind == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[1][i] - back;
+              }
+            } else if (lane == 63) {
+              right = sload(pk, idx0 + V, nt_sh);
+            } else {
+              right = from_lane;
+            }
+#pragma unroll
+            for (int j = 0; j + 1 < V; ++j) f[j][i][k] = v[j + 1];
+            f[V - 1][i][k] = right;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) collide_node<LAT, M, T>(f[j], nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      VT o;
+#pragma unroll
+      for (int j = 0; j < V; ++j) o[j] = f[j][i][k];
+      vstore<T, V>(dst + (size_t)(i * Q + k) * p.plane, idx0, o, nontemporal & NT_STORE);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -353,13 +525,25 @@ __global__ void k_diag_final(const double* __restrict__ partials, int blocks, in
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
-inline Tiling make_tiling(const LaunchArgs& a) {
+inline Tiling make_tiling(const LaunchArgs& a, int V = 1) {
   Tiling t;
-  t.tiles_x = (uint32_t)((a.p.nx + a.block_x - 1) / a.block_x);
+  const int64_t span = (int64_t)a.block_x * V;
+  t.tiles_x = (uint32_t)((a.p.nx + span - 1) / span);
   t.tiles_y = (uint32_t)((a.p.ny + a.block_y - 1) / a.block_y);
   t.tiles = t.tiles_x * t.tiles_y * (uint32_t)a.p.nz;
   t.remap = a.xcd_remap ? 1u : 0u;
   return t;
+}
+
+// Width of the vectorised sweep for this launch: the requested vec (1, 2, 4)
+// when the extents and offsets allow it, else 0 (the general 64-bit kernel).
+template <typename T>
+int vec_width(const LaunchArgs& a) {
+  if (a.vec <= 0 || a.block_x % 64) return 0;
+  if ((uint64_t)a.p.plane * sizeof(T) >= (1ull << 32)) return 0;
+  for (int v = a.vec; v >= 1; v >>= 1)
+    if (a.p.nx % v == 0) return v;
+  return 0;
 }
 
 template <int LAT, int M, typename T>
@@ -382,9 +566,23 @@ hipError_t run(Op op, const LaunchArgs& a) {
       break;
     }
     case Op::Step: {
-      const Tiling tl = make_tiling(a);
-      hipLaunchKernelGGL((k_step<LAT, M, T>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream, a.p,
-                         static_cast<const T*>(a.src), static_cast<T*>(a.dst), cst, a.pull, tl, a.nontemporal);
+      const int V = vec_width<T>(a);
+      const Tiling tl = make_tiling(a, V > 0 ? V : 1);
+      const dim3 grid(tl.tiles), block(a.block_x, a.block_y);
+      const T* src = static_cast<const T*>(a.src);
+      T* dst = static_cast<T*>(a.dst);
+      if (V == 4)
+        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 4>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                           a.nontemporal);
+      else if (V == 2)
+        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 2>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                           a.nontemporal);
+      else if (V == 1)
+        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 1>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                           a.nontemporal);
+      else
+        hipLaunchKernelGGL((k_step<LAT, M, T>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                           a.nontemporal);
       break;
     }
     case Op::StepLds: {

@@ -36,6 +36,7 @@ struct LaunchArgs {
   int block_x = 256, block_y = 1;
   int xcd_remap = 1;
   int nontemporal = 0;
+  int vec = 1;               // nodes per thread of the vectorised sweep (0: general kernel)
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;

@@ -28,7 +28,7 @@ def _dptr(t: torch.Tensor) -> int:
 
 
 def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", bc=None, xi_wall=None,
-                 relax: str = "paper", c_t: float = 1.0, xi_ref=None):
+                 relax: str = "paper", c_t: float = 1.0, xi_ref=None, plane_pad: int = 0):
     """Build an msd_problem plus the host arrays it points to (kept alive by the caller).
 
     bc: per axis (low, high) names from BCS; xi_wall: {(axis, side): (N,) values}.
@@ -68,6 +68,7 @@ def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", 
         p.linearized = 1
     p.c_t = float(c_t)
     p.relax = RELAX[relax]
+    p.plane_pad = int(plane_pad)
     return p, keep
 
 
@@ -75,14 +76,16 @@ class Sim:
     """One mixture on one lattice, evolved by the HIP sweep."""
 
     def __init__(self, lattice: str, D, shape, precision: str = "f32", bc=None, xi_wall=None,
-                 relax: str = "paper", c_t: float = 1.0, xi_ref=None, device=None, stream=None):
+                 relax: str = "paper", c_t: float = 1.0, xi_ref=None, device=None, stream=None,
+                 plane_pad: int = 0):
         self.lib = F.lib()
         self.lattice = lattice
         self.shape = tuple(int(s) for s in shape)
         self.d = DIMS[lattice]
         self.precision = precision
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.problem, self._keep = make_problem(lattice, D, shape, precision, bc, xi_wall, relax, c_t, xi_ref)
+        self.problem, self._keep = make_problem(lattice, D, shape, precision, bc, xi_wall, relax, c_t, xi_ref,
+                                                plane_pad)
         self.N = self.problem.n_species
         self.m = self.N - 1
         status = C.c_int32(0)
@@ -116,16 +119,18 @@ class Sim:
         return TORCH_DTYPES[PRECISIONS[self.precision]]
 
     # -- calls --------------------------------------------------------------------
-    def set_launch(self, block_x=0, block_y=0, xcd_remap=1, lds_resident=1, nontemporal=0):
+    def set_launch(self, block_x=0, block_y=0, xcd_remap=None, lds_resident=1, nontemporal=0, vec=0):
+        if xcd_remap is None:
+            xcd_remap = 1 if self.lattice == "D3Q7" else 0
         l = F.MsdLaunch()
-        l.block_x, l.block_y, l.xcd_remap, l.lds_resident, l.nontemporal = (
-            block_x, block_y, xcd_remap, lds_resident, nontemporal)
+        l.block_x, l.block_y, l.xcd_remap, l.lds_resident, l.nontemporal, l.vec = (
+            block_x, block_y, xcd_remap, lds_resident, nontemporal, vec)
         F.check(self.lib.msd_set_launch(self._h, C.byref(l)), "msd_set_launch")
 
     def get_launch(self) -> dict:
         l = F.MsdLaunch()
         F.check(self.lib.msd_get_launch(self._h, C.byref(l)), "msd_get_launch")
-        return {k: getattr(l, k) for k in ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal")}
+        return {k: getattr(l, k) for k in ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec")}
 
     def init(self, xi0):
         """xi0: (N or N-1, *nodes) array or tensor; float32/float64."""

@@ -57,7 +57,7 @@ def test_workspace_size_model():
     p, keep = make_problem("D2Q5", D, (100, 37), "f32")
     n, st = _ws(p)
     assert st == 0
-    plane = (100 * 37 + 63) // 64 * 64 + 64
+    plane = (100 * 37 + 63) // 64 * 64
     # two halves of m*q planes plus < 1 MiB of constants and reduction scratch
     assert 2 * 2 * 5 * plane * 4 <= n < 2 * 2 * 5 * plane * 4 + (1 << 20)
 
@@ -77,6 +77,9 @@ def test_workspace_size_model():
         (lambda p: p.bc.__setitem__(0, 1), -1),      # periodic paired with zero flux
         (lambda p: p.bc.__setitem__(4, 1), -1),      # z faces on a 2D lattice
         (lambda p: p.bc.__setitem__(0, 9), -1),
+        (lambda p: setattr(p, "plane_pad", 32), -1),
+        (lambda p: setattr(p, "plane_pad", -64), -1),
+        (lambda p: setattr(p, "reserved", 1), -1),
     ],
 )
 def test_validation_codes(mutate, code):
