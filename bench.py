@@ -110,6 +110,57 @@ def sweep_record(w, seconds, steps):
     return mlups, bytes_per_launch, per_launch, achieved
 
 
+def batched_extra(steps: int = 1000, warmup: int = 5):
+    """256-mixture workload: one launch per step (tuned schedule) against one launch
+    of the single-mixture sweep per mixture per step, same steps, same device."""
+    import tempfile
+
+    import torch
+
+    import workloads
+    from paper_1808_06787_amd import autotune
+    from paper_1808_06787_amd.batch import Batch
+
+    ws = workloads.batched_2d(steps=steps)
+    specs = [dict(D=w.D, shape=w.shape, bc=w.bc) for w in ws]
+    b = Batch(specs, "D2Q5", "f32")
+    for i, w in enumerate(ws):
+        b.init(i, torch.from_numpy(w.xi0))
+    b.release_inputs()
+    upd = sum(w.nodes * (w.N - 1) for w in ws)
+    byt = sum(w.nodes * (w.N - 1) * 2 * 5 * 4 for w in ws)
+    del ws
+    cache = os.path.join(tempfile.gettempdir(), "msd_autotune.json")
+    tune = autotune.tune_batch(b, cache_path=cache, steps=5, warmup=1)
+    state, t0 = b.save()
+
+    def timed(fn):
+        fn(warmup)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(b.stream)
+        fn(steps)
+        stop.record(b.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / 1e3
+
+    t_fused = timed(b.step)
+    b.restore(state, t0)
+    t_each = timed(b.step_each)
+    b.close()
+    return {
+        "mixtures": 256, "steps": steps, "node_component_updates_per_step": upd,
+        "MLUPS_batched": round(upd * steps / t_fused / 1e6, 1),
+        "MLUPS_one_launch_per_mixture": round(upd * steps / t_each / 1e6, 1),
+        "speedup_vs_one_launch_per_mixture": round(t_each / t_fused, 3),
+        "ms_per_step_batched": round(t_fused / steps * 1e3, 4),
+        "ms_per_step_one_launch_per_mixture": round(t_each / steps * 1e3, 4),
+        "GB_per_s_batched": round(byt * steps / t_fused / 1e9, 1),
+        "schedule": tune["best"],
+    }
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle (unchanged) on a bounded sub-grid of the workload, single thread."""
     try:
@@ -243,6 +294,10 @@ def main():
         extras["ternary_1d_d1q3_256_f64"] = {"MLUPS": round(m1, 2), "steps_per_s": round(w1.steps / s1, 1),
                                              "seconds": round(s1, 5)}
         print(f"# {w1.name}: {m1:.1f} MLUPS, {w1.steps / s1:.0f} steps/s", file=sys.stderr, flush=True)
+        bx = batched_extra()
+        extras["batched_256_mixtures_d2q5_f32"] = bx
+        print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS fused vs {bx['MLUPS_one_launch_per_mixture']:.0f} "
+              f"one launch per mixture ({bx['speedup_vs_one_launch_per_mixture']:.2f}x)", file=sys.stderr, flush=True)
     if extras:
         out["extras"] = extras
     if not args.no_cpu_baseline:

@@ -188,6 +188,86 @@ MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);
 MSD_API int msd_get_launch(const msd_sim* sim, msd_launch* launch);
 
 /* ---------------------------------------------------------------------------
+ * Batches of independent mixtures
+ *
+ * A batch holds `count` mixtures on one lattice and in one precision; their
+ * number of species, extents, diffusivities, faces and relaxation rules may
+ * all differ.  One msd_batch_step launch advances every node of every mixture
+ * by one time step of Eq. (3-13) (each mixture exactly as msd_step would); the
+ * tile schedule decides how workgroups map onto mixtures.  All mixtures share
+ * one clock: they are initialised at time 0 and step together.
+ * ------------------------------------------------------------------------- */
+
+enum msd_batch_mode {
+  MSD_BATCH_FUSED = 0,      /* one launch per step over all tiles of all mixtures */
+  MSD_BATCH_PER_CLASS = 1   /* one launch per step and per distinct N */
+};
+enum msd_tile_order {
+  MSD_ORDER_INSTANCE = 0,   /* the tiles of a mixture are consecutive workgroups */
+  MSD_ORDER_INTERLEAVED = 1 /* workgroups cycle over mixtures */
+};
+
+typedef struct msd_schedule {
+  int32_t block_x;          /* tile width in nodes (multiple of 64), block_x*block_y <= 256 */
+  int32_t block_y;
+  int32_t mode;             /* enum msd_batch_mode */
+  int32_t order;            /* enum msd_tile_order */
+  int32_t xcd_remap;        /* 1: consecutive tiles of a launch on one XCD */
+  int32_t nontemporal;      /* streaming-hint mask, as in msd_launch */
+  int32_t reserved[2];
+} msd_schedule;
+
+/* Workspace bytes for a batch (every mixture's buffers and constants plus the
+ * mixture table and the largest tile table any schedule needs).  Returns 0 and
+ * sets *status on invalid input (each problem is validated as in
+ * msd_workspace_bytes; all must share lattice and precision; count >= 1). */
+MSD_API size_t msd_batch_workspace_bytes(const msd_problem* problems, int32_t count, int32_t* status);
+
+/* Create a batch over the caller's workspace (>= msd_batch_workspace_bytes,
+ * 256-byte aligned).  Uploads the mixture and tile tables (asynchronously, on
+ * the stream).  The default schedule is 64 x 4 tiles, fused, instance order. */
+MSD_API int msd_batch_create(const msd_problem* problems, int32_t count, void* d_ws, size_t ws_bytes, void* stream,
+                             msd_batch** out);
+
+/* Initialise mixture `index` from N planes of its mole fractions (as msd_init).
+ * Valid only while the batch time is 0. */
+MSD_API int msd_batch_init(msd_batch* batch, int32_t index, const void* d_xi0, int32_t xi0_precision);
+
+/* Advance every mixture by nsteps with the batch schedule (requires every
+ * mixture initialised).  Asynchronous. */
+MSD_API int msd_batch_step(msd_batch* batch, int64_t nsteps);
+
+/* Reference schedule: the same steps with one launch of the single-mixture
+ * sweep per mixture per step (what `count` separate msd_sim handles would do). */
+MSD_API int msd_batch_step_each(msd_batch* batch, int64_t nsteps);
+
+MSD_API int64_t msd_batch_time(const msd_batch* batch);
+
+/* Observables of mixture `index` at the current time, as msd_read_moments. */
+MSD_API int msd_batch_read_moments(msd_batch* batch, int32_t index, int32_t out_precision, void* d_xi, void* d_J,
+                                   void* d_grad);
+
+/* Diagnostics of mixture `index`, as msd_diagnostics (synchronises). */
+MSD_API int msd_batch_diagnostics(msd_batch* batch, int32_t index, double* h_mass, double* h_min, double* h_max,
+                                  int64_t* h_nonfinite);
+
+/* Schedule (re)selection; rebuilds and uploads the tile table. */
+MSD_API int msd_batch_set_schedule(msd_batch* batch, const msd_schedule* schedule);
+MSD_API int msd_batch_get_schedule(const msd_batch* batch, msd_schedule* schedule);
+
+/* Whole-batch checkpoint: the current distributions of every mixture, packed
+ * back to back (msd_batch_state_bytes in total); restore sets the batch time. */
+MSD_API size_t msd_batch_state_bytes(const msd_batch* batch);
+MSD_API int msd_batch_save(const msd_batch* batch, void* d_dst, int64_t* h_step);
+MSD_API int msd_batch_restore(msd_batch* batch, const void* d_src, int64_t step);
+
+/* Number of workgroups of one msd_batch_step launch under the current schedule
+ * (all classes together). */
+MSD_API int64_t msd_batch_tiles(const msd_batch* batch);
+
+MSD_API int msd_batch_destroy(msd_batch* batch);
+
+/* ---------------------------------------------------------------------------
  * Errors and version
  * ------------------------------------------------------------------------- */
 

@@ -59,6 +59,22 @@ class MsdLaunch(C.Structure):
     ]
 
 
+class MsdSchedule(C.Structure):
+    _fields_ = [
+        ("block_x", C.c_int32),
+        ("block_y", C.c_int32),
+        ("mode", C.c_int32),
+        ("order", C.c_int32),
+        ("xcd_remap", C.c_int32),
+        ("nontemporal", C.c_int32),
+        ("reserved", C.c_int32 * 2),
+    ]
+
+
+BATCH_FUSED, BATCH_PER_CLASS = 0, 1
+ORDER_INSTANCE, ORDER_INTERLEAVED = 0, 1
+
+
 class MsdError(RuntimeError):
     def __init__(self, status: int, what: str, detail: str):
         self.status = status
@@ -99,6 +115,21 @@ def lib():
         "msd_save": (C.c_int, [vp, vp, P(i64)]),
         "msd_restore": (C.c_int, [vp, vp, i64]),
         "msd_destroy": (C.c_int, [vp]),
+        "msd_batch_workspace_bytes": (sz, [P(MsdProblem), i32, P(i32)]),
+        "msd_batch_create": (C.c_int, [P(MsdProblem), i32, vp, sz, vp, P(vp)]),
+        "msd_batch_init": (C.c_int, [vp, i32, vp, i32]),
+        "msd_batch_step": (C.c_int, [vp, i64]),
+        "msd_batch_step_each": (C.c_int, [vp, i64]),
+        "msd_batch_time": (i64, [vp]),
+        "msd_batch_read_moments": (C.c_int, [vp, i32, i32, vp, vp, vp]),
+        "msd_batch_diagnostics": (C.c_int, [vp, i32, P(C.c_double), P(C.c_double), P(C.c_double), P(i64)]),
+        "msd_batch_set_schedule": (C.c_int, [vp, P(MsdSchedule)]),
+        "msd_batch_get_schedule": (C.c_int, [vp, P(MsdSchedule)]),
+        "msd_batch_state_bytes": (sz, [vp]),
+        "msd_batch_save": (C.c_int, [vp, vp, P(i64)]),
+        "msd_batch_restore": (C.c_int, [vp, vp, i64]),
+        "msd_batch_tiles": (i64, [vp]),
+        "msd_batch_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -20,6 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmsd.so")
 SOURCES = [
     "msd_api.hip",
+    "msd_batch.hip",
     "msd_lat_d1q3.hip",
     "msd_lat_d2q5.hip",
     "msd_lat_d3q7.hip",

@@ -13,9 +13,11 @@
 #include <string>
 
 #include "../../include/msd.h"
+#include "msd_host.h"
 #include "msd_launch.h"
 
-namespace {
+namespace msd {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -32,20 +34,6 @@ int fail(int status, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
   return fail(MSD_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-int lattice_q(int lat) { return lat == MSD_D1Q3 ? 3 : (lat == MSD_D2Q5 ? 5 : 7); }
-int lattice_d(int lat) { return lat == MSD_D1Q3 ? 1 : (lat == MSD_D2Q5 ? 2 : 3); }
-
-constexpr int kDiagBlocksMax = 1024;
-
-struct Layout {
-  int64_t nodes = 0, plane = 0;
-  size_t consts_off = 0, partials_off = 0, diag_out_off = 0, half_off[2] = {0, 0};
-  size_t half_bytes = 0, total = 0;
-  int diag_blocks = 0;
-};
 
 int validate(const msd_problem* p) {
   if (!p) return fail(MSD_EINVAL, "problem is NULL");
@@ -111,6 +99,36 @@ int validate(const msd_problem* p) {
   return MSD_OK;
 }
 
+void fill_kernel_problem(const msd_problem* problem, int64_t plane, Problem* out) {
+  Problem& kp = *out;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.nx = (int32_t)problem->nx;
+  kp.ny = (int32_t)problem->ny;
+  kp.nz = (int32_t)problem->nz;
+  kp.relax = problem->relax;
+  kp.linearized = problem->linearized ? 1 : 0;
+  for (int f = 0; f < 6; ++f) kp.bc[f] = problem->bc[f];
+  kp.plane = plane;
+  kp.c_t = problem->c_t;
+  const int N = problem->n_species;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) kp.D[i][j] = (i == j) ? 1.0 : problem->D[i * N + j];
+  for (int f = 0; f < 6; ++f)
+    for (int i = 0; i < N; ++i)
+      kp.wall[f][i] = (problem->bc[f] == MSD_BC_DIRICHLET) ? problem->xi_wall[f * N + i] : 0.0;
+  if (problem->linearized)
+    for (int i = 0; i < N; ++i) kp.xi_ref[i] = problem->xi_ref[i];
+}
+
+hipError_t dispatch(Op op, const LaunchArgs& a) {
+  switch (a.lattice) {
+    case MSD_D1Q3: return msd::dispatch<1>(op, a);
+    case MSD_D2Q5: return msd::dispatch<2>(op, a);
+    case MSD_D3Q7: return msd::dispatch<3>(op, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 Layout layout_for(const msd_problem* p) {
   Layout L;
   const int m = p->n_species - 1, q = lattice_q(p->lattice), s = p->precision;
@@ -135,7 +153,25 @@ Layout layout_for(const msd_problem* p) {
   return L;
 }
 
-}  // namespace
+// Defaults from measurements on MI355X (4096^2 D2Q5 and 512^3 D3Q7, FP32): the
+// one-node-per-thread kernel with 256-thread row tiles runs at the speed of a
+// plain copy of the same planes; vector widths 2/4, streaming hints and plane
+// padding do not improve on it.  Remapping tiles onto XCDs helps in 3D (+1.5 %)
+// and costs 3 % in 2D.
+void default_launch(const msd_problem* p, msd_launch* l) {
+  std::memset(l, 0, sizeof(*l));
+  l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
+  l->block_y = std::max(1, (int)std::min<int64_t>(256 / l->block_x, p->ny));
+  l->xcd_remap = p->lattice == MSD_D3Q7 ? 1 : 0;
+  l->lds_resident = 1;
+  l->nontemporal = 0;
+  l->vec = 0;
+}
+
+}  // namespace host
+}  // namespace msd
+
+using namespace msd::host;
 
 struct msd_sim {
   msd_problem prob;          // pointers inside are not kept
@@ -167,30 +203,6 @@ msd::LaunchArgs base_args(const msd_sim* s) {
   a.nontemporal = s->launch.nontemporal;
   a.vec = s->launch.vec;
   return a;
-}
-
-hipError_t dispatch(msd::Op op, const msd::LaunchArgs& a) {
-  switch (a.lattice) {
-    case MSD_D1Q3: return msd::dispatch<1>(op, a);
-    case MSD_D2Q5: return msd::dispatch<2>(op, a);
-    case MSD_D3Q7: return msd::dispatch<3>(op, a);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-// Defaults from measurements on MI355X (4096^2 D2Q5 and 512^3 D3Q7, FP32): the
-// one-node-per-thread kernel with 256-thread row tiles runs at the speed of a
-// plain copy of the same planes; vector widths 2/4, streaming hints and plane
-// padding do not improve on it.  Remapping tiles onto XCDs helps in 3D (+1.5 %)
-// and costs 3 % in 2D.
-void default_launch(const msd_problem* p, msd_launch* l) {
-  std::memset(l, 0, sizeof(*l));
-  l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
-  l->block_y = std::max(1, (int)std::min<int64_t>(256 / l->block_x, p->ny));
-  l->xcd_remap = p->lattice == MSD_D3Q7 ? 1 : 0;
-  l->lds_resident = 1;
-  l->nontemporal = 0;
-  l->vec = 0;
 }
 
 bool use_lds(const msd_sim* s) {
@@ -252,24 +264,7 @@ int msd_create(const msd_problem* problem, void* d_ws, size_t ws_bytes, void* st
   s->d = lattice_d(problem->lattice);
   s->ws = static_cast<char*>(d_ws);
   s->stream = static_cast<hipStream_t>(stream);
-  msd::Problem& kp = s->kp;
-  std::memset(&kp, 0, sizeof(kp));
-  kp.nx = (int32_t)problem->nx;
-  kp.ny = (int32_t)problem->ny;
-  kp.nz = (int32_t)problem->nz;
-  kp.relax = problem->relax;
-  kp.linearized = problem->linearized ? 1 : 0;
-  for (int f = 0; f < 6; ++f) kp.bc[f] = problem->bc[f];
-  kp.plane = L.plane;
-  kp.c_t = problem->c_t;
-  const int N = problem->n_species;
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) kp.D[i][j] = (i == j) ? 1.0 : problem->D[i * N + j];
-  for (int f = 0; f < 6; ++f)
-    for (int i = 0; i < N; ++i)
-      kp.wall[f][i] = (problem->bc[f] == MSD_BC_DIRICHLET) ? problem->xi_wall[f * N + i] : 0.0;
-  if (problem->linearized)
-    for (int i = 0; i < N; ++i) kp.xi_ref[i] = problem->xi_ref[i];
+  fill_kernel_problem(problem, L.plane, &s->kp);
   default_launch(problem, &s->launch);
   *out = s;
   return MSD_OK;

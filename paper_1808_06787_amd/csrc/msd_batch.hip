@@ -1,0 +1,452 @@
+// C ABI of batches of independent mixtures (include/msd.h, "Batches").
+// Host code validates, lays out the caller's workspace, builds the mixture and
+// tile tables and launches kernels; the arithmetic runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/msd.h"
+#include "msd_host.h"
+#include "msd_launch.h"
+
+using namespace msd::host;
+
+namespace {
+
+struct Member {
+  msd_problem prob;          // host pointers cleared
+  msd::Problem kp;
+  int m = 0;
+  int64_t nodes = 0, plane = 0;
+  size_t consts_off = 0, half_off[2] = {0, 0}, state_bytes = 0;
+  int diag_blocks = 0;
+  bool initialised = false;
+  msd_launch single;         // launch of the single-mixture sweep (reference schedule)
+};
+
+struct Range {
+  int mmax;
+  uint32_t begin, count;
+};
+
+struct BatchLayout {
+  size_t desc_off = 0, tiles_off = 0, partials_off = 0, diag_out_off = 0, total = 0;
+  int64_t max_tiles = 0;
+  std::vector<size_t> consts_off, half_off0, half_off1, state_bytes;
+  std::vector<int64_t> plane;
+};
+
+int validate_batch(const msd_problem* probs, int32_t count) {
+  if (!probs) return fail(MSD_EINVAL, "problems is NULL");
+  if (count < 1) return fail(MSD_EINVAL, "count = %d", count);
+  for (int32_t b = 0; b < count; ++b) {
+    const int st = validate(&probs[b]);
+    if (st != MSD_OK) return st;
+    if (probs[b].lattice != probs[0].lattice || probs[b].precision != probs[0].precision)
+      return fail(MSD_EINVAL, "mixture %d: all mixtures of a batch share lattice and precision", b);
+  }
+  return MSD_OK;
+}
+
+BatchLayout batch_layout(const msd_problem* probs, int32_t count) {
+  BatchLayout L;
+  const int q = lattice_q(probs[0].lattice), s = probs[0].precision;
+  size_t off = 0;
+  L.desc_off = off;
+  off = align_up(off + sizeof(msd::BatchInst) * (size_t)count, 256);
+  for (int32_t b = 0; b < count; ++b)
+    L.max_tiles += (probs[b].nx + 63) / 64 * probs[b].ny * probs[b].nz;
+  L.tiles_off = off;
+  off = align_up(off + sizeof(msd::BatchTile) * (size_t)L.max_tiles, 256);
+  L.partials_off = off;
+  off = align_up(off + sizeof(double) * kDiagBlocksMax * (3 * MSD_MAX_SPECIES + 1), 256);
+  L.diag_out_off = off;
+  off = align_up(off + sizeof(double) * (3 * MSD_MAX_SPECIES + 1), 256);
+  for (int32_t b = 0; b < count; ++b) {
+    const int64_t nodes = probs[b].nx * probs[b].ny * probs[b].nz;
+    const int64_t plane = (nodes + 63) / 64 * 64 + probs[b].plane_pad;
+    const size_t half = align_up((size_t)(probs[b].n_species - 1) * q * (size_t)plane * s, 256);
+    L.plane.push_back(plane);
+    L.consts_off.push_back(off);
+    off = align_up(off + msd::kConstsBytes, 256);
+    L.half_off0.push_back(off);
+    off += half;
+    L.half_off1.push_back(off);
+    off += half;
+    L.state_bytes.push_back((size_t)(probs[b].n_species - 1) * q * (size_t)plane * s);
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct msd_batch {
+  int count = 0, lattice = 0, prec = 4, q = 0, d = 0;
+  std::vector<Member> mem;
+  BatchLayout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<msd::BatchInst> h_desc;
+  std::vector<msd::BatchTile> h_tiles;
+  std::vector<Range> ranges;
+  msd_schedule sched{};
+  int cur = 0;
+  int64_t t = 0;
+};
+
+namespace {
+
+msd::LaunchArgs member_args(const msd_batch* b, int idx) {
+  const Member& M = b->mem[idx];
+  msd::LaunchArgs a;
+  a.p = M.kp;
+  a.lattice = b->lattice;
+  a.m = M.m;
+  a.prec = b->prec;
+  a.stream = b->stream;
+  a.consts = b->ws + M.consts_off;
+  a.n_species = M.m + 1;
+  a.block_x = M.single.block_x;
+  a.block_y = M.single.block_y;
+  a.xcd_remap = M.single.xcd_remap;
+  a.nontemporal = M.single.nontemporal;
+  a.vec = M.single.vec;
+  return a;
+}
+
+int build_tiles(msd_batch* b) {
+  const msd_schedule& sc = b->sched;
+  std::vector<int> idx(b->count);
+  for (int i = 0; i < b->count; ++i) idx[i] = i;
+  std::vector<std::vector<int>> groups;
+  if (sc.mode == MSD_BATCH_PER_CLASS) {
+    for (int m = 1; m < MSD_MAX_SPECIES; ++m) {
+      std::vector<int> g;
+      for (int i : idx)
+        if (b->mem[i].m == m) g.push_back(i);
+      if (!g.empty()) groups.push_back(g);
+    }
+  } else {
+    groups.push_back(idx);
+  }
+  b->h_tiles.clear();
+  b->ranges.clear();
+  for (const auto& g : groups) {
+    Range r;
+    r.mmax = 0;
+    r.begin = (uint32_t)b->h_tiles.size();
+    std::vector<uint32_t> nt(g.size());
+    uint32_t most = 0;
+    for (size_t j = 0; j < g.size(); ++j) {
+      const msd_problem& p = b->mem[g[j]].prob;
+      const uint32_t tx = (uint32_t)((p.nx + sc.block_x - 1) / sc.block_x);
+      const uint32_t ty = (uint32_t)((p.ny + sc.block_y - 1) / sc.block_y);
+      nt[j] = tx * ty * (uint32_t)p.nz;
+      most = std::max(most, nt[j]);
+      r.mmax = std::max(r.mmax, b->mem[g[j]].m);
+    }
+    if (sc.order == MSD_ORDER_INTERLEAVED) {
+      for (uint32_t k = 0; k < most; ++k)
+        for (size_t j = 0; j < g.size(); ++j)
+          if (k < nt[j]) b->h_tiles.push_back({(uint32_t)g[j], k});
+    } else {
+      for (size_t j = 0; j < g.size(); ++j)
+        for (uint32_t k = 0; k < nt[j]; ++k) b->h_tiles.push_back({(uint32_t)g[j], k});
+    }
+    r.count = (uint32_t)b->h_tiles.size() - r.begin;
+    b->ranges.push_back(r);
+  }
+  if ((int64_t)b->h_tiles.size() > b->L.max_tiles) return fail(MSD_EINVAL, "tile table overflow");
+  // the host copy must stay untouched until the upload has been consumed
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch tile table synchronise");
+  e = hipMemcpyAsync(b->ws + b->L.tiles_off, b->h_tiles.data(), sizeof(msd::BatchTile) * b->h_tiles.size(),
+                     hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch tile table upload");
+  e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch tile table synchronise");
+  return MSD_OK;
+}
+
+int check_index(const msd_batch* b, int32_t index) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (index < 0 || index >= b->count) return fail(MSD_EINVAL, "index %d outside [0, %d)", index, b->count);
+  return MSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t msd_batch_workspace_bytes(const msd_problem* problems, int32_t count, int32_t* status) {
+  const int st = validate_batch(problems, count);
+  if (status) *status = st;
+  if (st != MSD_OK) return 0;
+  return batch_layout(problems, count).total;
+}
+
+int msd_batch_create(const msd_problem* problems, int32_t count, void* d_ws, size_t ws_bytes, void* stream,
+                     msd_batch** out) {
+  if (!out) return fail(MSD_EINVAL, "out is NULL");
+  *out = nullptr;
+  const int st = validate_batch(problems, count);
+  if (st != MSD_OK) return st;
+  if (!d_ws) return fail(MSD_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(MSD_EINVAL, "workspace must be 256-byte aligned");
+  const BatchLayout L = batch_layout(problems, count);
+  if (ws_bytes < L.total) return fail(MSD_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  msd_batch* b = new (std::nothrow) msd_batch();
+  if (!b) return fail(MSD_EINVAL, "host allocation failed");
+  b->count = count;
+  b->lattice = problems[0].lattice;
+  b->prec = problems[0].precision;
+  b->q = lattice_q(b->lattice);
+  b->d = lattice_d(b->lattice);
+  b->L = L;
+  b->ws = static_cast<char*>(d_ws);
+  b->stream = static_cast<hipStream_t>(stream);
+  b->mem.resize(count);
+  b->h_desc.resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    Member& M = b->mem[i];
+    M.prob = problems[i];
+    M.prob.D = nullptr;
+    M.prob.xi_wall = nullptr;
+    M.prob.xi_ref = nullptr;
+    M.m = problems[i].n_species - 1;
+    M.nodes = problems[i].nx * problems[i].ny * problems[i].nz;
+    M.plane = L.plane[i];
+    M.consts_off = L.consts_off[i];
+    M.half_off[0] = L.half_off0[i];
+    M.half_off[1] = L.half_off1[i];
+    M.state_bytes = L.state_bytes[i];
+    M.diag_blocks = (int)std::min<int64_t>(kDiagBlocksMax, (M.nodes + 255) / 256);
+    fill_kernel_problem(&problems[i], M.plane, &M.kp);
+    default_launch(&problems[i], &M.single);
+    M.single.lds_resident = 0;
+    msd::BatchInst& D = b->h_desc[i];
+    std::memset(&D, 0, sizeof(D));
+    D.p = M.kp;
+    D.m = M.m;
+    D.half_off[0] = M.half_off[0];
+    D.half_off[1] = M.half_off[1];
+    D.consts_off = M.consts_off;
+  }
+  hipError_t e = hipMemcpyAsync(b->ws + L.desc_off, b->h_desc.data(), sizeof(msd::BatchInst) * count,
+                                hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch table upload");
+  }
+  b->sched.block_x = 64;
+  b->sched.block_y = 4;
+  b->sched.mode = MSD_BATCH_FUSED;
+  b->sched.order = MSD_ORDER_INSTANCE;
+  b->sched.xcd_remap = 0;
+  b->sched.nontemporal = 0;
+  const int s2 = build_tiles(b);
+  if (s2 != MSD_OK) {
+    delete b;
+    return s2;
+  }
+  *out = b;
+  return MSD_OK;
+}
+
+int msd_batch_set_schedule(msd_batch* b, const msd_schedule* sc) {
+  if (!b || !sc) return fail(MSD_EINVAL, "NULL argument");
+  if (sc->block_x < 64 || sc->block_x % 64 || sc->block_y < 1 || sc->block_x * sc->block_y > 256)
+    return fail(MSD_EINVAL, "block %d x %d", sc->block_x, sc->block_y);
+  if (sc->mode != MSD_BATCH_FUSED && sc->mode != MSD_BATCH_PER_CLASS) return fail(MSD_EINVAL, "mode %d", sc->mode);
+  if (sc->order != MSD_ORDER_INSTANCE && sc->order != MSD_ORDER_INTERLEAVED)
+    return fail(MSD_EINVAL, "order %d", sc->order);
+  if (sc->nontemporal < 0 || sc->nontemporal > 7) return fail(MSD_EINVAL, "nontemporal %d", sc->nontemporal);
+  b->sched = *sc;
+  return build_tiles(b);
+}
+
+int msd_batch_get_schedule(const msd_batch* b, msd_schedule* sc) {
+  if (!b || !sc) return fail(MSD_EINVAL, "NULL argument");
+  *sc = b->sched;
+  return MSD_OK;
+}
+
+int64_t msd_batch_tiles(const msd_batch* b) { return b ? (int64_t)b->h_tiles.size() : -1; }
+
+int64_t msd_batch_time(const msd_batch* b) { return b ? b->t : -1; }
+
+int msd_batch_init(msd_batch* b, int32_t index, const void* d_xi0, int32_t xi0_precision) {
+  const int st = check_index(b, index);
+  if (st != MSD_OK) return st;
+  if (!d_xi0) return fail(MSD_EINVAL, "xi0 is NULL");
+  if (xi0_precision != MSD_F32 && xi0_precision != MSD_F64) return fail(MSD_EINVAL, "xi0_precision %d", xi0_precision);
+  if (b->t != 0) return fail(MSD_ESTATE, "batch mixtures are initialised at time 0 only");
+  b->cur = 0;
+  msd::LaunchArgs a = member_args(b, index);
+  a.consts_out = b->ws + b->mem[index].consts_off;
+  hipError_t e = dispatch(msd::Op::Constants, a);
+  if (e != hipSuccess) return hip_fail(e, "constants kernel");
+  a.xi0 = d_xi0;
+  a.in_prec = xi0_precision;
+  a.dst = b->ws + b->mem[index].half_off[0];
+  e = dispatch(msd::Op::Init, a);
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  b->mem[index].initialised = true;
+  return MSD_OK;
+}
+
+static int all_initialised(const msd_batch* b) {
+  for (int i = 0; i < b->count; ++i)
+    if (!b->mem[i].initialised) return fail(MSD_ESTATE, "mixture %d not initialised", i);
+  return MSD_OK;
+}
+
+int msd_batch_step(msd_batch* b, int64_t nsteps) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  const int st = all_initialised(b);
+  if (st != MSD_OK) return st;
+  msd::LaunchArgs a;
+  a.lattice = b->lattice;
+  a.prec = b->prec;
+  a.stream = b->stream;
+  a.insts = reinterpret_cast<const msd::BatchInst*>(b->ws + b->L.desc_off);
+  a.tiles = reinterpret_cast<const msd::BatchTile*>(b->ws + b->L.tiles_off);
+  a.ws = b->ws;
+  a.block_x = b->sched.block_x;
+  a.block_y = b->sched.block_y;
+  a.xcd_remap = b->sched.xcd_remap;
+  a.nontemporal = b->sched.nontemporal;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    a.cur = b->cur;
+    a.pull = b->t > 0 ? 1 : 0;
+    for (const Range& r : b->ranges) {
+      a.m = r.mmax;
+      a.tile_begin = r.begin;
+      a.ntiles = r.count;
+      const hipError_t e = dispatch(msd::Op::BatchStep, a);
+      if (e != hipSuccess) return hip_fail(e, "batched step kernel");
+    }
+    b->cur = 1 - b->cur;
+    b->t += 1;
+  }
+  return MSD_OK;
+}
+
+int msd_batch_step_each(msd_batch* b, int64_t nsteps) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  const int st = all_initialised(b);
+  if (st != MSD_OK) return st;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int i = 0; i < b->count; ++i) {
+      msd::LaunchArgs a = member_args(b, i);
+      a.src = b->ws + b->mem[i].half_off[b->cur];
+      a.dst = b->ws + b->mem[i].half_off[1 - b->cur];
+      a.pull = b->t > 0 ? 1 : 0;
+      const hipError_t e = dispatch(msd::Op::Step, a);
+      if (e != hipSuccess) return hip_fail(e, "step kernel");
+    }
+    b->cur = 1 - b->cur;
+    b->t += 1;
+  }
+  return MSD_OK;
+}
+
+int msd_batch_read_moments(msd_batch* b, int32_t index, int32_t out_precision, void* d_xi, void* d_J, void* d_grad) {
+  const int st = check_index(b, index);
+  if (st != MSD_OK) return st;
+  if (!d_xi) return fail(MSD_EINVAL, "xi is NULL");
+  if (!b->mem[index].initialised) return fail(MSD_ESTATE, "mixture %d not initialised", index);
+  if (out_precision != MSD_F32 && out_precision != MSD_F64) return fail(MSD_EINVAL, "out_precision %d", out_precision);
+  msd::LaunchArgs a = member_args(b, index);
+  a.src = b->ws + b->mem[index].half_off[b->cur];
+  a.pull = b->t > 0 ? 1 : 0;
+  a.out_prec = out_precision;
+  a.out_xi = d_xi;
+  a.out_J = d_J;
+  a.out_grad = d_grad;
+  const hipError_t e = dispatch(msd::Op::Read, a);
+  if (e != hipSuccess) return hip_fail(e, "read kernel");
+  return MSD_OK;
+}
+
+int msd_batch_diagnostics(msd_batch* b, int32_t index, double* h_mass, double* h_min, double* h_max,
+                          int64_t* h_nonfinite) {
+  const int st = check_index(b, index);
+  if (st != MSD_OK) return st;
+  if (!b->mem[index].initialised) return fail(MSD_ESTATE, "mixture %d not initialised", index);
+  msd::LaunchArgs a = member_args(b, index);
+  a.src = b->ws + b->mem[index].half_off[b->cur];
+  a.pull = b->t > 0 ? 1 : 0;
+  a.partials = reinterpret_cast<double*>(b->ws + b->L.partials_off);
+  a.diag_out = reinterpret_cast<double*>(b->ws + b->L.diag_out_off);
+  a.diag_blocks = b->mem[index].diag_blocks;
+  hipError_t e = dispatch(msd::Op::DiagPartial, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics kernel");
+  e = dispatch(msd::Op::DiagFinal, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics reduction kernel");
+  const int N = b->mem[index].m + 1;
+  double host[3 * MSD_MAX_SPECIES + 1];
+  e = hipMemcpyAsync(host, a.diag_out, sizeof(double) * (3 * N + 1), hipMemcpyDeviceToHost, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
+  e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics synchronise");
+  for (int i = 0; i < N; ++i) {
+    if (h_mass) h_mass[i] = host[i];
+    if (h_min) h_min[i] = host[N + i];
+    if (h_max) h_max[i] = host[2 * N + i];
+  }
+  const int64_t bad = (int64_t)host[3 * N];
+  if (h_nonfinite) *h_nonfinite = bad;
+  if (bad) return fail(MSD_EDIVERGED, "%lld non-finite mole fractions", (long long)bad);
+  return MSD_OK;
+}
+
+size_t msd_batch_state_bytes(const msd_batch* b) {
+  if (!b) return 0;
+  size_t s = 0;
+  for (const Member& M : b->mem) s += M.state_bytes;
+  return s;
+}
+
+int msd_batch_save(const msd_batch* b, void* d_dst, int64_t* h_step) {
+  if (!b || !d_dst) return fail(MSD_EINVAL, "NULL argument");
+  char* dst = static_cast<char*>(d_dst);
+  for (const Member& M : b->mem) {
+    const hipError_t e =
+        hipMemcpyAsync(dst, b->ws + M.half_off[b->cur], M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch save copy");
+    dst += M.state_bytes;
+  }
+  if (h_step) *h_step = b->t;
+  return MSD_OK;
+}
+
+int msd_batch_restore(msd_batch* b, const void* d_src, int64_t step) {
+  if (!b || !d_src) return fail(MSD_EINVAL, "NULL argument");
+  if (step < 0) return fail(MSD_EINVAL, "step < 0");
+  const int st = all_initialised(b);
+  if (st != MSD_OK) return st;
+  const char* src = static_cast<const char*>(d_src);
+  for (const Member& M : b->mem) {
+    const hipError_t e =
+        hipMemcpyAsync(b->ws + M.half_off[b->cur], src, M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch restore copy");
+    src += M.state_bytes;
+  }
+  b->t = step;
+  return MSD_OK;
+}
+
+int msd_batch_destroy(msd_batch* b) {
+  if (b) (void)hipStreamSynchronize(b->stream);
+  delete b;
+  return MSD_OK;
+}
+
+}  // extern "C"

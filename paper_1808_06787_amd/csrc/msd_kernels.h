@@ -523,6 +523,76 @@ __global__ void k_diag_final(const double* __restrict__ partials, int blocks, in
 }
 
 // ---------------------------------------------------------------------------
+// Batched sweep: one launch advances every tile of every mixture of a batch by
+// one step.  Workgroup b reads its (mixture, tile) from the tile table and
+// runs the same per-node body as k_step with that mixture's problem, buffers
+// and constants; the number of evolved species (uniform per workgroup) selects
+// the template instance, up to MMAX.
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void batch_tile_body(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
+                                                const Consts<T>* __restrict__ cst, uint32_t tile, int pull,
+                                                int nontemporal) {
+  constexpr int Q = Lattice<LAT>::Q;
+  const uint32_t tiles_x = ((uint32_t)p.nx + blockDim.x - 1) / blockDim.x;
+  const uint32_t tiles_y = ((uint32_t)p.ny + blockDim.y - 1) / blockDim.y;
+  const uint32_t tx = tile % tiles_x;
+  const uint32_t rest = tile / tiles_x;
+  const uint32_t ty = rest % tiles_y;
+  const uint32_t tz = rest / tiles_y;
+  NodePos n;
+  n.c[0] = (int32_t)(tx * blockDim.x + threadIdx.x);
+  n.c[1] = (int32_t)(ty * blockDim.y + threadIdx.y);
+  n.c[2] = (int32_t)tz;
+  if (n.c[0] >= p.nx || n.c[1] >= p.ny) return;
+  n.idx = n.c[0] + (int64_t)p.nx * (n.c[1] + (int64_t)p.ny * n.c[2]);
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  T f[M][Q];
+  gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
+  collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      store_value(dst + (int64_t)(i * Q + k) * p.plane + n.idx, f[i][k], nontemporal & NT_STORE);
+}
+
+template <int LAT, int MMAX, typename T>
+__global__ __launch_bounds__(256) void k_batch_step(const BatchInst* __restrict__ insts,
+                                                    const BatchTile* __restrict__ tiles, uint32_t tile_begin,
+                                                    uint32_t ntiles, char* __restrict__ ws, int cur, int pull,
+                                                    int remap, int nontemporal) {
+  Tiling tl;
+  tl.tiles = ntiles;
+  tl.remap = (uint32_t)remap;
+  const uint32_t L = logical_tile(tl);
+  const BatchTile bt = tiles[tile_begin + L];
+  const BatchInst* I = insts + bt.inst;
+  const int m = I->m;
+  const T* src = reinterpret_cast<const T*>(ws + I->half_off[cur]);
+  T* dst = reinterpret_cast<T*>(ws + I->half_off[1 - cur]);
+  const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + I->consts_off);
+  const Problem& p = I->p;
+#define MSD_BATCH_CASE(MM)                                                              \
+  case MM:                                                                              \
+    if constexpr (MM <= MMAX) batch_tile_body<LAT, MM, T>(p, src, dst, cst, bt.tile, pull, nontemporal); \
+    break;
+  switch (m) {
+    MSD_BATCH_CASE(1)
+    MSD_BATCH_CASE(2)
+    MSD_BATCH_CASE(3)
+    MSD_BATCH_CASE(4)
+    MSD_BATCH_CASE(5)
+    MSD_BATCH_CASE(6)
+    MSD_BATCH_CASE(7)
+    default:
+      break;
+  }
+#undef MSD_BATCH_CASE
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
 inline Tiling make_tiling(const LaunchArgs& a, int V = 1) {
@@ -611,6 +681,13 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::DiagFinal:
       hipLaunchKernelGGL(k_diag_final<LAT>, dim3(1), dim3(64), 0, a.stream, a.partials, a.diag_blocks, M + 1,
                          a.diag_out);
+      break;
+    case Op::BatchStep:
+      // here M is the largest number of evolved species in the launch
+      if (a.ntiles == 0) break;
+      hipLaunchKernelGGL((k_batch_step<LAT, M, T>), dim3(a.ntiles), dim3(a.block_x, a.block_y), 0, a.stream,
+                         a.insts, a.tiles, a.tile_begin, a.ntiles, a.ws, a.cur, a.pull, a.xcd_remap,
+                         a.nontemporal);
       break;
   }
   return hipGetLastError();

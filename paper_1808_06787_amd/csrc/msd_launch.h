@@ -8,7 +8,7 @@
 
 namespace msd {
 
-enum class Op { Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal };
+enum class Op { Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep };
 
 // Constants block written once per problem by the setup kernel and read by
 // every sweep kernel through uniform (scalar-cache) loads: R = 1/D (m rows of
@@ -22,6 +22,22 @@ struct Consts {
 };
 constexpr size_t kConstsBytes = 1024;   // >= sizeof(Consts<double>) = 960
 static_assert(sizeof(Consts<double>) <= kConstsBytes, "constants block too small");
+
+// One mixture of a batch, as the batched sweep sees it (device array, read
+// through uniform loads).  Offsets are bytes into the batch workspace.
+struct BatchInst {
+  Problem p;
+  int32_t m;
+  int32_t reserved;
+  uint64_t half_off[2];
+  uint64_t consts_off;
+};
+
+// One workgroup of a batched launch: which mixture, which tile of it.
+struct BatchTile {
+  uint32_t inst;
+  uint32_t tile;
+};
 
 struct LaunchArgs {
   Problem p;
@@ -51,6 +67,12 @@ struct LaunchArgs {
   double* diag_out = nullptr;
   int diag_blocks = 0;
   int n_species = 0;
+  // batched sweep
+  const BatchInst* insts = nullptr;
+  const BatchTile* tiles = nullptr;
+  uint32_t tile_begin = 0, ntiles = 0;
+  char* ws = nullptr;
+  int cur = 0;
 };
 
 // Largest domain (nodes) the single-workgroup LDS-resident sweep accepts for a

@@ -119,3 +119,24 @@ def test_create_rejects_small_or_misaligned_workspace_without_touching_it():
     assert not h.value
     assert F.lib().msd_step(None, 1) == -1
     assert F.lib().msd_strerror(-7) == b"workspace too small"
+
+
+def test_batch_validation_codes():
+    lib = F.lib()
+    D3 = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.3, 1.0]])
+    D2 = np.array([[1, 0.1], [0.1, 1.0]])
+    p0, k0 = make_problem("D2Q5", D3, (64, 64), "f32")
+    p1, k1 = make_problem("D2Q5", D2, (100, 7), "f32")
+    p2, k2 = make_problem("D3Q7", D2, (4, 4, 4), "f32")
+    p3, k3 = make_problem("D2Q5", D2, (8, 8), "f64")
+    arr = (F.MsdProblem * 2)(p0, p1)
+    st = C.c_int32(7)
+    n = lib.msd_batch_workspace_bytes(arr, 2, C.byref(st))
+    assert st.value == 0 and n > 2 * (64 * 64 * 10 * 4 + 704 * 5 * 4)
+    for other in (p2, p3):
+        bad = (F.MsdProblem * 2)(p0, other)
+        assert lib.msd_batch_workspace_bytes(bad, 2, C.byref(st)) == 0 and st.value == -1
+    assert lib.msd_batch_workspace_bytes(arr, 0, C.byref(st)) == 0 and st.value == -1
+    h = C.c_void_p()
+    assert lib.msd_batch_create(arr, 2, C.c_void_p(1 << 40), C.c_size_t(n - 1), None, C.byref(h)) == -7
+    assert lib.msd_batch_step(None, 1) == -1

@@ -1,0 +1,170 @@
+"""Batched sweep: every mixture of a heterogeneous batch matches the oracle, all
+schedules give identical fields, the one-launch-per-mixture reference schedule
+agrees, checkpoints and the autotuner leave the state intact, and the full
+256-mixture workload matches the oracle on sampled nodes."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import assert_parity, oracle_problem, oracle_run, rand_D, rand_field, smooth_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _specs(lattice, rng):
+    if lattice == "D2Q5":
+        shapes = [(64, 64), (97, 45), (128, 33), (65, 70), (1, 1), (130, 7)]
+        Ns = [2, 3, 4, 5, 3, 6]
+    else:
+        shapes = [(16, 8, 8), (9, 13, 5), (32, 4, 3), (5, 5, 5)]
+        Ns = [3, 4, 5, 2]
+    d = len(shapes[0])
+    specs = []
+    for b, (shape, N) in enumerate(zip(shapes, Ns)):
+        bc = None
+        walls = None
+        if b % 3 == 1:
+            bc = (("zero_flux", "zero_flux"),) + (("periodic", "periodic"),) * (d - 1)
+        elif b % 3 == 2:
+            bc = (("dirichlet", "zero_flux"),) + (("periodic", "periodic"),) * (d - 1)
+            walls = {(0, 0): rand_field(rng, N, ())}
+        specs.append(dict(D=rand_D(rng, N), shape=shape, bc=bc, xi_wall=walls,
+                          relax="srt" if b == 3 else "paper"))
+    fields = [smooth_field(rng, sp["D"].shape[0], sp["shape"][::-1], 0.1) for sp in specs]
+    return specs, fields
+
+
+def _batch(lattice, precision, specs, fields):
+    from paper_1808_06787_amd.batch import Batch
+
+    b = Batch(specs, lattice, precision)
+    for i, f in enumerate(fields):
+        b.init(i, torch.from_numpy(f))
+    return b
+
+
+def _read_all(b):
+    out = []
+    for i in range(b.count):
+        xi, J, g = b.read(i)
+        out.append((xi.cpu().numpy(), J.cpu().numpy(), g.cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("lattice", ["D2Q5", "D3Q7"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_matches_oracle_per_mixture(lattice, precision):
+    rng = np.random.default_rng(70)
+    specs, fields = _specs(lattice, rng)
+    b = _batch(lattice, precision, specs, fields)
+    b.step(25)
+    got = _read_all(b)
+    for i, (sp, f) in enumerate(zip(specs, fields)):
+        p = oracle_problem(lattice, sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"])
+        assert_parity(got[i], oracle_run(p, f, 25), precision, f"{lattice} mixture {i}")
+    b.close()
+
+
+def test_schedules_are_bitwise_identical_and_match_reference_schedule():
+    rng = np.random.default_rng(71)
+    specs, fields = _specs("D2Q5", rng)
+    ref_b = _batch("D2Q5", "f32", specs, fields)
+    ref_b.step(13)
+    ref = _read_all(ref_b)
+    ref_b.close()
+    for sched in (dict(block_x=256, block_y=1, mode="per_class", order="interleaved", xcd_remap=1),
+                  dict(block_x=64, block_y=1, mode="fused", order="interleaved", xcd_remap=0, nontemporal=7),
+                  dict(block_x=128, block_y=2, mode="per_class", order="instance", xcd_remap=1)):
+        b = _batch("D2Q5", "f32", specs, fields)
+        b.set_schedule(**sched)
+        b.step(13)
+        got = _read_all(b)
+        for g, r in zip(got, ref):
+            for x, y in zip(g, r):
+                np.testing.assert_array_equal(x, y, err_msg=str(sched))
+        b.close()
+    e = _batch("D2Q5", "f32", specs, fields)
+    e.step_each(13)
+    got = _read_all(e)
+    for g, r in zip(got, ref):
+        np.testing.assert_allclose(g[0], r[0], rtol=0, atol=2e-6)
+    e.close()
+
+
+def test_batch_checkpoint_and_autotuner_keep_the_state(tmp_path):
+    from paper_1808_06787_amd import autotune
+
+    rng = np.random.default_rng(72)
+    specs, fields = _specs("D2Q5", rng)
+    a = _batch("D2Q5", "f64", specs, fields)
+    a.step(20)
+    ref = _read_all(a)
+    a.close()
+    b = _batch("D2Q5", "f64", specs, fields)
+    b.step(8)
+    res = autotune.tune_batch(b, cache_path=str(tmp_path / "tune.json"), steps=2, warmup=1)
+    assert b.time == 8 and "best" in res and len(res["trials"]) > 10
+    state, t = b.save()
+    b.step(3)
+    b.restore(state, t)
+    b.step(12)
+    for g, r in zip(_read_all(b), ref):
+        for x, y in zip(g, r):
+            np.testing.assert_array_equal(x, y)
+    # cached result is applied without re-timing
+    res2 = autotune.tune_batch(b, cache_path=str(tmp_path / "tune.json"))
+    assert res2["best"] == res["best"] and b.get_schedule()["block_x"] == res["best"]["block_x"]
+    b.close()
+
+
+def test_batch_state_rules():
+    from paper_1808_06787_amd._ffi import MsdError
+    from paper_1808_06787_amd.batch import Batch
+
+    rng = np.random.default_rng(73)
+    specs, fields = _specs("D2Q5", rng)
+    b = Batch(specs, "D2Q5", "f32")
+    b.init(0, torch.from_numpy(fields[0]))
+    with pytest.raises(MsdError) as e:
+        b.step(1)                   # mixture 1 not initialised
+    assert e.value.status == -9
+    for i in range(1, b.count):
+        b.init(i, torch.from_numpy(fields[i]))
+    b.step(1)
+    with pytest.raises(MsdError) as e:
+        b.init(0, torch.from_numpy(fields[0]))
+    assert e.value.status == -9
+    b.close()
+
+
+def test_batched_workload_sampled():
+    """The 256-mixture workload (N in {3,4,5}, sides 64..1024) after 3 fused steps:
+    sampled nodes of several mixtures against the oracle on their light cones."""
+    import workloads
+    from paper_1808_06787_amd.batch import Batch
+
+    ws = workloads.batched_2d()
+    specs = [dict(D=w.D, shape=w.shape, bc=w.bc) for w in ws]
+    b = Batch(specs, "D2Q5", "f32")
+    for i, w in enumerate(ws):
+        b.init(i, torch.from_numpy(w.xi0))
+    b.release_inputs()
+    steps = 3
+    b.step(steps)
+    rng = np.random.default_rng(74)
+    from oracle import lbm
+
+    for i in rng.choice(len(ws), 6, replace=False):
+        w = ws[i]
+        xi, J, _ = b.read(int(i), torch.float64, grad=False)
+        for _ in range(4):
+            x, y = (int(v) for v in rng.integers(0, w.shape[0], size=2))
+            h = steps + 1
+            idx = [np.arange(c - h, c + h + 1) % w.shape[0] for c in (x, y)]
+            sub = np.take(np.take(w.xi0, idx[1], axis=1), idx[0], axis=2)
+            p = lbm.Problem("D2Q5", w.D, (2 * h + 1, 2 * h + 1),
+                            bc=((lbm.ZERO_FLUX, lbm.ZERO_FLUX), (lbm.ZERO_FLUX, lbm.ZERO_FLUX)))
+            oxi, _, oJ = lbm.observables(p, lbm.run(p, sub, steps))
+            assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= 1e-5
+            assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= 2e-6
+    b.close()
