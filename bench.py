@@ -161,6 +161,89 @@ def batched_extra(steps: int = 1000, warmup: int = 5):
     }
 
 
+def adjoint_extra():
+    """Gradient workload: 1024^2 ternary D2Q5, 2000 steps, checkpoints every 100.
+    FP32: time of the plain forward run, of the checkpointed forward run and of the
+    backward pass (recompute + adjoint).  FP64: the adjoint gradients against central
+    differences (h = 1e-4) for the three D_ij pairs and one direction of the
+    initial field."""
+    import torch
+
+    import workloads
+    from paper_1808_06787_amd import adjoint
+    from paper_1808_06787_amd.sim import Sim
+
+    w = workloads.adjoint_2d()
+    every = w.meta["checkpoint_every"]
+    N = w.N
+
+    def run(D, prec, x0, steps):
+        s = Sim(w.lattice, D, w.shape, prec, bc=w.bc)
+        s.init(torch.from_numpy(x0))
+        s.step(steps)
+        return s
+
+    ts = run(w.meta["D_target"], "f64", w.xi0, w.steps)
+    target = ts.read(torch.float64, flux=False, grad=False)[0]
+    ts.close()
+
+    def events(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3, out
+
+    res = {"extents": list(w.shape), "steps": w.steps, "checkpoint_every": every}
+    for prec in ("f32", "f64"):
+        s = Sim(w.lattice, w.D, w.shape, prec, bc=w.bc)
+        s.init(torch.from_numpy(w.xi0))             # warm-up of every kernel used below
+        ck = adjoint.forward_with_checkpoints(s, 5, 2)
+        xi = s.read(torch.float64, flux=False, grad=False)[0]
+        adjoint.gradients(s, ck, 5, 2.0 * (xi - target), 2)
+        del ck
+        s.init(torch.from_numpy(w.xi0))
+        t_plain, _ = events(lambda: s.step(w.steps))
+        s.init(torch.from_numpy(w.xi0))
+        t_fwd, ck = events(lambda: adjoint.forward_with_checkpoints(s, w.steps, every))
+        xi = s.read(torch.float64, flux=False, grad=False)[0]
+        L = float(((xi - target) ** 2).sum())
+        t_bwd, (gx, gD) = events(lambda: adjoint.gradients(s, ck, w.steps, 2.0 * (xi - target), every))
+        s.close()
+        del ck
+        res[prec] = {"loss": L, "forward_s": round(t_plain, 4), "forward_checkpointed_s": round(t_fwd, 4),
+                     "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3)}
+        if prec == "f64":
+            h = 1e-4
+
+            def loss(D, x0):
+                s2 = run(D, "f64", x0, w.steps)
+                v = float(((s2.read(torch.float64, flux=False, grad=False)[0] - target) ** 2).sum())
+                s2.close()
+                return v
+
+            worst = 0.0
+            fd_pairs = {}
+            for i in range(N):
+                for j in range(i + 1, N):
+                    Dp, Dm = w.D.copy(), w.D.copy()
+                    Dp[i, j] = Dp[j, i] = w.D[i, j] + h
+                    Dm[i, j] = Dm[j, i] = w.D[i, j] - h
+                    fd = (loss(Dp, w.xi0) - loss(Dm, w.xi0)) / (2 * h)
+                    fd_pairs[f"D{i + 1}{j + 1}"] = [fd, float(gD[i, j])]
+                    worst = max(worst, abs(fd - gD[i, j]) / abs(fd))
+            v = w.meta["direction"]
+            fd = (loss(w.D, w.xi0 + h * v) - loss(w.D, w.xi0 - h * v)) / (2 * h)
+            ad = float((gx.cpu().numpy() * v[: N - 1]).sum())
+            worst = max(worst, abs(fd - ad) / abs(fd))
+            res["fd_check_f64"] = {"h": h, "pairs_fd_vs_adjoint": fd_pairs, "direction_fd_vs_adjoint": [fd, ad],
+                                   "max_relative_difference": worst}
+    return res
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle (unchanged) on a bounded sub-grid of the workload, single thread."""
     try:
@@ -296,6 +379,10 @@ def main():
         print(f"# {w1.name}: {m1:.1f} MLUPS, {w1.steps / s1:.0f} steps/s", file=sys.stderr, flush=True)
         bx = batched_extra()
         extras["batched_256_mixtures_d2q5_f32"] = bx
+        ax = adjoint_extra()
+        extras["adjoint_1024x1024_d2q5_ternary"] = ax
+        print(f"# adjoint f32: backward/forward = {ax['f32']['backward_over_forward']:.2f}; FD check (f64) "
+              f"max rel diff {ax['fd_check_f64']['max_relative_difference']:.2e}", file=sys.stderr, flush=True)
         print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS fused vs {bx['MLUPS_one_launch_per_mixture']:.0f} "
               f"one launch per mixture ({bx['speedup_vs_one_launch_per_mixture']:.2f}x)", file=sys.stderr, flush=True)
     if extras:

@@ -162,6 +162,62 @@ MSD_API int msd_restore(msd_sim* sim, const void* d_src, int64_t step);
 MSD_API int msd_destroy(msd_sim* sim);
 
 /* ---------------------------------------------------------------------------
+ * Reverse mode (adjoint) of the sweep
+ *
+ * For a scalar loss L of the mole fractions at time T, these calls give
+ * dL/dxi(0) (the evolved species' initial fields) and dL/dD_ij.  The forward
+ * step t reads the buffer state s_{t-1} (the state after step t-1; s_0 is the
+ * initial f(0)) and writes s_t; the pre-collision distributions at time t are
+ * f^t = P(s_t) (P the propagation with the face rules of Sec. 4; f^0 = s_0).
+ * Adjoint buffers hold a_t = dL/df^t at each node, in the layout and precision
+ * of a state (msd_state_bytes).  The adjoint of step t maps a_t to a_{t-1}: it
+ * reads a_t through the transposed propagation, recomputes f^{t-1} from
+ * s_{t-1}, and applies the transposed collision Jacobian (through B of
+ * Eq. (2-10), the local solve, Eq. (3-26) and Eq. (3-16)).  A driver
+ * checkpoints states during the forward run (msd_save), recomputes segments
+ * with msd_record and walks the adjoint steps backwards.
+ * ------------------------------------------------------------------------- */
+
+/* Advance nsteps from the current state and also store the state after each
+ * step in consecutive slots of msd_state_bytes bytes at d_stack (slot s holds
+ * the state after step time+s+1). */
+MSD_API int msd_record(msd_sim* sim, int64_t nsteps, void* d_stack);
+
+/* Bytes of the FP64 accumulator of dL/dD (one slot per workgroup of the
+ * current launch configuration, which must stay unchanged through one adjoint
+ * pass), and its reset (a fill kernel). */
+MSD_API size_t msd_adjoint_accum_bytes(const msd_sim* sim);
+MSD_API int msd_adjoint_begin(msd_sim* sim, void* d_accum);
+
+/* a_T from dL/dxi at the current time T: d_dL_dxi holds N FP64 planes (the
+ * derivative with respect to every species' mole fraction, the last one
+ * included; xi_i = sum_k f_k^i (Eq. (3-15)), xi_N = 1 - sum of the others,
+ * Eq. (2-3b)). */
+MSD_API int msd_adjoint_seed(msd_sim* sim, const double* d_dL_dxi, void* d_adj_out);
+
+/* One adjoint step for forward step t >= 1: d_state_prev is s_{t-1}, d_adj_in
+ * is a_t, d_adj_out receives a_{t-1} (must not alias d_adj_in); dL/dD terms are
+ * added into d_accum. */
+MSD_API int msd_adjoint_step(msd_sim* sim, int64_t t, const void* d_state_prev, const void* d_adj_in,
+                             void* d_adj_out, void* d_accum);
+
+/* The adjoint steps t = t_hi, t_hi - 1, ..., t_lo + 1 of one recomputed
+ * segment in one call: the state read by step t is d_state_lo (s_{t_lo}) for
+ * t = t_lo + 1 and slot t - t_lo - 2 of d_stack (as written by msd_record from
+ * time t_lo) otherwise.  a_{t_hi} is read from d_adj_a; the two adjoint buffers
+ * alternate and *h_result_in_b reports where a_{t_lo} ends (0: d_adj_a,
+ * 1: d_adj_b). */
+MSD_API int msd_adjoint_steps(msd_sim* sim, int64_t t_hi, int64_t t_lo, const void* d_state_lo, const void* d_stack,
+                              void* d_adj_a, void* d_adj_b, void* d_accum, int32_t* h_result_in_b);
+
+/* From a_0 and the accumulator: dL/dxi(0) (N-1 FP64 planes, or NULL) and the
+ * N x N matrix dL/dD (host, row-major, or NULL; entry (i, j) = (j, i) is the
+ * derivative with respect to the symmetric pair D_ij = D_ji, diagonal 0).
+ * Synchronises the stream. */
+MSD_API int msd_adjoint_finish(msd_sim* sim, const void* d_adj0, const void* d_accum, double* d_dL_dxi0,
+                               double* h_dL_dD);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning of the single-mixture sweep
  * ------------------------------------------------------------------------- */
 

@@ -115,6 +115,13 @@ def lib():
         "msd_save": (C.c_int, [vp, vp, P(i64)]),
         "msd_restore": (C.c_int, [vp, vp, i64]),
         "msd_destroy": (C.c_int, [vp]),
+        "msd_record": (C.c_int, [vp, i64, vp]),
+        "msd_adjoint_accum_bytes": (sz, [vp]),
+        "msd_adjoint_begin": (C.c_int, [vp, vp]),
+        "msd_adjoint_seed": (C.c_int, [vp, vp, vp]),
+        "msd_adjoint_step": (C.c_int, [vp, i64, vp, vp, vp, vp]),
+        "msd_adjoint_finish": (C.c_int, [vp, vp, vp, vp, P(C.c_double)]),
+        "msd_adjoint_steps": (C.c_int, [vp, i64, i64, vp, vp, vp, vp, vp, P(i32)]),
         "msd_batch_workspace_bytes": (sz, [P(MsdProblem), i32, P(i32)]),
         "msd_batch_create": (C.c_int, [P(MsdProblem), i32, vp, sz, vp, P(vp)]),
         "msd_batch_init": (C.c_int, [vp, i32, vp, i32]),

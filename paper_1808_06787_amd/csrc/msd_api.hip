@@ -143,7 +143,8 @@ Layout layout_for(const msd_problem* p) {
   L.partials_off = off;
   off = align_up(off + sizeof(double) * (size_t)L.diag_blocks * (3 * p->n_species + 1), 256);
   L.diag_out_off = off;
-  off = align_up(off + sizeof(double) * (3 * MSD_MAX_SPECIES + 1), 256);
+  // diagnostics use 3N + 1 values, the adjoint's dL/dD N * N
+  off = align_up(off + sizeof(double) * (MSD_MAX_SPECIES * MSD_MAX_SPECIES + 3 * MSD_MAX_SPECIES + 1), 256);
   L.half_bytes = align_up((size_t)m * q * (size_t)L.plane * s, 256);
   L.half_off[0] = off;
   off += L.half_bytes;
@@ -422,6 +423,127 @@ int msd_restore(msd_sim* s, const void* d_src, int64_t step) {
                                       hipMemcpyDeviceToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(e, "restore copy");
   s->t = step;
+  return MSD_OK;
+}
+
+int msd_record(msd_sim* s, int64_t nsteps, void* d_stack) {
+  if (!s || !d_stack) return fail(MSD_EINVAL, "NULL argument");
+  if (!s->initialised) return fail(MSD_ESTATE, "msd_record before msd_init");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return MSD_OK;
+  const size_t sb = msd_state_bytes(s);
+  char* stack = static_cast<char*>(d_stack);
+  msd::LaunchArgs a = base_args(s);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    a.src = n == 0 ? (const void*)(s->ws + s->L.half_off[s->cur]) : (const void*)(stack + (size_t)(n - 1) * sb);
+    a.dst = stack + (size_t)n * sb;
+    a.pull = (s->t + n) > 0 ? 1 : 0;
+    const hipError_t e = dispatch(msd::Op::Step, a);
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+  }
+  const hipError_t e = hipMemcpyAsync(s->ws + s->L.half_off[s->cur], stack + (size_t)(nsteps - 1) * sb, sb,
+                                      hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "record copy");
+  s->t += nsteps;
+  return MSD_OK;
+}
+
+size_t msd_adjoint_accum_bytes(const msd_sim* s) {
+  if (!s) return 0;
+  const int64_t bx = (int64_t)s->launch.block_x * msd::kAdjointNodesPerThread, by = s->launch.block_y;
+  const int64_t tiles = (s->prob.nx + bx - 1) / bx * ((s->prob.ny + by - 1) / by) * s->prob.nz;
+  return sizeof(double) * (size_t)tiles * s->m * (s->m + 1);
+}
+
+int msd_adjoint_begin(msd_sim* s, void* d_accum) {
+  if (!s || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  msd::LaunchArgs a = base_args(s);
+  a.partials = static_cast<double*>(d_accum);
+  a.fill_count = (int64_t)(msd_adjoint_accum_bytes(s) / sizeof(double));
+  const hipError_t e = dispatch(msd::Op::FillZero, a);
+  if (e != hipSuccess) return hip_fail(e, "fill kernel");
+  return MSD_OK;
+}
+
+int msd_adjoint_seed(msd_sim* s, const double* d_dL_dxi, void* d_adj_out) {
+  if (!s || !d_dL_dxi || !d_adj_out) return fail(MSD_EINVAL, "NULL argument");
+  if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
+  msd::LaunchArgs a = base_args(s);
+  a.xi0 = d_dL_dxi;
+  a.dst = d_adj_out;
+  a.pull = s->t > 0 ? 1 : 0;
+  const hipError_t e = dispatch(msd::Op::AdjointSeed, a);
+  if (e != hipSuccess) return hip_fail(e, "adjoint seed kernel");
+  return MSD_OK;
+}
+
+int msd_adjoint_step(msd_sim* s, int64_t t, const void* d_state_prev, const void* d_adj_in, void* d_adj_out,
+                     void* d_accum) {
+  if (!s || !d_state_prev || !d_adj_in || !d_adj_out || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
+  if (t < 1) return fail(MSD_EINVAL, "adjoint step t = %lld < 1", (long long)t);
+  if (d_adj_in == d_adj_out) return fail(MSD_EINVAL, "adjoint input and output must differ");
+  msd::LaunchArgs a = base_args(s);
+  a.src = d_state_prev;
+  a.adj_in = d_adj_in;
+  a.dst = d_adj_out;
+  a.pull = t >= 2 ? 1 : 0;   // s_{t-1} holds pre-collision values only for t = 1
+  a.partials = static_cast<double*>(d_accum);
+  const hipError_t e = dispatch(msd::Op::AdjointStep, a);
+  if (e != hipSuccess) return hip_fail(e, "adjoint step kernel");
+  return MSD_OK;
+}
+
+int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_state_lo, const void* d_stack,
+                      void* d_adj_a, void* d_adj_b, void* d_accum, int32_t* h_result_in_b) {
+  if (!s || !d_state_lo || !d_adj_a || !d_adj_b || !d_accum || !h_result_in_b)
+    return fail(MSD_EINVAL, "NULL argument");
+  if (t_lo < 0 || t_hi < t_lo) return fail(MSD_EINVAL, "steps (%lld, %lld]", (long long)t_lo, (long long)t_hi);
+  if (t_hi - t_lo > 1 && !d_stack) return fail(MSD_EINVAL, "stack is NULL");
+  const size_t sb = msd_state_bytes(s);
+  void* a = d_adj_a;
+  void* b = d_adj_b;
+  int in_b = 0;
+  for (int64_t t = t_hi; t > t_lo; --t) {
+    const void* prev = (t - 1 == t_lo) ? d_state_lo
+                                       : (const void*)(static_cast<const char*>(d_stack) + (size_t)(t - t_lo - 2) * sb);
+    const int st = msd_adjoint_step(s, t, prev, a, b, d_accum);
+    if (st != MSD_OK) return st;
+    void* tmp = a;
+    a = b;
+    b = tmp;
+    in_b ^= 1;
+  }
+  *h_result_in_b = in_b;
+  return MSD_OK;
+}
+
+int msd_adjoint_finish(msd_sim* s, const void* d_adj0, const void* d_accum, double* d_dL_dxi0, double* h_dL_dD) {
+  if (!s || !d_adj0 || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  msd::LaunchArgs a = base_args(s);
+  a.adj_in = d_adj0;
+  hipError_t e;
+  if (d_dL_dxi0) {
+    a.out_xi = d_dL_dxi0;
+    e = dispatch(msd::Op::AdjointXi0, a);
+    if (e != hipSuccess) return hip_fail(e, "adjoint initial-field kernel");
+  }
+  if (h_dL_dD) {
+    a.partials = static_cast<double*>(const_cast<void*>(d_accum));
+    a.diag_out = reinterpret_cast<double*>(s->ws + s->L.diag_out_off);
+    e = dispatch(msd::Op::AdjointDD, a);
+    if (e != hipSuccess) return hip_fail(e, "adjoint diffusivity kernel");
+    const int N = s->prob.n_species;
+    double host[MSD_MAX_SPECIES * MSD_MAX_SPECIES];
+    e = hipMemcpyAsync(host, a.diag_out, sizeof(double) * N * N, hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint synchronise");
+    for (int i = 0; i < N * N; ++i) h_dL_dD[i] = host[i];
+  } else {
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint synchronise");
+  }
   return MSD_OK;
 }
 

@@ -319,4 +319,262 @@ __device__ __forceinline__ void gather_node(const Problem& p, const T* src, cons
   for (int k = 0; k < Q; ++k) pull_direction<LAT, M, T>(p, src, n, k, f, wall, nt);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint building blocks.
+// ---------------------------------------------------------------------------
+
+// Transpose of the propagation, read as a gather.  The forward pull delivers
+// g_k(y) to exactly one pre-collision value: f_k(y + c_k) inside the domain
+// (wrapping at periodic faces), or, where y + c_k lies beyond a wall face,
+// f_kbar(y) by bounce-back (+1) or anti-bounce-back (-1).  So, with fbar the
+// adjoint of the pre-collision values, gbar_k(y) = fbar_k(y + c_k) or
+// +-fbar_kbar(y) at such a face.
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void pull_direction_transposed(const Problem& p, const T* src, const NodePos& n, int k,
+                                                          T (&out)[M][Lattice<LAT>::Q]) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const int a = L::axis(k);
+  if (a < 0) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+    return;
+  }
+  const int s = L::sgn(k);
+  const int32_t ext = extent(p, a);
+  const int64_t st = axis_stride<LAT>(p, a);
+  // the face that direction k leaves the domain through
+  const bool edge = (s > 0) ? (n.c[a] == ext - 1) : (n.c[a] == 0);
+  const int face = 2 * a + (s > 0 ? 1 : 0);
+  const int kind = edge ? p.bc[face] : BC_PERIODIC;
+  if (kind == BC_PERIODIC) {
+    const int64_t off = edge ? n.idx - (int64_t)s * (ext - 1) * st : n.idx + (int64_t)s * st;
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+  } else {
+    const int kb = L::opp(k);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T v = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
+      out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+    }
+  }
+}
+
+// Plane accessor: plane pl of a buffer at base + pl * plane.  With A32 the
+// per-lane part of the address is a 32-bit byte offset from the (uniform)
+// plane start, which needs plane * sizeof(T) < 2^32.
+template <typename T, bool A32>
+struct Planes {
+  const T* base;
+  int64_t plane;
+  __device__ __forceinline__ T operator()(int pl, int64_t idx) const {
+    if constexpr (A32) {
+      const char* b = reinterpret_cast<const char*>(base + (int64_t)pl * plane);
+      return *reinterpret_cast<const T*>(b + (uint32_t)idx * (uint32_t)sizeof(T));
+    } else {
+      return base[(int64_t)pl * plane + idx];
+    }
+  }
+};
+
+// pull_direction / pull_direction_transposed over a plane accessor.
+template <int LAT, int M, typename T, bool A32>
+__device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>& src, const NodePos& n, int k,
+                                         T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M], bool transposed) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const int a = L::axis(k);
+  if (a < 0) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, n.idx);
+    return;
+  }
+  const int s = transposed ? -L::sgn(k) : L::sgn(k);   // read from x - s c
+  const int32_t ext = extent(p, a);
+  const int64_t st = axis_stride<LAT>(p, a);
+  const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
+  const int face = 2 * a + (s > 0 ? 0 : 1);
+  const int kind = edge ? p.bc[face] : BC_PERIODIC;
+  const int kb = L::opp(k);
+  if (kind == BC_PERIODIC) {
+    const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+#pragma unroll
+    for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, off);
+  } else if (!transposed) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T back = src(i * Q + kb, n.idx);
+      out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T v = src(i * Q + kb, n.idx);
+      out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+    }
+  }
+}
+
+// Reverse-mode derivative of collide_node.  Given the pre-collision f of one
+// node and u = dL/df^+, returns fbar = dL/df and adds dL/dR (R = 1/D, entry
+// [i][j] for i < m, j <= m) into Rbar.  The forward quantities are recomputed
+// exactly as collide_node computes them:
+//   g = f - Lambda_1 neq - diag(delta) even,  Lambda_1 = 2 (I - K),
+//   K = (I + h B)^-1,  delta_i = phi(Lambda_1_ii) - Lambda_1_ii,  phi(l) = 8 (l - 2)/(l - 8).
+template <int LAT, int M, typename T>
+__device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT>::Q], const T (&u)[M][Lattice<LAT>::Q],
+                                                     const T (&R)[M][M + 1], const T (&xref)[M], bool linearized,
+                                                     bool srt, T (&fbar)[M][Lattice<LAT>::Q],
+                                                     double (&Rbar)[M][M + 1]) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const T h = T(0.5 * L::cs2);
+  T xi[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = f[i][0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) s += f[i][k];
+    xi[i] = s;
+  }
+  T xb[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) xb[i] = linearized ? xref[i] : xi[i];
+  T K[M][M];
+  ms_inverse<M, T>(xb, R, h, K);
+  T L1[M][M], delta[M], dphi[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) L1[i][j] = (i == j ? T(2) : T(0)) - T(2) * K[i][j];
+    const T l = L1[i][i];
+    delta[i] = srt ? T(0) : (T(8) * (l - T(2)) / (l - T(8)) - l);
+    dphi[i] = srt ? T(0) : (T(-48) / ((l - T(8)) * (l - T(8))) - T(1));   // d delta / d lambda
+  }
+  T neq[M][Q], ev[M][Q];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      neq[i][k] = f[i][k] - T(L::w(k)) * xi[i];
+      s += neq[i][k];
+    }
+    neq[i][0] = -s;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int kb = L::opp(k);
+      ev[i][k] = (k == kb) ? neq[i][k] : T(0.5) * (neq[i][k] + neq[i][kb]);
+    }
+
+  // g_ik = f_ik - sum_j L1_ij neq_jk - delta_i ev_ik
+  T nbar[M][Q], L1bar[M][M], dbar[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T d = T(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) d -= u[i][k] * ev[i][k];
+    dbar[i] = d;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc -= u[i][k] * neq[j][k];
+      L1bar[i][j] = acc;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) acc -= L1[i][j] * u[i][k];
+      nbar[j][k] = acc;
+    }
+  // even part: ev_ik = (neq_ik + neq_ikbar)/2 (k != 0), ev_i0 = neq_i0; evbar = -delta u
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int kb = L::opp(k);
+      const T e_k = -delta[i] * u[i][k];
+      if (k == kb) {
+        nbar[i][k] += e_k;
+      } else {
+        const T e_kb = -delta[i] * u[i][kb];
+        nbar[i][k] += T(0.5) * (e_k + e_kb);
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < M; ++i) L1bar[i][i] += dbar[i] * dphi[i];
+
+  // neq_ik = f_ik - w_k xi_i
+  T xibar[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      fbar[i][k] = u[i][k] + nbar[i][k];
+      s -= T(L::w(k)) * nbar[i][k];
+    }
+    xibar[i] = s;
+  }
+
+  // Lambda_1 = 2 (I - K):  Kbar = -2 L1bar;  K = A^-1: Abar = -K^T Kbar K^T;  A = I + h B: Bbar = h Abar
+  T Kbar[M][M], tmp[M][M], Bbar[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) Kbar[i][j] = T(-2) * L1bar[i][j];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < M; ++l) acc += Kbar[i][l] * K[j][l];   // (Kbar K^T)_ij
+      tmp[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < M; ++l) acc += K[l][i] * tmp[l][j];    // (K^T tmp)_ij
+      Bbar[i][j] = -h * acc;
+    }
+
+  // B_ij = -xb_i S_ij (i != j), B_ii = R_iN + sum_{k != i} xb_k S_ik,  S_ik = R_ik - R_iN
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double rN = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j == i) continue;
+      const T S = R[i][j] - R[i][M];
+      // off-diagonal B_ij
+      if (!linearized) xibar[i] -= Bbar[i][j] * S;
+      Rbar[i][j] += (double)(-Bbar[i][j] * xb[i]);
+      rN += (double)(Bbar[i][j] * xb[i]);
+      // diagonal B_ii depends on xb_j through S_ij
+      if (!linearized) xibar[j] += Bbar[i][i] * S;
+      Rbar[i][j] += (double)(Bbar[i][i] * xb[j]);
+      rN -= (double)(Bbar[i][i] * xb[j]);
+    }
+    rN += (double)Bbar[i][i];
+    Rbar[i][M] += rN;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) fbar[i][k] += xibar[i];
+}
+
 }  // namespace msd

@@ -593,6 +593,154 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchInst* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint sweep.  Adjoint buffers hold dL/df^t, the derivative with respect to
+// the pre-collision distributions at time t, at their own node.  Forward step
+// t is g^t = C(f^{t-1}) and f^t = P(g^t) (P the propagation, f^{t-1} = P(s_{t-1})
+// for t >= 2 and f^0 = s_0).  Its adjoint reads dL/df^t through the transposed
+// propagation (dL/dg^t = P^T dL/df^t), recomputes f^{t-1} from s_{t-1}, applies
+// the transposed collision Jacobian and stores dL/df^{t-1} at the node; dL/dR
+// is accumulated per tile in FP64.
+// ---------------------------------------------------------------------------
+template <int LAT, int M, typename T>
+__global__ __launch_bounds__(256) void k_adjoint_seed(Problem p, const double* __restrict__ G, T* __restrict__ adj,
+                                                      int pull, Tiling tl) {
+  constexpr int Q = Lattice<LAT>::Q;
+  NodePos n;
+  if (!tile_node(p, tl, n)) return;
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  // xi_i = sum_k f_ik (i < N) and xi_N = 1 - sum: dL/df_ik = G_i - G_N for every k
+  const double gN = G[(int64_t)M * nodes + n.idx];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const T v = T(G[(int64_t)i * nodes + n.idx] - gN);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) adj[(int64_t)(i * Q + k) * p.plane + n.idx] = v;
+  }
+}
+
+// The adjoint sweep gives each thread kAdjointNodesPerThread nodes (from
+// consecutive block_x-wide strips along x), so that one workgroup reduction of
+// dL/dR covers 4 * 256 nodes.
+template <int LAT, int M, typename T, bool A32>
+__global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __restrict__ state_prev,
+                                                      const T* __restrict__ adj_in, T* __restrict__ adj_out,
+                                                      const Consts<T>* __restrict__ cst, int pull, Tiling tl,
+                                                      double* __restrict__ racc) {
+  constexpr int Q = Lattice<LAT>::Q, E = M * (M + 1), NPT = kAdjointNodesPerThread;
+  const uint32_t tile = logical_tile(tl);
+  const uint32_t tx = tile % tl.tiles_x;
+  const uint32_t rest = tile / tl.tiles_x;
+  const uint32_t ty = rest % tl.tiles_y;
+  const uint32_t tz = rest / tl.tiles_y;
+  double Rbar[M][M + 1];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= M; ++j) Rbar[i][j] = 0.0;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  const Planes<T, A32> S{state_prev, p.plane}, A{adj_in, p.plane};
+  NodePos n;
+  n.c[1] = (int32_t)(ty * blockDim.y + threadIdx.y);
+  n.c[2] = (int32_t)tz;
+  for (int j = 0; j < NPT; ++j) {
+    n.c[0] = (int32_t)((tx * NPT + j) * blockDim.x + threadIdx.x);
+    if (n.c[0] >= p.nx || n.c[1] >= p.ny) continue;
+    n.idx = n.c[0] + (int64_t)p.nx * (n.c[1] + (int64_t)p.ny * n.c[2]);
+    T f[M][Q], u[M][Q], fb[M][Q];
+    if (pull) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) pull_dir<LAT, M, T, A32>(p, S, n, k, f, nc.wall, false);
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) f[i][k] = S(i * Q + k, n.idx);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) pull_dir<LAT, M, T, A32>(p, A, n, k, u, nc.wall, true);
+    collide_node_adjoint<LAT, M, T>(f, u, nc.R, nc.xref, p.linearized != 0, p.relax != 0, fb, Rbar);
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        T* plane_out = adj_out + (int64_t)(i * Q + k) * p.plane;
+        if constexpr (A32)
+          *reinterpret_cast<T*>(reinterpret_cast<char*>(plane_out) + (uint32_t)n.idx * (uint32_t)sizeof(T)) = fb[i][k];
+        else
+          plane_out[n.idx] = fb[i][k];
+      }
+  }
+  // workgroup sum of dL/dR, added to this tile's accumulator slot
+  __shared__ double red[4][E];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= M; ++j) {
+      const double s = wave_sum(Rbar[i][j]);
+      if (lane == 0) red[wv][i * (M + 1) + j] = s;
+    }
+  __syncthreads();
+  const int waves = (int)((blockDim.x * blockDim.y + 63) / 64);
+  if (tid < E) {
+    double s = red[0][tid];
+    for (int w = 1; w < waves; ++w) s += red[w][tid];
+    racc[(int64_t)tile * E + tid] += s;
+  }
+}
+
+template <int LAT, int M, typename T>
+__global__ __launch_bounds__(256) void k_adjoint_xi0(Problem p, const T* __restrict__ adj0, double* __restrict__ out,
+                                                     Tiling tl) {
+  using L = Lattice<LAT>;
+  NodePos n;
+  if (!tile_node(p, tl, n)) return;
+  const int64_t nodes = (int64_t)p.nx * p.ny * p.nz;
+  // f^0_ik = w_k xi0_i (Sec. 4 initialisation)
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) s += L::w(k) * (double)adj0[(int64_t)(i * L::Q + k) * p.plane + n.idx];
+    out[(int64_t)i * nodes + n.idx] = s;
+  }
+}
+
+// dL/dD for the symmetric pair (i, j): -(Rbar_ij + Rbar_ji) / D_ij^2, where
+// Rbar_ji exists only when both species are evolved.  One workgroup, fixed
+// summation order over tiles.
+template <int LAT, int M>
+__global__ void k_adjoint_dD(Problem p, const double* __restrict__ racc, uint32_t tiles, double* __restrict__ out) {
+  constexpr int E = M * (M + 1), N = M + 1;
+  __shared__ double tot[E];
+  const int e = threadIdx.x;
+  if (e < E) {
+    double s = 0.0;
+    for (uint32_t t = 0; t < tiles; ++t) s += racc[(int64_t)t * E + e];
+    tot[e] = s;
+  }
+  __syncthreads();
+  if (e < N * N) {
+    const int i = e / N, j = e % N;
+    double g = 0.0;
+    if (i != j) {
+      if (i < M) g += tot[i * (M + 1) + j];
+      if (j < M) g += tot[j * (M + 1) + i];
+      g = -g / (p.D[i][j] * p.D[i][j]);
+    }
+    out[e] = g;
+  }
+}
+
+template <int LAT>
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
 inline Tiling make_tiling(const LaunchArgs& a, int V = 1) {
@@ -681,6 +829,40 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::DiagFinal:
       hipLaunchKernelGGL(k_diag_final<LAT>, dim3(1), dim3(64), 0, a.stream, a.partials, a.diag_blocks, M + 1,
                          a.diag_out);
+      break;
+    case Op::AdjointSeed: {
+      const Tiling tl = make_tiling(a);
+      hipLaunchKernelGGL((k_adjoint_seed<LAT, M, T>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream, a.p,
+                         static_cast<const double*>(a.xi0), static_cast<T*>(a.dst), a.pull, tl);
+      break;
+    }
+    case Op::AdjointStep: {
+      const Tiling tl = make_tiling(a, kAdjointNodesPerThread);
+      const bool a32 = (uint64_t)a.p.plane * sizeof(T) < (1ull << 32);
+      if (a32)
+        hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, true>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0,
+                           a.stream, a.p, static_cast<const T*>(a.src), static_cast<const T*>(a.adj_in),
+                           static_cast<T*>(a.dst), cst, a.pull, tl, a.partials);
+      else
+        hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, false>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0,
+                           a.stream, a.p, static_cast<const T*>(a.src), static_cast<const T*>(a.adj_in),
+                           static_cast<T*>(a.dst), cst, a.pull, tl, a.partials);
+      break;
+    }
+    case Op::AdjointXi0: {
+      const Tiling tl = make_tiling(a);
+      hipLaunchKernelGGL((k_adjoint_xi0<LAT, M, T>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0, a.stream, a.p,
+                         static_cast<const T*>(a.adj_in), static_cast<double*>(a.out_xi), tl);
+      break;
+    }
+    case Op::AdjointDD: {
+      const Tiling tl = make_tiling(a, kAdjointNodesPerThread);
+      hipLaunchKernelGGL((k_adjoint_dD<LAT, M>), dim3(1), dim3(64), 0, a.stream, a.p, a.partials, tl.tiles,
+                         a.diag_out);
+      break;
+    }
+    case Op::FillZero:
+      hipLaunchKernelGGL(k_fill_zero<LAT>, dim3(256), dim3(256), 0, a.stream, a.partials, a.fill_count);
       break;
     case Op::BatchStep:
       // here M is the largest number of evolved species in the launch

@@ -8,7 +8,10 @@
 
 namespace msd {
 
-enum class Op { Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep };
+enum class Op {
+  Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
+  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero
+};
 
 // Constants block written once per problem by the setup kernel and read by
 // every sweep kernel through uniform (scalar-cache) loads: R = 1/D (m rows of
@@ -73,7 +76,13 @@ struct LaunchArgs {
   uint32_t tile_begin = 0, ntiles = 0;
   char* ws = nullptr;
   int cur = 0;
+  // adjoint
+  const void* adj_in = nullptr;
+  int64_t fill_count = 0;
 };
+
+// Nodes per thread of the adjoint sweep (see k_adjoint_step).
+constexpr int kAdjointNodesPerThread = 4;
 
 // Largest domain (nodes) the single-workgroup LDS-resident sweep accepts for a
 // given m, q and value size: two copies of m*q values per node in <= 64 KiB.

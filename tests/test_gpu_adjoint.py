@@ -1,0 +1,166 @@
+"""Hand-written adjoint of the sweep (through the C ABI) against the autograd
+twin of the oracle and against central finite differences of the GPU forward
+run in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import oracle_problem, rand_D, rand_field, smooth_field
+from oracle import twin
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(lattice, D, shape, precision, xi0, target, steps, every, **kw):
+    from paper_1808_06787_amd import adjoint
+    from paper_1808_06787_amd.sim import Sim
+
+    sim = Sim(lattice, D, shape, precision, **kw)
+    sim.init(torch.from_numpy(xi0))
+    ckpts = adjoint.forward_with_checkpoints(sim, steps, every)
+    xi, _, _ = sim.read(torch.float64, flux=False, grad=False)
+    tgt = torch.from_numpy(target).to(xi.device)
+    L = float(((xi - tgt) ** 2).sum())
+    dxi0, dD = adjoint.gradients(sim, ckpts, steps, 2.0 * (xi - tgt), every)
+    sim.close()
+    return L, dD, dxi0.cpu().numpy()
+
+
+def _compare(ref, got, rel, label):
+    L0, gD0, gx0 = ref
+    L1, gD1, gx1 = got
+    assert abs(L1 - L0) <= rel * max(abs(L0), 1e-30), (label, L0, L1)
+    sD = np.abs(gD0).max()
+    assert np.abs(gD1 - gD0).max() <= rel * sD, (label, gD0, gD1)
+    sx = np.abs(gx0).max()
+    assert np.abs(gx1 - gx0).max() <= rel * sx, (label, np.abs(gx1 - gx0).max(), sx)
+
+
+CASES = [
+    ("D2Q5", (13, 9), 3, (("dirichlet", "zero_flux"), ("periodic", "periodic"))),
+    ("D2Q5", (17, 6), 4, (("periodic", "periodic"), ("zero_flux", "zero_flux"))),
+    ("D1Q3", (23,), 4, (("zero_flux", "dirichlet"),)),
+    ("D3Q7", (6, 5, 4), 3, (("zero_flux", "zero_flux"), ("periodic", "periodic"), ("dirichlet", "dirichlet"))),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("relax", ["paper", "srt"])
+def test_adjoint_matches_autograd_twin_fp64(case, relax):
+    lattice, shape, N, bc = CASES[case]
+    rng = np.random.default_rng(60 + case)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    target = smooth_field(rng, N, shape[::-1], 0.15)
+    steps, every = 20, 6
+    p = oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax)
+    ref = twin.misfit_gradients(p, xi0, target, steps)
+    got = _gpu_grads(lattice, D, shape, "f64", xi0, target, steps, every, bc=bc, xi_wall=walls, relax=relax)
+    _compare(ref, got, 1e-10, f"{lattice} {relax}")
+
+
+def test_adjoint_linearised_mode_fp64():
+    rng = np.random.default_rng(66)
+    N, shape = 4, (11, 10)
+    D = rand_D(rng, N)
+    xref = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    p = oracle_problem("D2Q5", D, shape, xi_ref=xref)
+    ref = twin.misfit_gradients(p, xi0, target, 15)
+    got = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, 15, 4, xi_ref=xref)
+    _compare(ref, got, 1e-10, "linearised")
+
+
+@pytest.mark.parametrize("steps,every", [(0, 5), (1, 5), (7, 7), (7, 1), (12, 100)])
+def test_adjoint_segmenting_edge_cases(steps, every):
+    rng = np.random.default_rng(67)
+    N, shape = 3, (9, 7)
+    D = rand_D(rng, N)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    p = oracle_problem("D2Q5", D, shape)
+    ref = twin.misfit_gradients(p, xi0, target, steps)
+    got = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, steps, every)
+    if steps <= 1:
+        # no step, or one step from f(0) = w xi(0), whose non-equilibrium part is
+        # zero: L does not depend on D (both sides hold rounding noise at most)
+        assert np.abs(got[1]).max() <= 1e-15 and np.abs(ref[1]).max() <= 1e-15
+        np.testing.assert_allclose(got[2], ref[2], rtol=0, atol=1e-13 * np.abs(ref[2]).max())
+    else:
+        _compare(ref, got, 1e-10, f"{steps}/{every}")
+
+
+def test_adjoint_fp32_close_to_fp64_reference():
+    rng = np.random.default_rng(68)
+    N, shape = 3, (40, 33)
+    D = rand_D(rng, N, 0.05, 0.5)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    ref = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, 60, 16)
+    got = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, 60, 16)
+    _compare(ref, got, 2e-4, "fp32")
+
+
+def test_adjoint_agrees_with_central_differences():
+    """Central differences with h = 1e-4 of the FP64 forward run (a 64 x 48 ternary
+    problem, 300 steps) against the adjoint: every D_ij pair and one random
+    direction of the initial field agree to 1e-4 relative."""
+    from paper_1808_06787_amd.sim import Sim
+
+    rng = np.random.default_rng(69)
+    N, shape, steps = 3, (64, 48), 300
+    D = rand_D(rng, N, 0.05, 0.5)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    L, gD, gx = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, steps, 50)
+
+    def loss(Dm, x0):
+        s = Sim("D2Q5", Dm, shape, "f64")
+        s.init(torch.from_numpy(x0))
+        s.step(steps)
+        xi, _, _ = s.read(torch.float64, flux=False, grad=False)
+        s.close()
+        return float(((xi.cpu().numpy() - target) ** 2).sum())
+
+    h = 1e-4
+    for i in range(N):
+        for j in range(i + 1, N):
+            Dp, Dm = D.copy(), D.copy()
+            Dp[i, j] = Dp[j, i] = D[i, j] + h
+            Dm[i, j] = Dm[j, i] = D[i, j] - h
+            fd = (loss(Dp, xi0) - loss(Dm, xi0)) / (2 * h)
+            assert abs(fd - gD[i, j]) <= 1e-4 * abs(fd), (i, j, fd, gD[i, j])
+    v = rng.standard_normal(size=xi0.shape)
+    v -= v.mean(axis=0, keepdims=True)
+    v /= np.linalg.norm(v)
+    fd = (loss(D, xi0 + h * v) - loss(D, xi0 - h * v)) / (2 * h)
+    ad = float((gx * v[: N - 1]).sum())
+    assert abs(fd - ad) <= 1e-4 * abs(fd), (fd, ad)
+
+
+def test_autograd_function():
+    from paper_1808_06787_amd.adjoint import MSDiffusion
+
+    rng = np.random.default_rng(70)
+    N, shape = 3, (12, 8)
+    D = rand_D(rng, N)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    x = torch.tensor(xi0, device="cuda", requires_grad=True)
+    Dt = torch.tensor(D, requires_grad=True)
+    spec = dict(lattice="D2Q5", shape=shape, precision="f64", steps=10, every=3)
+    xi = MSDiffusion.apply(x, Dt, spec)
+    L = ((xi - torch.tensor(target, device="cuda")) ** 2).sum()
+    L.backward()
+    p = oracle_problem("D2Q5", D, shape)
+    L0, gD0, gx0 = twin.misfit_gradients(p, xi0, target, 10)
+    assert abs(L.item() - L0) <= 1e-12 * L0
+    np.testing.assert_allclose(Dt.grad.numpy() + Dt.grad.numpy().T, gD0, rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(x.grad.cpu().numpy()[: N - 1], gx0, rtol=1e-10, atol=1e-14 * np.abs(gx0).max())
+    assert np.all(x.grad.cpu().numpy()[N - 1] == 0)
