@@ -237,7 +237,11 @@ typedef struct msd_launch {
                                vector accesses; used when nx % vec == 0, else the largest
                                power of two dividing nx); 0 (default) selects the general
                                one-node-per-thread kernel */
-  int32_t reserved[2];
+  int32_t temporal;         /* D2Q5 only: 2 or 3 steps per pass over HBM (temporally blocked
+                               sweep: rows of each time level kept in LDS); 0 or 1: one step
+                               per pass.  Falls back to one step per pass where the LDS rings
+                               of the species count and precision do not fit */
+  int32_t seg_rows;         /* rows per workgroup of the blocked sweep (0: 32) */
 } msd_launch;
 
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);

@@ -55,7 +55,8 @@ class MsdLaunch(C.Structure):
         ("lds_resident", C.c_int32),
         ("nontemporal", C.c_int32),
         ("vec", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("temporal", C.c_int32),
+        ("seg_rows", C.c_int32),
     ]
 
 

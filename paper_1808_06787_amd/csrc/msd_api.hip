@@ -167,6 +167,8 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
+  l->temporal = 0;
+  l->seg_rows = 32;
 }
 
 }  // namespace host
@@ -204,6 +206,14 @@ msd::LaunchArgs base_args(const msd_sim* s) {
   a.nontemporal = s->launch.nontemporal;
   a.vec = s->launch.vec;
   return a;
+}
+
+// Steps per pass of the blocked sweep for this handle (0 when not applicable).
+int blocked_steps(const msd_sim* s) {
+  const int tb = s->launch.temporal;
+  if (tb < 2 || s->prob.lattice != MSD_D2Q5) return 0;
+  if (msd::blocked_cols(s->m, tb, s->prob.precision) == 0) return 0;
+  return tb;
 }
 
 bool use_lds(const msd_sim* s) {
@@ -287,6 +297,9 @@ int msd_set_launch(msd_sim* s, const msd_launch* l) {
     v.block_y = d.block_y;
   }
   if (v.nontemporal < 0 || v.nontemporal > 7) return fail(MSD_EINVAL, "nontemporal mask %d", v.nontemporal);
+  if (v.temporal < 0 || v.temporal > 3) return fail(MSD_EINVAL, "temporal = %d must be 0..3", v.temporal);
+  if (v.seg_rows < 0 || v.seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", v.seg_rows);
+  if (v.seg_rows == 0) v.seg_rows = 32;
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4)
     return fail(MSD_EINVAL, "vec = %d must be 0, 1, 2 or 4", v.vec);
   if (v.block_x < 64 || v.block_x % 64 || v.block_y < 1 || v.block_x * v.block_y > 256)
@@ -337,14 +350,28 @@ int msd_step(msd_sim* s, int64_t nsteps) {
     s->t += nsteps;
     return MSD_OK;
   }
-  for (int64_t n = 0; n < nsteps; ++n) {
+  const int tb = blocked_steps(s);
+  int64_t n = 0;
+  while (n < nsteps) {
     a.src = s->ws + s->L.half_off[s->cur];
     a.dst = s->ws + s->L.half_off[1 - s->cur];
     a.pull = s->t > 0 ? 1 : 0;
-    const hipError_t e = dispatch(msd::Op::Step, a);
+    int64_t done = 1;
+    hipError_t e;
+    if (tb >= 2 && s->t > 0 && nsteps - n >= tb) {
+      // tb steps in one pass; the first step after msd_init reads pre-collision
+      // values and is always a single step
+      a.tb = tb;
+      a.seg_rows = s->launch.seg_rows;
+      e = dispatch(msd::Op::StepBlocked, a);
+      done = tb;
+    } else {
+      e = dispatch(msd::Op::Step, a);
+    }
     if (e != hipSuccess) return hip_fail(e, "step kernel");
     s->cur = 1 - s->cur;
-    s->t += 1;
+    s->t += done;
+    n += done;
   }
   return MSD_OK;
 }

@@ -301,6 +301,122 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Temporally blocked D2Q5 sweep: TB time steps per pass over HBM.
+//
+// Workgroup (tile, segment) owns output columns [x0, x0 + W), W = C - 2 TB, and
+// output rows [y0, y1).  Thread c holds column x = x0 - TB + c (a halo of TB
+// columns each side; wrapped for periodic x).  The workgroup marches over the
+// input rows y0 - TB .. y1 - 1 + TB (wrapped for periodic y): each input row is
+// loaded once (prefetched one row ahead into registers) into the level-0 ring;
+// level l then produces row r_in - l from rows r - 1, r, r + 1 of level l - 1,
+// i.e. one step of pull-propagation + collision, and level TB writes the
+// output row.  Level l is valid on columns [l, C - l) and rows
+// [y0 - TB + l, y1 - 1 + TB - l]; nodes beyond a wall are never produced and
+// never read (the face rule at a boundary node reads the node itself).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int mod3(int r) { return ((r % 3) + 3) % 3; }
+
+template <int M, typename T, int TB, int C>
+__global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
+                                                    const Consts<T>* __restrict__ cst, int seg_rows,
+                                                    uint32_t tiles_x, int nontemporal) {
+  using L = Lattice<2>;
+  constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB;
+  __shared__ T ring[TB][3][P][C];
+  const int c = (int)threadIdx.x;
+  const int nx = p.nx, ny = p.ny;
+  const uint32_t tx = blockIdx.x % tiles_x;
+  const uint32_t seg = blockIdx.x / tiles_x;
+  const int x0 = (int)tx * W;
+  const int y0 = (int)seg * seg_rows;
+  const int y1 = min(y0 + seg_rows, ny);
+  const int x = x0 - TB + c;
+  const bool px = p.bc[0] == BC_PERIODIC, py = p.bc[2] == BC_PERIODIC;
+  const bool x_in = x >= 0 && x < nx;
+  const bool col_ok = x_in || px;
+  const int xl = x_in ? x : (((x % nx) + nx) % nx);
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+
+  T reg[P];
+  auto load_row = [&](int r) {
+    const bool r_in = r >= 0 && r < ny;
+    const int rl = r_in ? r : (((r % ny) + ny) % ny);
+    if (col_ok && (r_in || py)) {
+      const int64_t idx = (int64_t)rl * nx + xl;
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) reg[pl] = ld(src + (int64_t)pl * p.plane + idx, (nontemporal & NT_LOAD_ALIGNED) != 0);
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) reg[pl] = T(0);
+    }
+  };
+
+  const int r_last = y1 - 1 + TB;
+  int r_in = y0 - TB;
+  load_row(r_in);
+  for (; r_in <= r_last; ++r_in) {
+    {
+      const int slot = mod3(r_in);
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) ring[0][slot][pl][c] = reg[pl];
+    }
+    __syncthreads();
+    if (r_in < r_last) load_row(r_in + 1);
+#pragma unroll
+    for (int lvl = 1; lvl <= TB; ++lvl) {
+      const int r = r_in - lvl;
+      const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
+      const bool here = row_ok && c >= lvl && c < C - lvl && (px || x_in);
+      if (here) {
+        const int s0 = mod3(r), sm = mod3(r - 1), sp = mod3(r + 1);
+        T f[M][Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const int kb = L::opp(k);
+          const int a = L::axis(k), sg = L::sgn(k);
+          // the face direction k enters through, and whether its source lies beyond it
+          const int fk = a < 0 ? 0 : 2 * a + (sg > 0 ? 0 : 1);
+          bool wall = false;
+          if (a == 0) wall = !px && (sg > 0 ? x == 0 : x == nx - 1);
+          if (a == 1) wall = !py && (sg > 0 ? r == 0 : r == ny - 1);
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            T v;
+            if (wall) {
+              const T back = ring[lvl - 1][s0][i * Q + kb][c];
+              v = (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
+            } else if (a < 0) {
+              v = ring[lvl - 1][s0][i * Q + k][c];
+            } else if (a == 0) {
+              v = ring[lvl - 1][s0][i * Q + k][sg > 0 ? c - 1 : c + 1];
+            } else {
+              v = ring[lvl - 1][sg > 0 ? sm : sp][i * Q + k][c];
+            }
+            f[i][k] = v;
+          }
+        }
+        collide_node<2, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+        if (lvl < TB) {
+#pragma unroll
+          for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = 0; k < Q; ++k) ring[lvl][s0][i * Q + k][c] = f[i][k];
+        } else if (c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
+          const int64_t idx = (int64_t)r * nx + x;
+#pragma unroll
+          for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+              store_value(dst + (int64_t)(i * Q + k) * p.plane + idx, f[i][k], nontemporal & NT_STORE);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small domains: one workgroup keeps both ping-pong copies in LDS and runs all
 // requested steps in one launch (launch latency would otherwise dominate).
 // ---------------------------------------------------------------------------
@@ -753,6 +869,29 @@ inline Tiling make_tiling(const LaunchArgs& a, int V = 1) {
   return t;
 }
 
+template <int M, typename T, int TB>
+hipError_t launch_blocked_tb(const LaunchArgs& a) {
+  constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
+  if constexpr (C == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int W = C - 2 * TB;
+    const uint32_t tiles_x = (uint32_t)((a.p.nx + W - 1) / W);
+    const uint32_t segs = (uint32_t)((a.p.ny + a.seg_rows - 1) / a.seg_rows);
+    hipLaunchKernelGGL((k_step_blocked<M, T, TB, C>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p,
+                       static_cast<const T*>(a.src), static_cast<T*>(a.dst), static_cast<const Consts<T>*>(a.consts),
+                       a.seg_rows, tiles_x, a.nontemporal);
+    return hipSuccess;
+  }
+}
+
+template <int M, typename T>
+hipError_t launch_blocked(const LaunchArgs& a) {
+  if (a.tb == 2) return launch_blocked_tb<M, T, 2>(a);
+  if (a.tb == 3) return launch_blocked_tb<M, T, 3>(a);
+  return hipErrorInvalidValue;
+}
+
 // Width of the vectorised sweep for this launch: the requested vec (1, 2, 4)
 // when the extents and offsets allow it, else 0 (the general 64-bit kernel).
 template <typename T>
@@ -863,6 +1002,14 @@ hipError_t run(Op op, const LaunchArgs& a) {
     }
     case Op::FillZero:
       hipLaunchKernelGGL(k_fill_zero<LAT>, dim3(256), dim3(256), 0, a.stream, a.partials, a.fill_count);
+      break;
+    case Op::StepBlocked:
+      if constexpr (LAT == 2) {
+        const hipError_t e = launch_blocked<M, T>(a);
+        if (e != hipSuccess) return e;
+      } else {
+        return hipErrorInvalidValue;
+      }
       break;
     case Op::BatchStep:
       // here M is the largest number of evolved species in the launch

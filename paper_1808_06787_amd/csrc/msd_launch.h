@@ -10,7 +10,7 @@ namespace msd {
 
 enum class Op {
   Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
-  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero
+  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked
 };
 
 // Constants block written once per problem by the setup kernel and read by
@@ -56,6 +56,8 @@ struct LaunchArgs {
   int xcd_remap = 1;
   int nontemporal = 0;
   int vec = 1;               // nodes per thread of the vectorised sweep (0: general kernel)
+  int tb = 0;                // steps per pass of the temporally blocked sweep
+  int seg_rows = 32;         // rows per workgroup segment of the blocked sweep
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;
@@ -80,6 +82,18 @@ struct LaunchArgs {
   const void* adj_in = nullptr;
   int64_t fill_count = 0;
 };
+
+// Temporally blocked D2Q5 sweep (k_step_blocked): a workgroup of `cols`
+// threads keeps, for each of TB - 1 intermediate time levels and for the input,
+// a ring of three rows of m*5 planes in LDS.  cols is the widest of 256, 128, 64
+// whose rings fit in 64 KiB; 0 when none does.
+constexpr int kBlockedLdsBytes = 64 * 1024;
+constexpr int blocked_cols(int m, int tb, int bytes) {
+  return (tb * 3 * m * 5 * 256 * bytes <= kBlockedLdsBytes)   ? 256
+         : (tb * 3 * m * 5 * 128 * bytes <= kBlockedLdsBytes) ? 128
+         : (tb * 3 * m * 5 * 64 * bytes <= kBlockedLdsBytes)  ? 64
+                                                               : 0;
+}
 
 // Nodes per thread of the adjoint sweep (see k_adjoint_step).
 constexpr int kAdjointNodesPerThread = 4;

@@ -230,3 +230,48 @@ def test_streaming_hints_and_padding_do_not_change_results(vec):
         sim.close()
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
+
+
+BLOCKED_CASES = [
+    ((301, 29), (("zero_flux", "zero_flux"), ("periodic", "periodic"))),
+    ((257, 40), (("periodic", "periodic"), ("dirichlet", "zero_flux"))),
+    ((70, 130), (("dirichlet", "dirichlet"), ("zero_flux", "dirichlet"))),
+    ((3, 700), (("periodic", "periodic"), ("periodic", "periodic"))),
+]
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
+@pytest.mark.parametrize("tb", [2, 3])
+@pytest.mark.parametrize("N", [2, 3, 5])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_temporally_blocked_sweep(case, tb, N, precision):
+    """Several steps per pass over HBM (rows of each time level in LDS): ragged
+    tiles and row segments, every face kind, odd step counts (remainder single
+    steps) and the pre-collision first step."""
+    shape, bc = BLOCKED_CASES[case]
+    rng = np.random.default_rng(300 + 10 * case + N)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 23
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls), xi0, steps)
+    for seg in (5, 32):
+        gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls,
+                      launch=dict(temporal=tb, seg_rows=seg, lds_resident=0), split=[1, 6, 16])
+        assert_parity(gpu, orc, precision, f"blocked tb={tb} seg={seg} {shape} N={N} {precision}")
+
+
+def test_blocked_sweep_matches_single_step_sweep():
+    rng = np.random.default_rng(310)
+    D = rand_D(rng, 3)
+    shape = (500, 97)
+    xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
+    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(lds_resident=0))
+    for tb in (2, 3):
+        got = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(temporal=tb, lds_resident=0))
+        for a, b in zip(ref, got):
+            np.testing.assert_allclose(a, b, rtol=0, atol=2e-6)
