@@ -5,15 +5,19 @@
 
 Default workload: 2D ternary mixture on a 4096^2 D2Q5 lattice in FP32
 (periodic, smooth random field, random D_ij), K = 2000 steps timed after W
-warm-up steps.  One step is one fused collide-and-stream launch over every
-node (propagation with face rules, moments, the local Maxwell-Stefan solve,
-relaxation, store).  Prints one JSON line:
+warm-up steps.  One step is one fused collide-and-stream update of every node
+(propagation with face rules, moments, the local Maxwell-Stefan solve,
+relaxation, store); the 2D sweep performs several steps per launch (temporal
+blocking: intermediate time levels stay on chip).  Prints one JSON line:
 
   value        MLUPS = nodes * (N - 1) * K / seconds / 1e6 (node-component updates)
   roofline     HBM roofline of the sweep kernel: algorithmic bytes per launch
-               (2 q (N-1) bytes-per-value per node: every distribution read
-               once and written once) over the average launch duration
-               measured with HIP events on the sweep's stream
+               (2 q (N-1) bytes-per-value per node and step: every distribution
+               read once and written once, times the steps one launch performs)
+               over the average launch duration measured with HIP events on the
+               sweep's stream.  With several steps per launch the kernel moves
+               about 1/steps of these bytes, so frac can exceed 1; `traffic` is
+               the measured HBM bytes per launch
   cpu_baseline the FP64 numpy oracle on a bounded sample of the same workload
   extras       the 3D quaternary workload and the other kernels, timed the same way
 """
@@ -44,12 +48,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None if
-    absent or taken on a different version of the kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+def load_profile(kind: str, workload: str) -> dict:
+    """Key/value lines of a committed rocprofv3 summary (profiles/<kind>_<workload>.txt),
+    or {} if absent or taken on a different version of the kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as fh:
         for line in fh:
@@ -57,9 +61,23 @@ def load_traffic(workload: str):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_sources_sha256_16") != kernel_hash():
-        return None
+        return {}
+    return vals
+
+
+def load_traffic(workload: str):
+    """Measured HBM bytes per launch of the sweep kernel (FETCH_SIZE + WRITE_SIZE, calibrated
+    on a copy kernel), or None."""
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(load_profile("traffic", workload)["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_valu_time(workload: str):
+    """VALU issue time per launch (seconds at 2.4 GHz) from the SQ_INSTS_VALU count, or None."""
+    try:
+        return float(load_profile("valu", workload)["valu_issue_time_us_at_2.4GHz"]) * 1e-6
     except (KeyError, ValueError):
         return None
 
@@ -98,16 +116,24 @@ def time_sweep(w, steps: int, warmup: int, launch=None):
     return start.elapsed_time(stop) / 1e3, sim
 
 
-def sweep_record(w, seconds, steps):
+def sweep_record(w, seconds, steps, steps_per_pass=1):
+    """MLUPS and the HBM roofline figures of a timed run of `steps` steps from t > 0.
+
+    A launch of the blocked sweep advances `steps_per_pass` steps; its algorithmic
+    bytes are those of the steps it performs (2 q (N-1) value sizes per node and
+    step), so `achieved` is comparable with the one-step-per-pass sweep."""
     m = w.N - 1
     q = Q[w.lattice]
     s = 4 if w.precision == "f32" else 8
     nodes = w.nodes
     mlups = nodes * m * steps / seconds / 1e6
-    bytes_per_launch = nodes * m * 2 * q * s
-    per_launch = seconds / steps
-    achieved = bytes_per_launch / per_launch / 1e9
-    return mlups, bytes_per_launch, per_launch, achieved
+    spp = max(1, int(steps_per_pass))
+    launches = steps // spp + steps % spp
+    bytes_per_launch = nodes * m * 2 * q * s * spp
+    per_launch = seconds / launches
+    achieved = bytes_per_launch / per_launch / 1e9 if steps % spp == 0 else nodes * m * 2 * q * s * steps / seconds / 1e9
+    return dict(mlups=mlups, per_step=seconds / steps, launches=launches, per_launch=per_launch,
+                bytes_per_launch=bytes_per_launch, achieved=achieved, steps_per_pass=spp)
 
 
 def batched_extra(steps: int = 1000, warmup: int = 5):
@@ -295,6 +321,9 @@ def main():
     ap.add_argument("--nontemporal", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--vec", type=int, default=0)
+    ap.add_argument("--temporal", type=int, default=None,
+                    help="steps per pass of the blocked D2Q5 sweep (0: one step per pass; default: library's)")
+    ap.add_argument("--seg-rows", type=int, default=None)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -320,16 +349,19 @@ def main():
     w = make_workload(args.workload)
     steps = args.steps if args.steps is not None else w.steps
     launch = dict(block_x=args.block_x, block_y=args.block_y, xcd_remap=args.xcd_remap,
-                  nontemporal=args.nontemporal, vec=args.vec)
+                  nontemporal=args.nontemporal, vec=args.vec, temporal=args.temporal, seg_rows=args.seg_rows)
     print(f"# workload {w.name}: {w.lattice} N={w.N} shape={w.shape} {w.precision}; "
           f"warmup {args.warmup}, timing {steps} steps", file=sys.stderr, flush=True)
     seconds, sim = time_sweep(w, steps, args.warmup, launch)
-    mlups, bpl, per_launch, achieved = sweep_record(w, seconds, steps)
+    rec = sweep_record(w, seconds, steps, sim.steps_per_pass())
+    mlups, bpl, per_launch, achieved = rec["mlups"], rec["bytes_per_launch"], rec["per_launch"], rec["achieved"]
     _, _, _, bad = sim.diagnostics(raise_on_diverged=False)
     used_launch = sim.get_launch()
+    used_launch["steps_per_pass"] = rec["steps_per_pass"]
     sim.close()
     del sim
     traffic = load_traffic(w.name)
+    valu_time = load_valu_time(w.name)
     out = {
         "metric": "MLUPS (node-component updates per second) of the fused collide-and-stream sweep",
         "value": round(mlups, 1),
@@ -337,7 +369,7 @@ def main():
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(per_launch * 1e3, 5),
+        "ms_per_step": round(rec["per_step"] * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -353,17 +385,27 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bpl,
+            "steps_per_launch": rec["steps_per_pass"],
+            "launches_timed": rec["launches"],
+            "ms_per_launch": round(per_launch * 1e3, 5),
+            "traffic_GBps": round(traffic / per_launch / 1e9, 1) if traffic else None,
+            "traffic_frac": round(traffic / per_launch / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+            "valu_busy_frac": round(valu_time / per_launch, 4) if valu_time else None,
+            "note": ("several steps per launch (temporal blocking): achieved counts the bytes of every step "
+                     "performed, the kernel moves `traffic` bytes per launch; its limiter is VALU issue "
+                     "(valu_busy_frac at 2.4 GHz) rather than HBM") if rec["steps_per_pass"] > 1 else None,
         },
         "nonfinite": bad,
     }
-    print(f"# {w.name}: {mlups:.0f} MLUPS, {per_launch * 1e3:.4f} ms/step, {achieved:.0f} GB/s "
+    print(f"# {w.name}: {mlups:.0f} MLUPS, {rec['per_step'] * 1e3:.4f} ms/step, {achieved:.0f} GB/s "
           f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)", file=sys.stderr, flush=True)
     extras = {}
     if not args.no_extras and args.workload == "ternary_2d":
         w3 = make_workload("quaternary_3d")
         s3, sim3 = time_sweep(w3, w3.steps, 5)
+        r3 = sweep_record(w3, s3, w3.steps, sim3.steps_per_pass())
         sim3.close()
-        m3, b3, p3, a3 = sweep_record(w3, s3, w3.steps)
+        m3, p3, a3 = r3["mlups"], r3["per_step"], r3["achieved"]
         extras["quaternary_3d_d3q7_512^3_f32"] = {
             "MLUPS": round(m3, 1), "ms_per_step": round(p3 * 1e3, 4), "steps": w3.steps,
             "GB_per_s": round(a3, 1), "hbm_frac": round(a3 / HBM_PEAK_GBS, 4)}

@@ -237,15 +237,30 @@ typedef struct msd_launch {
                                vector accesses; used when nx % vec == 0, else the largest
                                power of two dividing nx); 0 (default) selects the general
                                one-node-per-thread kernel */
-  int32_t temporal;         /* D2Q5 only: 2 or 3 steps per pass over HBM (temporally blocked
-                               sweep: rows of each time level kept in LDS); 0 or 1: one step
-                               per pass.  Falls back to one step per pass where the LDS rings
-                               of the species count and precision do not fit */
-  int32_t seg_rows;         /* rows per workgroup of the blocked sweep (0: 32) */
+  int32_t temporal;         /* D2Q5 only: at most this many steps (2, 3 or 4) per pass over
+                               HBM (temporally blocked sweep: each workgroup marches along y
+                               with the intermediate time levels of a few rows on chip); 0 or
+                               1: one step per pass.  The library takes the largest count up
+                               to this one whose on-chip window fits the species count and
+                               precision (FP32: m <= 2 up to 4, m = 3 up to 3, m = 4 up to 2;
+                               FP64: m = 1 up to 4, m = 2 up to 2; else one step per pass).
+                               Default 4 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
+  int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
+                               automatic, 16 rows, or 8 when 16 give fewer than 512
+                               workgroups, and one step per pass when 8 still give fewer
+                               than 512 (small domains run faster unblocked); negative or
+                               above 2^20 is MSD_EINVAL */
 } msd_launch;
 
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);
 MSD_API int msd_get_launch(const msd_sim* sim, msd_launch* launch);
+
+/* Time steps the sweep advances per pass over HBM (one kernel launch) under the
+ * current launch configuration: the temporally blocked count (2..4) or 1.  The
+ * step from time 0 (from the state msd_init writes) and a remainder shorter
+ * than a pass run one step per launch.  Negative status (MSD_EINVAL) for a NULL
+ * handle. */
+MSD_API int msd_steps_per_pass(const msd_sim* sim);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent mixtures

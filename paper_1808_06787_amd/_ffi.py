@@ -107,6 +107,7 @@ def lib():
         "msd_set_stream": (C.c_int, [vp, vp]),
         "msd_set_launch": (C.c_int, [vp, P(MsdLaunch)]),
         "msd_get_launch": (C.c_int, [vp, P(MsdLaunch)]),
+        "msd_steps_per_pass": (C.c_int, [vp]),
         "msd_init": (C.c_int, [vp, vp, i32]),
         "msd_step": (C.c_int, [vp, i64]),
         "msd_time": (i64, [vp]),

@@ -107,8 +107,11 @@ def tune_sim(sim, cache_path: Optional[str] = None, steps: int = 10, warmup: int
         sim.set_launch(**cache[key]["best"])
         return cache[key]
     if candidates is None:
-        candidates = [dict(block_x=bx, block_y=by, vec=vec, xcd_remap=xcd, nontemporal=nt)
+        candidates = [dict(block_x=bx, block_y=by, vec=vec, xcd_remap=xcd, nontemporal=nt, temporal=0)
                       for (bx, by), vec, xcd, nt in itertools.product(SIM_BLOCKS, (0, 1, 4), (0, 1), (0, 7))]
+        if sim.lattice == "D2Q5":
+            candidates += [dict(temporal=tb, seg_rows=seg, nontemporal=nt)
+                           for tb, seg, nt in itertools.product((2, 3, 4), (16, 32, 64), (0, 1))]
     state, t0 = sim.save()
     trials = []
     for cand in candidates:

@@ -158,7 +158,9 @@ Layout layout_for(const msd_problem* p) {
 // one-node-per-thread kernel with 256-thread row tiles runs at the speed of a
 // plain copy of the same planes; vector widths 2/4, streaming hints and plane
 // padding do not improve on it.  Remapping tiles onto XCDs helps in 3D (+1.5 %)
-// and costs 3 % in 2D.
+// and costs 3 % in 2D.  In 2D the temporally blocked sweep with four steps per
+// pass and 16-row segments is 2.7x faster than one step per pass (ternary,
+// FP32); the species count and precision may lower the steps per pass.
 void default_launch(const msd_problem* p, msd_launch* l) {
   std::memset(l, 0, sizeof(*l));
   l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
@@ -167,8 +169,8 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
-  l->temporal = 0;
-  l->seg_rows = 32;
+  l->temporal = p->lattice == MSD_D2Q5 ? 4 : 0;
+  l->seg_rows = 0;
 }
 
 }  // namespace host
@@ -208,12 +210,40 @@ msd::LaunchArgs base_args(const msd_sim* s) {
   return a;
 }
 
-// Steps per pass of the blocked sweep for this handle (0 when not applicable).
-int blocked_steps(const msd_sim* s) {
-  const int tb = s->launch.temporal;
-  if (tb < 2 || s->prob.lattice != MSD_D2Q5) return 0;
-  if (msd::blocked_cols(s->m, tb, s->prob.precision) == 0) return 0;
-  return tb;
+// Plan of the blocked sweep for this handle: steps per pass (the largest count
+// up to the requested one whose on-chip window fits; 0: one step per pass) and
+// rows per workgroup segment.  Automatic segments (seg_rows = 0): 16 rows, or
+// 8 when 16 leave fewer than 512 workgroups (two per CU); if 8-row segments
+// still leave fewer than 512, one step per pass is faster (measured on 512^2
+// to 4096^2 ternary FP32 lattices).  32-bit in-plane offsets need plane bytes
+// < 4 GiB.
+struct BlockedPlan {
+  int tb = 0;
+  int seg = 0;
+};
+
+BlockedPlan blocked_plan(const msd_sim* s) {
+  BlockedPlan pl;
+  if (s->prob.lattice != MSD_D2Q5) return pl;
+  if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
+  int tb = 0;
+  for (int t = s->launch.temporal; t >= 2; --t)
+    if (msd::blocked_cols(s->m, t, s->prob.precision) > 0) {
+      tb = t;
+      break;
+    }
+  if (tb == 0) return pl;
+  const int64_t W = msd::kBlockedCols - 2 * tb;
+  const int64_t tiles_x = (s->prob.nx + W - 1) / W;
+  auto groups = [&](int64_t seg) { return tiles_x * ((s->prob.ny + seg - 1) / seg); };
+  int seg = s->launch.seg_rows;
+  if (seg <= 0) {
+    seg = groups(16) >= 512 ? 16 : 8;
+    if (groups(seg) < 512) return pl;
+  }
+  pl.tb = tb;
+  pl.seg = seg;
+  return pl;
 }
 
 bool use_lds(const msd_sim* s) {
@@ -297,9 +327,8 @@ int msd_set_launch(msd_sim* s, const msd_launch* l) {
     v.block_y = d.block_y;
   }
   if (v.nontemporal < 0 || v.nontemporal > 7) return fail(MSD_EINVAL, "nontemporal mask %d", v.nontemporal);
-  if (v.temporal < 0 || v.temporal > 3) return fail(MSD_EINVAL, "temporal = %d must be 0..3", v.temporal);
+  if (v.temporal < 0 || v.temporal > 4) return fail(MSD_EINVAL, "temporal = %d must be 0..4", v.temporal);
   if (v.seg_rows < 0 || v.seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", v.seg_rows);
-  if (v.seg_rows == 0) v.seg_rows = 32;
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4)
     return fail(MSD_EINVAL, "vec = %d must be 0, 1, 2 or 4", v.vec);
   if (v.block_x < 64 || v.block_x % 64 || v.block_y < 1 || v.block_x * v.block_y > 256)
@@ -313,6 +342,12 @@ int msd_get_launch(const msd_sim* s, msd_launch* l) {
   if (!s || !l) return fail(MSD_EINVAL, "NULL argument");
   *l = s->launch;
   return MSD_OK;
+}
+
+int msd_steps_per_pass(const msd_sim* s) {
+  if (!s) return fail(MSD_EINVAL, "NULL argument");
+  const int tb = blocked_plan(s).tb;
+  return tb >= 2 ? tb : 1;
 }
 
 int msd_init(msd_sim* s, const void* d_xi0, int32_t xi0_precision) {
@@ -350,7 +385,8 @@ int msd_step(msd_sim* s, int64_t nsteps) {
     s->t += nsteps;
     return MSD_OK;
   }
-  const int tb = blocked_steps(s);
+  const BlockedPlan plan = blocked_plan(s);
+  const int tb = plan.tb;
   int64_t n = 0;
   while (n < nsteps) {
     a.src = s->ws + s->L.half_off[s->cur];
@@ -362,7 +398,7 @@ int msd_step(msd_sim* s, int64_t nsteps) {
       // tb steps in one pass; the first step after msd_init reads pre-collision
       // values and is always a single step
       a.tb = tb;
-      a.seg_rows = s->launch.seg_rows;
+      a.seg_rows = plan.seg;
       e = dispatch(msd::Op::StepBlocked, a);
       done = tb;
     } else {

@@ -305,25 +305,40 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
 //
 // Workgroup (tile, segment) owns output columns [x0, x0 + W), W = C - 2 TB, and
 // output rows [y0, y1).  Thread c holds column x = x0 - TB + c (a halo of TB
-// columns each side; wrapped for periodic x).  The workgroup marches over the
-// input rows y0 - TB .. y1 - 1 + TB (wrapped for periodic y): each input row is
-// loaded once (prefetched one row ahead into registers) into the level-0 ring;
-// level l then produces row r_in - l from rows r - 1, r, r + 1 of level l - 1,
-// i.e. one step of pull-propagation + collision, and level TB writes the
-// output row.  Level l is valid on columns [l, C - l) and rows
-// [y0 - TB + l, y1 - 1 + TB - l]; nodes beyond a wall are never produced and
-// never read (the face rule at a boundary node reads the node itself).
+// columns each side; wrapped for periodic x) at every time level.  The
+// workgroup marches over the input rows y0 - TB .. y1 - 1 + TB (wrapped for
+// periodic y); when input row r_in arrives, level l produces row r_in - l from
+// rows r - 1, r, r + 1 of level l - 1 (one pull-propagation + collision), and
+// level TB writes the output row.
+//
+// Pull propagation takes the y-directions from the same column, so each level
+// keeps them in registers: the +y population of row r - 1, and the rest, +y
+// and -y populations of rows r and r + 1.  Only the two x-directions cross
+// columns; they go through LDS, two rows per level (ping-pong by row parity),
+// so one barrier per input row orders every LDS write after the reads of the
+// previous occupant of its slot.  Level l is valid on columns [l, C - l) and
+// rows [y0 - TB + l, y1 - 1 + TB - l]: a row outside that range (a uniform
+// condition) is skipped but still advances the register window; invalid
+// columns compute values that no valid node reads.  Nodes beyond a wall are
+// never read: the face rule at a boundary node reads the node itself.
+// Offsets within a plane are 32-bit (the host checks plane bytes < 4 GiB).
+// WALLS = false is the instantiation for a fully periodic domain: no face code.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int mod3(int r) { return ((r % 3) + 3) % 3; }
-
-template <int M, typename T, int TB, int C>
+template <int M, typename T, int TB, int C, bool WALLS>
 __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
                                                     const Consts<T>* __restrict__ cst, int seg_rows,
                                                     uint32_t tiles_x, int nontemporal) {
   using L = Lattice<2>;
   constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB;
-  __shared__ T ring[TB][3][P][C];
+  // D2Q5 order: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y.
+  static_assert(L::axis(1) == 0 && L::sgn(1) > 0 && L::axis(3) == 0 && L::sgn(3) < 0, "x directions");
+  static_assert(L::axis(2) == 1 && L::sgn(2) > 0 && L::axis(4) == 1 && L::sgn(4) < 0, "y directions");
+  constexpr int KXP = 1, KYP = 2, KXM = 3, KYM = 4;
+  // x-direction populations of each level's two most recent rows: [level][row parity][+x/-x][species][column]
+  __shared__ T xs[TB][2][2][M][C];
+
   const int c = (int)threadIdx.x;
+  const int cm = c > 0 ? c - 1 : 0, cp = c < C - 1 ? c + 1 : C - 1;
   const int nx = p.nx, ny = p.ny;
   const uint32_t tx = blockIdx.x % tiles_x;
   const uint32_t seg = blockIdx.x / tiles_x;
@@ -334,84 +349,128 @@ __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restri
   const bool px = p.bc[0] == BC_PERIODIC, py = p.bc[2] == BC_PERIODIC;
   const bool x_in = x >= 0 && x < nx;
   const bool col_ok = x_in || px;
-  const int xl = x_in ? x : (((x % nx) + nx) % nx);
+  const uint32_t xl = (uint32_t)(x_in ? x : (((x % nx) + nx) % nx));
+  // a tile that reaches an x wall (uniform): only there do x-pulls need the face rule
+  const bool tile_xwall = !px && (x0 - TB <= 0 || x0 - TB + C - 1 >= nx - 1);
+  const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
+  const bool lin = p.linearized != 0, srt = p.relax != 0;
+  const bool nt_ld = (nontemporal & NT_LOAD_ALIGNED) != 0;
+  const int nt_st = nontemporal & NT_STORE;
 
-  T reg[P];
+  // Per level (0 .. TB-1): +y of row r-1; rest/+y/-y of rows r (cur) and r+1 (nxt).
+  T yprev[TB][M], cur[TB][3][M], nxt[TB][3][M];
+#pragma unroll
+  for (int l = 0; l < TB; ++l)
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      yprev[l][i] = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
+    }
+
+  auto plane_src = [&](int pl) { return reinterpret_cast<const char*>(src + (int64_t)pl * p.plane); };
+  auto plane_dst = [&](int pl) { return reinterpret_cast<char*>(dst + (int64_t)pl * p.plane); };
+
+  T ld_row[P];
   auto load_row = [&](int r) {
     const bool r_in = r >= 0 && r < ny;
     const int rl = r_in ? r : (((r % ny) + ny) % ny);
     if (col_ok && (r_in || py)) {
-      const int64_t idx = (int64_t)rl * nx + xl;
+      const uint32_t off = ((uint32_t)rl * (uint32_t)nx + xl) * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) reg[pl] = ld(src + (int64_t)pl * p.plane + idx, (nontemporal & NT_LOAD_ALIGNED) != 0);
+      for (int pl = 0; pl < P; ++pl) ld_row[pl] = ld(reinterpret_cast<const T*>(plane_src(pl) + off), nt_ld);
     } else {
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) reg[pl] = T(0);
+      for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
     }
+  };
+  // Advance level l's window by one row; a computed row r also enters it (and LDS).
+  auto advance = [&](int l) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      yprev[l][i] = cur[l][1][i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i];
+    }
+  };
+  auto enter = [&](int l, int r, const T (&f)[M][Q]) {
+    const int s = r & 1;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      xs[l][s][0][i][c] = f[i][KXP];
+      xs[l][s][1][i][c] = f[i][KXM];
+      nxt[l][0][i] = f[i][0];
+      nxt[l][1][i] = f[i][KYP];
+      nxt[l][2][i] = f[i][KYM];
+    }
+  };
+  // Dirichlet face: 2 w xi_wall minus the node's own opposite population; zero flux: that population.
+  auto face = [&](int fk, int kb, int i, T back) {
+    return (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
   };
 
   const int r_last = y1 - 1 + TB;
   int r_in = y0 - TB;
   load_row(r_in);
   for (; r_in <= r_last; ++r_in) {
-    {
-      const int slot = mod3(r_in);
-#pragma unroll
-      for (int pl = 0; pl < P; ++pl) ring[0][slot][pl][c] = reg[pl];
-    }
     __syncthreads();
+    {
+      T f[M][Q];
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) f[i][k] = ld_row[i * Q + k];
+      advance(0);
+      enter(0, r_in, f);
+    }
     if (r_in < r_last) load_row(r_in + 1);
 #pragma unroll
     for (int lvl = 1; lvl <= TB; ++lvl) {
       const int r = r_in - lvl;
+      const int lp = lvl - 1;
+      const int s = r & 1;
       const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
-      const bool here = row_ok && c >= lvl && c < C - lvl && (px || x_in);
-      if (here) {
-        const int s0 = mod3(r), sm = mod3(r - 1), sp = mod3(r + 1);
-        T f[M][Q];
+      if (lvl < TB) advance(lvl);
+      if (!row_ok) continue;
+      T f[M][Q];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const int kb = L::opp(k);
-          const int a = L::axis(k), sg = L::sgn(k);
-          // the face direction k enters through, and whether its source lies beyond it
-          const int fk = a < 0 ? 0 : 2 * a + (sg > 0 ? 0 : 1);
-          bool wall = false;
-          if (a == 0) wall = !px && (sg > 0 ? x == 0 : x == nx - 1);
-          if (a == 1) wall = !py && (sg > 0 ? r == 0 : r == ny - 1);
+      for (int i = 0; i < M; ++i) {
+        f[i][0] = cur[lp][0][i];
+        f[i][KXP] = xs[lp][s][0][i][cm];
+        f[i][KXM] = xs[lp][s][1][i][cp];
+        f[i][KYP] = yprev[lp][i];
+        f[i][KYM] = nxt[lp][2][i];
+      }
+      if constexpr (WALLS) {
+        if (tile_xwall) {
 #pragma unroll
           for (int i = 0; i < M; ++i) {
-            T v;
-            if (wall) {
-              const T back = ring[lvl - 1][s0][i * Q + kb][c];
-              v = (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
-            } else if (a < 0) {
-              v = ring[lvl - 1][s0][i * Q + k][c];
-            } else if (a == 0) {
-              v = ring[lvl - 1][s0][i * Q + k][sg > 0 ? c - 1 : c + 1];
-            } else {
-              v = ring[lvl - 1][sg > 0 ? sm : sp][i * Q + k][c];
-            }
-            f[i][k] = v;
+            if (wall_xlo) f[i][KXP] = face(0, KXM, i, xs[lp][s][1][i][c]);
+            if (wall_xhi) f[i][KXM] = face(1, KXP, i, xs[lp][s][0][i][c]);
           }
         }
-        collide_node<2, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
-        if (lvl < TB) {
+        if (!py && r == 0) {
 #pragma unroll
-          for (int i = 0; i < M; ++i)
+          for (int i = 0; i < M; ++i) f[i][KYP] = face(2, KYM, i, cur[lp][2][i]);
+        }
+        if (!py && r == ny - 1) {
 #pragma unroll
-            for (int k = 0; k < Q; ++k) ring[lvl][s0][i * Q + k][c] = f[i][k];
-        } else if (c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
-          const int64_t idx = (int64_t)r * nx + x;
-#pragma unroll
-          for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-              store_value(dst + (int64_t)(i * Q + k) * p.plane + idx, f[i][k], nontemporal & NT_STORE);
+          for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, cur[lp][1][i]);
         }
       }
-      __syncthreads();
+      collide_node<2, M, T>(f, nc.R, nc.xref, lin, srt);
+      if (lvl < TB) {
+        enter(lvl, r, f);
+      } else if (c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
+        const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int k = 0; k < Q; ++k)
+            store_value(reinterpret_cast<T*>(plane_dst(i * Q + k) + off), f[i][k], nt_st);
+      }
     }
   }
 }
@@ -878,9 +937,16 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     constexpr int W = C - 2 * TB;
     const uint32_t tiles_x = (uint32_t)((a.p.nx + W - 1) / W);
     const uint32_t segs = (uint32_t)((a.p.ny + a.seg_rows - 1) / a.seg_rows);
-    hipLaunchKernelGGL((k_step_blocked<M, T, TB, C>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p,
-                       static_cast<const T*>(a.src), static_cast<T*>(a.dst), static_cast<const Consts<T>*>(a.consts),
-                       a.seg_rows, tiles_x, a.nontemporal);
+    const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
+    const T* src = static_cast<const T*>(a.src);
+    T* dst = static_cast<T*>(a.dst);
+    const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
+    if (walls)
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal);
+    else
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal);
     return hipSuccess;
   }
 }
@@ -889,6 +955,7 @@ template <int M, typename T>
 hipError_t launch_blocked(const LaunchArgs& a) {
   if (a.tb == 2) return launch_blocked_tb<M, T, 2>(a);
   if (a.tb == 3) return launch_blocked_tb<M, T, 3>(a);
+  if (a.tb == 4) return launch_blocked_tb<M, T, 4>(a);
   return hipErrorInvalidValue;
 }
 

@@ -83,16 +83,18 @@ struct LaunchArgs {
   int64_t fill_count = 0;
 };
 
-// Temporally blocked D2Q5 sweep (k_step_blocked): a workgroup of `cols`
-// threads keeps, for each of TB - 1 intermediate time levels and for the input,
-// a ring of three rows of m*5 planes in LDS.  cols is the widest of 256, 128, 64
-// whose rings fit in 64 KiB; 0 when none does.
-constexpr int kBlockedLdsBytes = 64 * 1024;
+// Temporally blocked D2Q5 sweep (k_step_blocked): workgroup width in columns
+// for m evolved species, tb steps per pass and value size `bytes`, or 0 when
+// the per-thread register window (7m values per time level plus one input row
+// of 5m) would take more than 90 VGPRs, so that the kernel keeps several waves
+// per SIMD without spilling.  The LDS exchange of the x-directions takes
+// tb * 2 rows * 2 directions * m * cols values.
+constexpr int kBlockedCols = 256;
 constexpr int blocked_cols(int m, int tb, int bytes) {
-  return (tb * 3 * m * 5 * 256 * bytes <= kBlockedLdsBytes)   ? 256
-         : (tb * 3 * m * 5 * 128 * bytes <= kBlockedLdsBytes) ? 128
-         : (tb * 3 * m * 5 * 64 * bytes <= kBlockedLdsBytes)  ? 64
-                                                               : 0;
+  return (tb >= 2 && tb <= 4 && (7 * m * tb + 5 * m) * bytes / 4 <= 90 &&
+          tb * 2 * 2 * m * kBlockedCols * bytes <= 64 * 1024)
+             ? kBlockedCols
+             : 0;
 }
 
 // Nodes per thread of the adjoint sweep (see k_adjoint_step).

@@ -119,17 +119,17 @@ class Sim:
         return TORCH_DTYPES[PRECISIONS[self.precision]]
 
     # -- calls --------------------------------------------------------------------
-    def set_launch(self, block_x=0, block_y=0, xcd_remap=None, lds_resident=1, nontemporal=0, vec=0,
-                   temporal=None, seg_rows=0):
-        cur = self.get_launch() if hasattr(self, "_h") else {}
-        if xcd_remap is None:
-            xcd_remap = 1 if self.lattice == "D3Q7" else 0
-        if temporal is None:
-            temporal = cur.get("temporal", 0)
+    def set_launch(self, **fields):
+        """Change the named fields of the launch configuration (msd_launch); the
+        others keep their current values (the library defaults after creation)."""
+        cur = self.get_launch()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise TypeError(f"unknown launch fields {sorted(unknown)}")
+        cur.update({k: int(v) for k, v in fields.items() if v is not None})
         l = F.MsdLaunch()
-        l.block_x, l.block_y, l.xcd_remap, l.lds_resident, l.nontemporal, l.vec = (
-            block_x, block_y, xcd_remap, lds_resident, nontemporal, vec)
-        l.temporal, l.seg_rows = int(temporal), int(seg_rows)
+        for k, v in cur.items():
+            setattr(l, k, v)
         F.check(self.lib.msd_set_launch(self._h, C.byref(l)), "msd_set_launch")
 
     def get_launch(self) -> dict:
@@ -137,6 +137,13 @@ class Sim:
         F.check(self.lib.msd_get_launch(self._h, C.byref(l)), "msd_get_launch")
         return {k: getattr(l, k) for k in ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec",
                                           "temporal", "seg_rows")}
+
+    def steps_per_pass(self) -> int:
+        """Time steps per launch of the sweep under the current launch configuration."""
+        n = int(self.lib.msd_steps_per_pass(self._h))
+        if n < 1:
+            F.check(n, "msd_steps_per_pass")
+        return n
 
     def init(self, xi0):
         """xi0: (N or N-1, *nodes) array or tensor; float32/float64."""

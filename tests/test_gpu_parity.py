@@ -101,10 +101,10 @@ def test_launch_configurations_are_bitwise_identical():
     D = rand_D(rng, 4)
     shape = (203, 67)
     xi0 = smooth_field(rng, 4, shape[::-1], 0.1)
-    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=dict(block_x=256, block_y=1, xcd_remap=0))
+    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=dict(block_x=256, block_y=1, xcd_remap=0, temporal=0))
     for launch in (dict(block_x=64, block_y=4), dict(block_x=128, block_y=2, nontemporal=1),
                    dict(block_x=192, block_y=1, xcd_remap=1), dict(block_x=64, block_y=1, xcd_remap=1)):
-        got = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=launch)
+        got = gpu_run("D2Q5", D, shape, "f32", xi0, 25, launch=dict(launch, temporal=0))
         for a, b in zip(ref, got):
             np.testing.assert_array_equal(a, b, err_msg=str(launch))
 
@@ -189,7 +189,7 @@ def test_vectorised_paths(lattice, vec, xface, precision):
     steps = 23
     orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls), xi0, steps)
     gpu = gpu_run(lattice, D, shape, precision, xi0, steps, bc=bc, xi_wall=walls,
-                  launch=dict(vec=vec, lds_resident=0))
+                  launch=dict(vec=vec, lds_resident=0, temporal=0))
     assert_parity(gpu, orc, precision, f"{lattice} vec={vec} {xface} {precision}")
 
 
@@ -201,10 +201,10 @@ def test_vector_widths_agree_to_rounding():
     D = rand_D(rng, 4)
     shape = (512, 37)
     xi0 = smooth_field(rng, 4, shape[::-1], 0.1)
-    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 17, launch=dict(vec=0))
+    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 17, launch=dict(vec=0, temporal=0))
     for launch in (dict(vec=1), dict(vec=2, block_x=64, block_y=4), dict(vec=4, block_x=128, block_y=2),
                    dict(vec=4, block_x=64, block_y=1, xcd_remap=0, nontemporal=7)):
-        got = gpu_run("D2Q5", D, shape, "f32", xi0, 17, launch=launch)
+        got = gpu_run("D2Q5", D, shape, "f32", xi0, 17, launch=dict(launch, temporal=0))
         np.testing.assert_allclose(got[0], ref[0], rtol=0, atol=2e-6, err_msg=str(launch))
 
 
@@ -241,7 +241,7 @@ BLOCKED_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
-@pytest.mark.parametrize("tb", [2, 3])
+@pytest.mark.parametrize("tb", [2, 3, 4])
 @pytest.mark.parametrize("N", [2, 3, 5])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_temporally_blocked_sweep(case, tb, N, precision):
@@ -270,8 +270,42 @@ def test_blocked_sweep_matches_single_step_sweep():
     D = rand_D(rng, 3)
     shape = (500, 97)
     xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
-    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(lds_resident=0))
-    for tb in (2, 3):
-        got = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(temporal=tb, lds_resident=0))
+    ref = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(lds_resident=0, temporal=0))
+    for tb in (2, 3, 4):
+        got = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(temporal=tb, seg_rows=16, lds_resident=0))
         for a, b in zip(ref, got):
             np.testing.assert_allclose(a, b, rtol=0, atol=2e-6)
+
+
+def test_steps_per_pass_plan():
+    """The library takes the largest pass its on-chip window allows for the species
+    count and precision, and one step per pass where it cannot fill the GPU."""
+    import torch
+
+    from paper_1808_06787_amd.sim import Sim
+
+    rng = np.random.default_rng(320)
+    cases = [  # (N, precision, shape, launch, expected steps per pass)
+        (3, "f32", (4096, 512), {}, 4),
+        (3, "f32", (4096, 4096), dict(temporal=4, seg_rows=0), 4),
+        (2, "f64", (2048, 512), {}, 4),
+        (4, "f32", (2048, 1024), {}, 3),
+        (5, "f32", (2048, 1024), {}, 2),
+        (3, "f64", (2048, 1024), {}, 2),
+        (4, "f64", (2048, 1024), {}, 1),
+        (3, "f32", (2048, 1024), dict(temporal=3), 3),
+        (3, "f32", (2048, 1024), dict(temporal=0), 1),
+        (3, "f32", (200, 100), {}, 1),
+        (3, "f32", (512, 512), {}, 1),
+        (3, "f32", (1024, 1024), {}, 4),
+        (3, "f32", (200, 100), dict(seg_rows=8), 4),
+    ]
+    for N, prec, shape, launch, want in cases:
+        sim = Sim("D2Q5", rand_D(rng, N), shape, prec)
+        if launch:
+            sim.set_launch(**launch)
+        assert sim.steps_per_pass() == want, (N, prec, shape, launch)
+        sim.close()
+    sim = Sim("D3Q7", rand_D(rng, 3), (64, 64, 64), "f32")
+    assert sim.steps_per_pass() == 1
+    sim.close()
