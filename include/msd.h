@@ -289,7 +289,13 @@ typedef struct msd_schedule {
   int32_t order;            /* enum msd_tile_order */
   int32_t xcd_remap;        /* 1: consecutive tiles of a launch on one XCD */
   int32_t nontemporal;      /* streaming-hint mask, as in msd_launch */
-  int32_t reserved[2];
+  int32_t temporal;         /* D2Q5: at most this many steps (2..4) per pass over HBM with the
+                               temporally blocked sweep, as in msd_launch (each class of equal
+                               N takes the largest count its on-chip window allows; classes
+                               then launch separately whatever `mode` says, and block_x,
+                               block_y, order apply to their single steps); 0 or 1: one step
+                               per launch.  Default 4 for D2Q5, 0 otherwise */
+  int32_t seg_rows;         /* rows per workgroup of the blocked sweep (0: 16) */
 } msd_schedule;
 
 /* Workspace bytes for a batch (every mixture's buffers and constants plus the

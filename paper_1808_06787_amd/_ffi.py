@@ -68,7 +68,8 @@ class MsdSchedule(C.Structure):
         ("order", C.c_int32),
         ("xcd_remap", C.c_int32),
         ("nontemporal", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("temporal", C.c_int32),
+        ("seg_rows", C.c_int32),
     ]
 
 

@@ -74,9 +74,12 @@ def tune_batch(batch, cache_path: Optional[str] = None, steps: int = 8, warmup: 
         batch.set_schedule(**cache[key]["best"])
         return cache[key]
     if candidates is None:
-        candidates = [dict(block_x=bx, block_y=by, mode=mode, order=order, xcd_remap=xcd)
+        candidates = [dict(block_x=bx, block_y=by, mode=mode, order=order, xcd_remap=xcd, temporal=0)
                       for (bx, by), mode, order, xcd in itertools.product(
                           BATCH_BLOCKS, ("fused", "per_class"), ("instance", "interleaved"), (0, 1))]
+        if batch.lattice == "D2Q5":
+            candidates += [dict(block_x=64, block_y=4, mode="per_class", order=order, temporal=tb, seg_rows=seg)
+                           for tb, seg, order in itertools.product((2, 3, 4), (8, 16, 32), ("instance", "interleaved"))]
     state, t0 = batch.save()
     trials = []
     for cand in candidates:

@@ -113,12 +113,20 @@ class Batch:
                 "msd_batch_diagnostics")
         return np.array(mass[:]), np.array(mn[:]), np.array(mx[:]), int(bad.value)
 
-    def set_schedule(self, block_x=64, block_y=4, mode="fused", order="instance", xcd_remap=0, nontemporal=0):
+    def set_schedule(self, **fields):
+        """Change the named fields of the tile schedule (msd_schedule); the others
+        keep their current values (the library defaults after creation)."""
+        cur = self.get_schedule()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise TypeError(f"unknown schedule fields {sorted(unknown)}")
+        cur.update({k: v for k, v in fields.items() if v is not None})
         s = F.MsdSchedule()
-        s.block_x, s.block_y = int(block_x), int(block_y)
-        s.mode = MODES[mode] if isinstance(mode, str) else int(mode)
-        s.order = ORDERS[order] if isinstance(order, str) else int(order)
-        s.xcd_remap, s.nontemporal = int(xcd_remap), int(nontemporal)
+        s.block_x, s.block_y = int(cur["block_x"]), int(cur["block_y"])
+        s.mode = MODES[cur["mode"]] if isinstance(cur["mode"], str) else int(cur["mode"])
+        s.order = ORDERS[cur["order"]] if isinstance(cur["order"], str) else int(cur["order"])
+        s.xcd_remap, s.nontemporal = int(cur["xcd_remap"]), int(cur["nontemporal"])
+        s.temporal, s.seg_rows = int(cur["temporal"]), int(cur["seg_rows"])
         F.check(self.lib.msd_batch_set_schedule(self._h, C.byref(s)), "msd_batch_set_schedule")
 
     def get_schedule(self) -> dict:
@@ -127,7 +135,7 @@ class Batch:
         inv_m = {v: k for k, v in MODES.items()}
         inv_o = {v: k for k, v in ORDERS.items()}
         return dict(block_x=s.block_x, block_y=s.block_y, mode=inv_m[s.mode], order=inv_o[s.order],
-                    xcd_remap=s.xcd_remap, nontemporal=s.nontemporal)
+                    xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows)
 
     def state_bytes(self) -> int:
         return int(self.lib.msd_batch_state_bytes(self._h))

@@ -24,12 +24,19 @@ struct Member {
   size_t consts_off = 0, half_off[2] = {0, 0}, state_bytes = 0;
   int diag_blocks = 0;
   bool initialised = false;
+  int cur = 0;               // which half holds the state
   msd_launch single;         // launch of the single-mixture sweep (reference schedule)
 };
 
+// Mixtures launched together.  Blocked ranges (tb >= 2, one species count)
+// also have a table of blocked tiles; the one-step tiles serve their first step
+// and remainders.  Every mixture of a range has the same `cur`.
 struct Range {
-  int mmax;
-  uint32_t begin, count;
+  int mmax = 0;
+  uint32_t begin = 0, count = 0;
+  int tb = 0, seg = 0, walls = 0;
+  uint32_t bbegin = 0, bcount = 0;
+  std::vector<int> members;
 };
 
 struct BatchLayout {
@@ -57,8 +64,9 @@ BatchLayout batch_layout(const msd_problem* probs, int32_t count) {
   size_t off = 0;
   L.desc_off = off;
   off = align_up(off + sizeof(msd::BatchInst) * (size_t)count, 256);
+  // one-step tiles of 64 x 1 nodes at most, plus at most as many blocked tiles
   for (int32_t b = 0; b < count; ++b)
-    L.max_tiles += (probs[b].nx + 63) / 64 * probs[b].ny * probs[b].nz;
+    L.max_tiles += 2 * ((probs[b].nx + 63) / 64 * probs[b].ny * probs[b].nz);
   L.tiles_off = off;
   off = align_up(off + sizeof(msd::BatchTile) * (size_t)L.max_tiles, 256);
   L.partials_off = off;
@@ -94,7 +102,6 @@ struct msd_batch {
   std::vector<msd::BatchTile> h_tiles;
   std::vector<Range> ranges;
   msd_schedule sched{};
-  int cur = 0;
   int64_t t = 0;
 };
 
@@ -118,12 +125,46 @@ msd::LaunchArgs member_args(const msd_batch* b, int idx) {
   return a;
 }
 
+// Steps per pass for a class of `m` evolved species under schedule `sc`: the
+// largest count up to sc.temporal whose on-chip window fits, 0 for one step.
+int class_steps_per_pass(const msd_batch* b, const std::vector<int>& g, int m) {
+  if (b->lattice != MSD_D2Q5 || b->sched.temporal < 2) return 0;
+  for (int i : g)
+    if ((uint64_t)b->mem[i].plane * (uint64_t)b->prec >= (1ull << 32)) return 0;
+  for (int t = b->sched.temporal; t >= 2; --t)
+    if (msd::blocked_cols(m, t, b->prec) > 0) return t;
+  return 0;
+}
+
+void push_tiles(std::vector<msd::BatchTile>& out, const std::vector<int>& g, const std::vector<uint32_t>& nt,
+                int order) {
+  uint32_t most = 0;
+  for (uint32_t n : nt) most = std::max(most, n);
+  if (order == MSD_ORDER_INTERLEAVED) {
+    for (uint32_t k = 0; k < most; ++k)
+      for (size_t j = 0; j < g.size(); ++j)
+        if (k < nt[j]) out.push_back({(uint32_t)g[j], k});
+  } else {
+    for (size_t j = 0; j < g.size(); ++j)
+      for (uint32_t k = 0; k < nt[j]; ++k) out.push_back({(uint32_t)g[j], k});
+  }
+}
+
 int build_tiles(msd_batch* b) {
   const msd_schedule& sc = b->sched;
+  // launches over several mixtures need them on the same buffer half
+  for (Member& M : b->mem) {
+    if (M.cur == 0) continue;
+    const hipError_t e = hipMemcpyAsync(b->ws + M.half_off[0], b->ws + M.half_off[1], M.state_bytes,
+                                        hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch state move");
+    M.cur = 0;
+  }
   std::vector<int> idx(b->count);
   for (int i = 0; i < b->count; ++i) idx[i] = i;
   std::vector<std::vector<int>> groups;
-  if (sc.mode == MSD_BATCH_PER_CLASS) {
+  const bool by_class = sc.mode == MSD_BATCH_PER_CLASS || (b->lattice == MSD_D2Q5 && sc.temporal >= 2);
+  if (by_class) {
     for (int m = 1; m < MSD_MAX_SPECIES; ++m) {
       std::vector<int> g;
       for (int i : idx)
@@ -137,27 +178,31 @@ int build_tiles(msd_batch* b) {
   b->ranges.clear();
   for (const auto& g : groups) {
     Range r;
-    r.mmax = 0;
+    r.members = g;
     r.begin = (uint32_t)b->h_tiles.size();
     std::vector<uint32_t> nt(g.size());
-    uint32_t most = 0;
     for (size_t j = 0; j < g.size(); ++j) {
       const msd_problem& p = b->mem[g[j]].prob;
       const uint32_t tx = (uint32_t)((p.nx + sc.block_x - 1) / sc.block_x);
       const uint32_t ty = (uint32_t)((p.ny + sc.block_y - 1) / sc.block_y);
       nt[j] = tx * ty * (uint32_t)p.nz;
-      most = std::max(most, nt[j]);
       r.mmax = std::max(r.mmax, b->mem[g[j]].m);
     }
-    if (sc.order == MSD_ORDER_INTERLEAVED) {
-      for (uint32_t k = 0; k < most; ++k)
-        for (size_t j = 0; j < g.size(); ++j)
-          if (k < nt[j]) b->h_tiles.push_back({(uint32_t)g[j], k});
-    } else {
-      for (size_t j = 0; j < g.size(); ++j)
-        for (uint32_t k = 0; k < nt[j]; ++k) b->h_tiles.push_back({(uint32_t)g[j], k});
-    }
+    push_tiles(b->h_tiles, g, nt, sc.order);
     r.count = (uint32_t)b->h_tiles.size() - r.begin;
+    if (by_class) r.tb = class_steps_per_pass(b, g, r.mmax);
+    if (r.tb >= 2) {
+      r.seg = sc.seg_rows > 0 ? sc.seg_rows : 16;
+      const int64_t W = msd::kBlockedCols - 2 * r.tb;
+      r.bbegin = (uint32_t)b->h_tiles.size();
+      for (size_t j = 0; j < g.size(); ++j) {
+        const msd_problem& p = b->mem[g[j]].prob;
+        nt[j] = (uint32_t)(((p.nx + W - 1) / W) * ((p.ny + r.seg - 1) / r.seg));
+        if (p.bc[0] != MSD_BC_PERIODIC || p.bc[2] != MSD_BC_PERIODIC) r.walls = 1;
+      }
+      push_tiles(b->h_tiles, g, nt, sc.order);
+      r.bcount = (uint32_t)b->h_tiles.size() - r.bbegin;
+    }
     b->ranges.push_back(r);
   }
   if ((int64_t)b->h_tiles.size() > b->L.max_tiles) return fail(MSD_EINVAL, "tile table overflow");
@@ -248,6 +293,8 @@ int msd_batch_create(const msd_problem* problems, int32_t count, void* d_ws, siz
   b->sched.order = MSD_ORDER_INSTANCE;
   b->sched.xcd_remap = 0;
   b->sched.nontemporal = 0;
+  b->sched.temporal = b->lattice == MSD_D2Q5 ? 4 : 0;
+  b->sched.seg_rows = 0;
   const int s2 = build_tiles(b);
   if (s2 != MSD_OK) {
     delete b;
@@ -265,6 +312,8 @@ int msd_batch_set_schedule(msd_batch* b, const msd_schedule* sc) {
   if (sc->order != MSD_ORDER_INSTANCE && sc->order != MSD_ORDER_INTERLEAVED)
     return fail(MSD_EINVAL, "order %d", sc->order);
   if (sc->nontemporal < 0 || sc->nontemporal > 7) return fail(MSD_EINVAL, "nontemporal %d", sc->nontemporal);
+  if (sc->temporal < 0 || sc->temporal > 4) return fail(MSD_EINVAL, "temporal = %d must be 0..4", sc->temporal);
+  if (sc->seg_rows < 0 || sc->seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", sc->seg_rows);
   b->sched = *sc;
   return build_tiles(b);
 }
@@ -285,7 +334,7 @@ int msd_batch_init(msd_batch* b, int32_t index, const void* d_xi0, int32_t xi0_p
   if (!d_xi0) return fail(MSD_EINVAL, "xi0 is NULL");
   if (xi0_precision != MSD_F32 && xi0_precision != MSD_F64) return fail(MSD_EINVAL, "xi0_precision %d", xi0_precision);
   if (b->t != 0) return fail(MSD_ESTATE, "batch mixtures are initialised at time 0 only");
-  b->cur = 0;
+  b->mem[index].cur = 0;
   msd::LaunchArgs a = member_args(b, index);
   a.consts_out = b->ws + b->mem[index].consts_off;
   hipError_t e = dispatch(msd::Op::Constants, a);
@@ -321,19 +370,37 @@ int msd_batch_step(msd_batch* b, int64_t nsteps) {
   a.block_y = b->sched.block_y;
   a.xcd_remap = b->sched.xcd_remap;
   a.nontemporal = b->sched.nontemporal;
-  for (int64_t n = 0; n < nsteps; ++n) {
-    a.cur = b->cur;
-    a.pull = b->t > 0 ? 1 : 0;
-    for (const Range& r : b->ranges) {
-      a.m = r.mmax;
-      a.tile_begin = r.begin;
-      a.ntiles = r.count;
-      const hipError_t e = dispatch(msd::Op::BatchStep, a);
+  // each range runs its own sequence of launches (the mixtures are independent)
+  for (const Range& r : b->ranges) {
+    int cur = b->mem[r.members[0]].cur;
+    a.m = r.mmax;
+    int64_t n = 0;
+    while (n < nsteps) {
+      const int64_t t = b->t + n;
+      a.cur = cur;
+      int64_t done = 1;
+      hipError_t e;
+      if (r.tb >= 2 && t > 0 && nsteps - n >= r.tb) {
+        a.tb = r.tb;
+        a.seg_rows = r.seg;
+        a.walls = r.walls;
+        a.tile_begin = r.bbegin;
+        a.ntiles = r.bcount;
+        e = dispatch(msd::Op::BatchStepBlocked, a);
+        done = r.tb;
+      } else {
+        a.pull = t > 0 ? 1 : 0;
+        a.tile_begin = r.begin;
+        a.ntiles = r.count;
+        e = dispatch(msd::Op::BatchStep, a);
+      }
       if (e != hipSuccess) return hip_fail(e, "batched step kernel");
+      cur = 1 - cur;
+      n += done;
     }
-    b->cur = 1 - b->cur;
-    b->t += 1;
+    for (int i : r.members) b->mem[i].cur = cur;
   }
+  b->t += nsteps;
   return MSD_OK;
 }
 
@@ -344,14 +411,15 @@ int msd_batch_step_each(msd_batch* b, int64_t nsteps) {
   if (st != MSD_OK) return st;
   for (int64_t n = 0; n < nsteps; ++n) {
     for (int i = 0; i < b->count; ++i) {
+      Member& M = b->mem[i];
       msd::LaunchArgs a = member_args(b, i);
-      a.src = b->ws + b->mem[i].half_off[b->cur];
-      a.dst = b->ws + b->mem[i].half_off[1 - b->cur];
+      a.src = b->ws + M.half_off[M.cur];
+      a.dst = b->ws + M.half_off[1 - M.cur];
       a.pull = b->t > 0 ? 1 : 0;
       const hipError_t e = dispatch(msd::Op::Step, a);
       if (e != hipSuccess) return hip_fail(e, "step kernel");
+      M.cur = 1 - M.cur;
     }
-    b->cur = 1 - b->cur;
     b->t += 1;
   }
   return MSD_OK;
@@ -364,7 +432,7 @@ int msd_batch_read_moments(msd_batch* b, int32_t index, int32_t out_precision, v
   if (!b->mem[index].initialised) return fail(MSD_ESTATE, "mixture %d not initialised", index);
   if (out_precision != MSD_F32 && out_precision != MSD_F64) return fail(MSD_EINVAL, "out_precision %d", out_precision);
   msd::LaunchArgs a = member_args(b, index);
-  a.src = b->ws + b->mem[index].half_off[b->cur];
+  a.src = b->ws + b->mem[index].half_off[b->mem[index].cur];
   a.pull = b->t > 0 ? 1 : 0;
   a.out_prec = out_precision;
   a.out_xi = d_xi;
@@ -381,7 +449,7 @@ int msd_batch_diagnostics(msd_batch* b, int32_t index, double* h_mass, double* h
   if (st != MSD_OK) return st;
   if (!b->mem[index].initialised) return fail(MSD_ESTATE, "mixture %d not initialised", index);
   msd::LaunchArgs a = member_args(b, index);
-  a.src = b->ws + b->mem[index].half_off[b->cur];
+  a.src = b->ws + b->mem[index].half_off[b->mem[index].cur];
   a.pull = b->t > 0 ? 1 : 0;
   a.partials = reinterpret_cast<double*>(b->ws + b->L.partials_off);
   a.diag_out = reinterpret_cast<double*>(b->ws + b->L.diag_out_off);
@@ -419,7 +487,7 @@ int msd_batch_save(const msd_batch* b, void* d_dst, int64_t* h_step) {
   char* dst = static_cast<char*>(d_dst);
   for (const Member& M : b->mem) {
     const hipError_t e =
-        hipMemcpyAsync(dst, b->ws + M.half_off[b->cur], M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
+        hipMemcpyAsync(dst, b->ws + M.half_off[M.cur], M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch save copy");
     dst += M.state_bytes;
   }
@@ -435,7 +503,7 @@ int msd_batch_restore(msd_batch* b, const void* d_src, int64_t step) {
   const char* src = static_cast<const char*>(d_src);
   for (const Member& M : b->mem) {
     const hipError_t e =
-        hipMemcpyAsync(b->ws + M.half_off[b->cur], src, M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
+        hipMemcpyAsync(b->ws + M.half_off[M.cur], src, M.state_bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch restore copy");
     src += M.state_bytes;
   }

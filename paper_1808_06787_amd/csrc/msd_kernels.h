@@ -325,9 +325,9 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
 // WALLS = false is the instantiation for a fully periodic domain: no face code.
 // ---------------------------------------------------------------------------
 template <int M, typename T, int TB, int C, bool WALLS>
-__global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
-                                                    const Consts<T>* __restrict__ cst, int seg_rows,
-                                                    uint32_t tiles_x, int nontemporal) {
+__device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
+                                             const Consts<T>* __restrict__ cst, int seg_rows, uint32_t tx,
+                                             uint32_t seg, int nontemporal) {
   using L = Lattice<2>;
   constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB;
   // D2Q5 order: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y.
@@ -340,8 +340,6 @@ __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restri
   const int c = (int)threadIdx.x;
   const int cm = c > 0 ? c - 1 : 0, cp = c < C - 1 ? c + 1 : C - 1;
   const int nx = p.nx, ny = p.ny;
-  const uint32_t tx = blockIdx.x % tiles_x;
-  const uint32_t seg = blockIdx.x / tiles_x;
   const int x0 = (int)tx * W;
   const int y0 = (int)seg * seg_rows;
   const int y1 = min(y0 + seg_rows, ny);
@@ -473,6 +471,33 @@ __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restri
       }
     }
   }
+}
+
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
+                                                    const Consts<T>* __restrict__ cst, int seg_rows,
+                                                    uint32_t tiles_x, int nontemporal) {
+  blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
+                                   nontemporal);
+}
+
+// The blocked sweep over the mixtures of one batch class (equal m): workgroup
+// g takes tile table entry tile_begin + g, i.e. (mixture, column tile + segment
+// * column tiles of that mixture); cur selects each mixture's source buffer.
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __restrict__ insts,
+                                                          const BatchTile* __restrict__ tiles, uint32_t tile_begin,
+                                                          char* __restrict__ ws, int cur, int seg_rows,
+                                                          int nontemporal) {
+  constexpr int W = C - 2 * TB;
+  const BatchTile bt = tiles[tile_begin + blockIdx.x];
+  const BatchInst* I = insts + bt.inst;
+  const Problem& p = I->p;
+  const uint32_t tiles_x = (uint32_t)((p.nx + W - 1) / W);
+  const T* src = reinterpret_cast<const T*>(ws + I->half_off[cur]);
+  T* dst = reinterpret_cast<T*>(ws + I->half_off[1 - cur]);
+  const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + I->consts_off);
+  blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, bt.tile % tiles_x, bt.tile / tiles_x, nontemporal);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,6 +976,31 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
   }
 }
 
+template <int M, typename T, int TB>
+hipError_t launch_batch_blocked_tb(const LaunchArgs& a) {
+  constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
+  if constexpr (C == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.ntiles == 0) return hipSuccess;
+    if (a.walls)
+      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), dim3(a.ntiles), dim3(C), 0, a.stream, a.insts,
+                         a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+    else
+      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), dim3(a.ntiles), dim3(C), 0, a.stream, a.insts,
+                         a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+    return hipSuccess;
+  }
+}
+
+template <int M, typename T>
+hipError_t launch_batch_blocked(const LaunchArgs& a) {
+  if (a.tb == 2) return launch_batch_blocked_tb<M, T, 2>(a);
+  if (a.tb == 3) return launch_batch_blocked_tb<M, T, 3>(a);
+  if (a.tb == 4) return launch_batch_blocked_tb<M, T, 4>(a);
+  return hipErrorInvalidValue;
+}
+
 template <int M, typename T>
 hipError_t launch_blocked(const LaunchArgs& a) {
   if (a.tb == 2) return launch_blocked_tb<M, T, 2>(a);
@@ -1073,6 +1123,14 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::StepBlocked:
       if constexpr (LAT == 2) {
         const hipError_t e = launch_blocked<M, T>(a);
+        if (e != hipSuccess) return e;
+      } else {
+        return hipErrorInvalidValue;
+      }
+      break;
+    case Op::BatchStepBlocked:
+      if constexpr (LAT == 2) {
+        const hipError_t e = launch_batch_blocked<M, T>(a);
         if (e != hipSuccess) return e;
       } else {
         return hipErrorInvalidValue;

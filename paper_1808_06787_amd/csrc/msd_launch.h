@@ -10,7 +10,7 @@ namespace msd {
 
 enum class Op {
   Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
-  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked
+  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked, BatchStepBlocked
 };
 
 // Constants block written once per problem by the setup kernel and read by
@@ -58,6 +58,7 @@ struct LaunchArgs {
   int vec = 1;               // nodes per thread of the vectorised sweep (0: general kernel)
   int tb = 0;                // steps per pass of the temporally blocked sweep
   int seg_rows = 32;         // rows per workgroup segment of the blocked sweep
+  int walls = 0;             // blocked batch launch: some mixture has a non-periodic face
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;
