@@ -189,8 +189,9 @@ def batched_extra(steps: int = 1000, warmup: int = 5):
 
 def adjoint_extra():
     """Gradient workload: 1024^2 ternary D2Q5, 2000 steps, checkpoints every 100.
-    FP32: time of the plain forward run, of the checkpointed forward run and of the
-    backward pass (recompute + adjoint).  FP64: the adjoint gradients against central
+    Per precision: time of the plain forward run (default launch, and one step per
+    pass), of the checkpointed forward run and of the backward pass (recompute +
+    adjoint).  FP64: the adjoint gradients against central
     differences (h = 1e-4) for the three D_ij pairs and one direction of the
     initial field."""
     import torch
@@ -233,6 +234,11 @@ def adjoint_extra():
         del ck
         s.init(torch.from_numpy(w.xi0))
         t_plain, _ = events(lambda: s.step(w.steps))
+        launch = s.get_launch()
+        s.set_launch(temporal=0)
+        s.init(torch.from_numpy(w.xi0))
+        t_plain1, _ = events(lambda: s.step(w.steps))
+        s.set_launch(temporal=launch["temporal"])
         s.init(torch.from_numpy(w.xi0))
         t_fwd, ck = events(lambda: adjoint.forward_with_checkpoints(s, w.steps, every))
         xi = s.read(torch.float64, flux=False, grad=False)[0]
@@ -241,7 +247,9 @@ def adjoint_extra():
         s.close()
         del ck
         res[prec] = {"loss": L, "forward_s": round(t_plain, 4), "forward_checkpointed_s": round(t_fwd, 4),
-                     "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3)}
+                     "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3),
+                     "forward_one_step_per_pass_s": round(t_plain1, 4),
+                     "backward_over_forward_one_step_per_pass": round(t_bwd / t_plain1, 3)}
         if prec == "f64":
             h = 1e-4
 

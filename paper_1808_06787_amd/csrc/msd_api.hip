@@ -222,13 +222,14 @@ struct BlockedPlan {
   int seg = 0;
 };
 
-BlockedPlan blocked_plan(const msd_sim* s) {
+BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   BlockedPlan pl;
   if (s->prob.lattice != MSD_D2Q5) return pl;
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)
-    if (msd::blocked_cols(s->m, t, s->prob.precision) > 0) {
+    if ((adjoint ? msd::adjoint_blocked_cols(s->m, t, s->prob.precision)
+                 : msd::blocked_cols(s->m, t, s->prob.precision)) > 0) {
       tb = t;
       break;
     }
@@ -497,12 +498,27 @@ int msd_record(msd_sim* s, int64_t nsteps, void* d_stack) {
   const size_t sb = msd_state_bytes(s);
   char* stack = static_cast<char*>(d_stack);
   msd::LaunchArgs a = base_args(s);
-  for (int64_t n = 0; n < nsteps; ++n) {
+  const BlockedPlan plan = blocked_plan(s);
+  int64_t n = 0;
+  while (n < nsteps) {
     a.src = n == 0 ? (const void*)(s->ws + s->L.half_off[s->cur]) : (const void*)(stack + (size_t)(n - 1) * sb);
     a.dst = stack + (size_t)n * sb;
     a.pull = (s->t + n) > 0 ? 1 : 0;
-    const hipError_t e = dispatch(msd::Op::Step, a);
+    int64_t done = 1;
+    hipError_t e;
+    if (plan.tb >= 2 && s->t + n > 0 && nsteps - n >= plan.tb) {
+      // one pass writes the states after each of its steps into consecutive slots
+      a.tb = plan.tb;
+      a.seg_rows = plan.seg;
+      a.rec_stride = (int64_t)(sb / (size_t)s->prob.precision);
+      e = dispatch(msd::Op::StepBlocked, a);
+      a.rec_stride = 0;
+      done = plan.tb;
+    } else {
+      e = dispatch(msd::Op::Step, a);
+    }
     if (e != hipSuccess) return hip_fail(e, "step kernel");
+    n += done;
   }
   const hipError_t e = hipMemcpyAsync(s->ws + s->L.half_off[s->cur], stack + (size_t)(nsteps - 1) * sb, sb,
                                       hipMemcpyDeviceToDevice, s->stream);
@@ -511,11 +527,22 @@ int msd_record(msd_sim* s, int64_t nsteps, void* d_stack) {
   return MSD_OK;
 }
 
+// Workgroup slots of the dL/dR accumulator: enough for the one-step adjoint
+// tiling and for the blocked adjoint's (tile, segment) workgroups.
+static int64_t adjoint_slots(const msd_sim* s) {
+  const int64_t bx = (int64_t)s->launch.block_x * msd::kAdjointNodesPerThread, by = s->launch.block_y;
+  int64_t slots = (s->prob.nx + bx - 1) / bx * ((s->prob.ny + by - 1) / by) * s->prob.nz;
+  const BlockedPlan plan = blocked_plan(s, true);
+  if (plan.tb >= 2) {
+    const int64_t W = msd::kBlockedCols - 2 * plan.tb;
+    slots = std::max<int64_t>(slots, (s->prob.nx + W - 1) / W * ((s->prob.ny + plan.seg - 1) / plan.seg));
+  }
+  return slots;
+}
+
 size_t msd_adjoint_accum_bytes(const msd_sim* s) {
   if (!s) return 0;
-  const int64_t bx = (int64_t)s->launch.block_x * msd::kAdjointNodesPerThread, by = s->launch.block_y;
-  const int64_t tiles = (s->prob.nx + bx - 1) / bx * ((s->prob.ny + by - 1) / by) * s->prob.nz;
-  return sizeof(double) * (size_t)tiles * s->m * (s->m + 1);
+  return sizeof(double) * (size_t)adjoint_slots(s) * s->m * (s->m + 1);
 }
 
 int msd_adjoint_begin(msd_sim* s, void* d_accum) {
@@ -563,19 +590,41 @@ int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_stat
     return fail(MSD_EINVAL, "NULL argument");
   if (t_lo < 0 || t_hi < t_lo) return fail(MSD_EINVAL, "steps (%lld, %lld]", (long long)t_lo, (long long)t_hi);
   if (t_hi - t_lo > 1 && !d_stack) return fail(MSD_EINVAL, "stack is NULL");
+  if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
+  if (d_adj_a == d_adj_b) return fail(MSD_EINVAL, "the two adjoint buffers must differ");
   const size_t sb = msd_state_bytes(s);
   void* a = d_adj_a;
   void* b = d_adj_b;
   int in_b = 0;
-  for (int64_t t = t_hi; t > t_lo; --t) {
-    const void* prev = (t - 1 == t_lo) ? d_state_lo
-                                       : (const void*)(static_cast<const char*>(d_stack) + (size_t)(t - t_lo - 2) * sb);
-    const int st = msd_adjoint_step(s, t, prev, a, b, d_accum);
-    if (st != MSD_OK) return st;
+  // s_j for t_lo <= j < t_hi: the segment's first state, else its stack slot
+  auto state = [&](int64_t j) {
+    return j == t_lo ? d_state_lo : (const void*)(static_cast<const char*>(d_stack) + (size_t)(j - t_lo - 1) * sb);
+  };
+  const BlockedPlan plan = blocked_plan(s, true);
+  int64_t t = t_hi;
+  while (t > t_lo) {
+    int64_t done = 1;
+    if (plan.tb >= 2 && t - plan.tb >= std::max<int64_t>(t_lo, 1)) {
+      // adjoint steps t .. t - tb + 1 in one pass; every level pulls its state
+      msd::LaunchArgs la = base_args(s);
+      for (int l = 1; l <= plan.tb; ++l) la.states[l - 1] = state(t - l);
+      la.adj_in = a;
+      la.dst = b;
+      la.tb = plan.tb;
+      la.seg_rows = plan.seg;
+      la.partials = static_cast<double*>(d_accum);
+      const hipError_t e = dispatch(msd::Op::AdjointBlocked, la);
+      if (e != hipSuccess) return hip_fail(e, "blocked adjoint kernel");
+      done = plan.tb;
+    } else {
+      const int st = msd_adjoint_step(s, t, state(t - 1), a, b, d_accum);
+      if (st != MSD_OK) return st;
+    }
     void* tmp = a;
     a = b;
     b = tmp;
     in_b ^= 1;
+    t -= done;
   }
   *h_result_in_b = in_b;
   return MSD_OK;
@@ -593,6 +642,7 @@ int msd_adjoint_finish(msd_sim* s, const void* d_adj0, const void* d_accum, doub
   }
   if (h_dL_dD) {
     a.partials = static_cast<double*>(const_cast<void*>(d_accum));
+    a.accum_slots = adjoint_slots(s);
     a.diag_out = reinterpret_cast<double*>(s->ws + s->L.diag_out_off);
     e = dispatch(msd::Op::AdjointDD, a);
     if (e != hipSuccess) return hip_fail(e, "adjoint diffusivity kernel");

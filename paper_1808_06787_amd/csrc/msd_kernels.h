@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
 template <int M, typename T, int TB, int C, bool WALLS>
 __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
                                              const Consts<T>* __restrict__ cst, int seg_rows, uint32_t tx,
-                                             uint32_t seg, int nontemporal) {
+                                             uint32_t seg, int nontemporal, int64_t rec_stride = 0) {
   using L = Lattice<2>;
   constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB;
   // D2Q5 order: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y.
@@ -369,7 +369,6 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     }
 
   auto plane_src = [&](int pl) { return reinterpret_cast<const char*>(src + (int64_t)pl * p.plane); };
-  auto plane_dst = [&](int pl) { return reinterpret_cast<char*>(dst + (int64_t)pl * p.plane); };
 
   T ld_row[P];
   auto load_row = [&](int r) {
@@ -459,15 +458,18 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
         }
       }
       collide_node<2, M, T>(f, nc.R, nc.xref, lin, srt);
-      if (lvl < TB) {
-        enter(lvl, r, f);
-      } else if (c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
+      if (lvl < TB) enter(lvl, r, f);
+      // the last level is the pass's output; recording (rec_stride > 0, uniform)
+      // also stores every intermediate level, level l at dst + (l - 1) rec_stride
+      if ((lvl == TB || rec_stride > 0) && c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
         const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+        T* out = dst + (rec_stride > 0 ? (int64_t)(lvl - 1) * rec_stride : 0);
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
           for (int k = 0; k < Q; ++k)
-            store_value(reinterpret_cast<T*>(plane_dst(i * Q + k) + off), f[i][k], nt_st);
+            store_value(reinterpret_cast<T*>(reinterpret_cast<char*>(out + (int64_t)(i * Q + k) * p.plane) + off),
+                        f[i][k], nt_st);
       }
     }
   }
@@ -476,9 +478,9 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
 template <int M, typename T, int TB, int C, bool WALLS>
 __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
                                                     const Consts<T>* __restrict__ cst, int seg_rows,
-                                                    uint32_t tiles_x, int nontemporal) {
+                                                    uint32_t tiles_x, int nontemporal, int64_t rec_stride) {
   blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
-                                   nontemporal);
+                                   nontemporal, rec_stride);
 }
 
 // The blocked sweep over the mixtures of one batch class (equal m): workgroup
@@ -891,6 +893,232 @@ __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Temporally blocked adjoint sweep (D2Q5): TB adjoint steps per pass, for the
+// forward steps t, t-1, ..., t-TB+1.  Level 0 holds a_t (read once); level l
+// produces a_{t-l} from level l-1 through the transposed propagation and from
+// the state s_{t-l}, pulled straight from memory.  The transposed pull takes
+// the y-directions from the same column (u_+y(r) = a_+y(r+1), u_-y(r) =
+// a_-y(r-1)), so each level keeps a register window as the forward blocked
+// sweep does, with the x-directions exchanged through LDS.  dL/dR is summed
+// only over the nodes a workgroup owns (its output rows and columns at every
+// level), so overlapping halos are not counted twice; the per-workgroup FP64
+// sum goes to accumulator slot blockIdx.x.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjStates {
+  const T* s[4];   // s[l - 1] = s_{t-l}
+};
+
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S, const T* __restrict__ adj_in,
+                                                       T* __restrict__ adj_out, const Consts<T>* __restrict__ cst,
+                                                       int seg_rows, uint32_t tiles_x, double* __restrict__ racc) {
+  using L = Lattice<2>;
+  constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB, E = M * (M + 1);
+  static_assert(L::axis(1) == 0 && L::sgn(1) > 0 && L::axis(3) == 0 && L::sgn(3) < 0, "x directions");
+  static_assert(L::axis(2) == 1 && L::sgn(2) > 0 && L::axis(4) == 1 && L::sgn(4) < 0, "y directions");
+  constexpr int KXP = 1, KYP = 2, KXM = 3, KYM = 4;
+  __shared__ T xs[TB][2][2][M][C];
+  __shared__ double red[C / 64][E];
+
+  const int c = (int)threadIdx.x;
+  const int cm = c > 0 ? c - 1 : 0, cp = c < C - 1 ? c + 1 : C - 1;
+  const int nx = p.nx, ny = p.ny;
+  const uint32_t tx = blockIdx.x % tiles_x;
+  const uint32_t seg = blockIdx.x / tiles_x;
+  const int x0 = (int)tx * W;
+  const int y0 = (int)seg * seg_rows;
+  const int y1 = min(y0 + seg_rows, ny);
+  const int x = x0 - TB + c;
+  const bool px = p.bc[0] == BC_PERIODIC, py = p.bc[2] == BC_PERIODIC;
+  const bool x_in = x >= 0 && x < nx;
+  const bool col_ok = x_in || px;
+  const bool col_own = c >= TB && c < C - TB && x_in;
+  const int xl = x_in ? x : (((x % nx) + nx) % nx);
+  // neighbour columns of the pull from a state (wrapped; at a wall the face rule applies instead)
+  const int xlm = xl > 0 ? xl - 1 : nx - 1, xlp = xl < nx - 1 ? xl + 1 : 0;
+  const bool tile_xwall = !px && (x0 - TB <= 0 || x0 - TB + C - 1 >= nx - 1);
+  const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
+  NodeConsts<M, T> nc;
+  load_consts<M, T>(cst, nc);
+  const bool lin = p.linearized != 0, srt = p.relax != 0;
+  double Rbar[M][M + 1];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= M; ++j) Rbar[i][j] = 0.0;
+
+  // Per level (0 .. TB-1): -y of row r-1; rest/+y/-y of rows r (cur) and r+1 (nxt).
+  T yprev[TB][M], cur[TB][3][M], nxt[TB][3][M];
+#pragma unroll
+  for (int l = 0; l < TB; ++l)
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      yprev[l][i] = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
+    }
+  auto at = [&](const T* base, int pl, int row, int col) {
+    const uint32_t off = ((uint32_t)row * (uint32_t)nx + (uint32_t)col) * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + (int64_t)pl * p.plane) + off);
+  };
+  T ld_row[P];
+  auto load_row = [&](int r) {
+    const bool r_in = r >= 0 && r < ny;
+    const int rl = r_in ? r : (((r % ny) + ny) % ny);
+    if (col_ok && (r_in || py)) {
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) ld_row[pl] = at(adj_in, pl, rl, xl);
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
+    }
+  };
+  auto advance = [&](int l) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      yprev[l][i] = cur[l][2][i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i];
+    }
+  };
+  auto enter = [&](int l, int r, const T (&g)[M][Q]) {
+    const int s = r & 1;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      xs[l][s][0][i][c] = g[i][KXP];
+      xs[l][s][1][i][c] = g[i][KXM];
+      nxt[l][0][i] = g[i][0];
+      nxt[l][1][i] = g[i][KYP];
+      nxt[l][2][i] = g[i][KYM];
+    }
+  };
+  // transposed face rule: the adjoint of a zero-flux face passes the value on, of a Dirichlet face negates it
+  auto tface = [&](int fk, T v) { return (p.bc[fk] == BC_ZERO_FLUX) ? v : -v; };
+  auto face = [&](int fk, int kb, int i, T back) {
+    return (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
+  };
+
+  const int r_last = y1 - 1 + TB;
+  int r_in = y0 - TB;
+  load_row(r_in);
+  for (; r_in <= r_last; ++r_in) {
+    __syncthreads();
+    {
+      T g[M][Q];
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) g[i][k] = ld_row[i * Q + k];
+      advance(0);
+      enter(0, r_in, g);
+    }
+    if (r_in < r_last) load_row(r_in + 1);
+#pragma unroll
+    for (int lvl = 1; lvl <= TB; ++lvl) {
+      const int r = r_in - lvl;
+      const int lp = lvl - 1;
+      const int s = r & 1;
+      const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
+      if (lvl < TB) advance(lvl);
+      if (!row_ok) continue;
+      // u = dL/dg at this node: the transposed pull of a_{t-l+1}
+      T u[M][Q];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        u[i][0] = cur[lp][0][i];
+        u[i][KXP] = xs[lp][s][0][i][cp];
+        u[i][KXM] = xs[lp][s][1][i][cm];
+        u[i][KYP] = nxt[lp][1][i];
+        u[i][KYM] = yprev[lp][i];
+      }
+      // f = f^{t-l} at this node: the pull of s_{t-l}
+      const int rl = (r >= 0 && r < ny) ? r : (((r % ny) + ny) % ny);
+      const int rlm = rl > 0 ? rl - 1 : ny - 1, rlp = rl < ny - 1 ? rl + 1 : 0;
+      const T* st = S.s[lp];
+      T f[M][Q];
+      if (col_ok) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          f[i][0] = at(st, i * Q, rl, xl);
+          f[i][KXP] = at(st, i * Q + KXP, rl, xlm);
+          f[i][KXM] = at(st, i * Q + KXM, rl, xlp);
+          f[i][KYP] = at(st, i * Q + KYP, rlm, xl);
+          f[i][KYM] = at(st, i * Q + KYM, rlp, xl);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int k = 0; k < Q; ++k) f[i][k] = T(0);
+      }
+      if constexpr (WALLS) {
+        if (tile_xwall) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            if (wall_xlo) {
+              f[i][KXP] = face(0, KXM, i, at(st, i * Q + KXM, rl, xl));
+              u[i][KXM] = tface(0, xs[lp][s][0][i][c]);
+            }
+            if (wall_xhi) {
+              f[i][KXM] = face(1, KXP, i, at(st, i * Q + KXP, rl, xl));
+              u[i][KXP] = tface(1, xs[lp][s][1][i][c]);
+            }
+          }
+        }
+        if (!py && r == 0) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            f[i][KYP] = face(2, KYM, i, at(st, i * Q + KYM, rl, xl));
+            u[i][KYM] = tface(2, cur[lp][1][i]);
+          }
+        }
+        if (!py && r == ny - 1) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            f[i][KYM] = face(3, KYP, i, at(st, i * Q + KYP, rl, xl));
+            u[i][KYP] = tface(3, cur[lp][2][i]);
+          }
+        }
+      }
+      T g[M][Q];
+      if (r >= y0 && r < y1) {
+        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, srt, g, Rbar);
+      } else {
+        double Rhalo[M][M + 1] = {};
+        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, srt, g, Rhalo);
+      }
+      if (lvl < TB) {
+        enter(lvl, r, g);
+      } else if (col_own && r >= y0 && r < y1) {
+        const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int k = 0; k < Q; ++k)
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(adj_out + (int64_t)(i * Q + k) * p.plane) + off) = g[i][k];
+      }
+    }
+  }
+  // workgroup sum of dL/dR over the owned columns, added to this workgroup's slot
+  const int lane = c & 63, wv = c >> 6;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= M; ++j) {
+      const double v = wave_sum(col_own ? Rbar[i][j] : 0.0);
+      if (lane == 0) red[wv][i * (M + 1) + j] = v;
+    }
+  __syncthreads();
+  if (c < E) {
+    double v = red[0][c];
+#pragma unroll
+    for (int w = 1; w < C / 64; ++w) v += red[w][c];
+    racc[(int64_t)blockIdx.x * E + c] += v;
+  }
+}
+
 template <int LAT, int M, typename T>
 __global__ __launch_bounds__(256) void k_adjoint_xi0(Problem p, const T* __restrict__ adj0, double* __restrict__ out,
                                                      Tiling tl) {
@@ -954,6 +1182,39 @@ inline Tiling make_tiling(const LaunchArgs& a, int V = 1) {
 }
 
 template <int M, typename T, int TB>
+hipError_t launch_adjoint_blocked_tb(const LaunchArgs& a) {
+  constexpr int C = adjoint_blocked_cols(M, TB, (int)sizeof(T));
+  if constexpr (C == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int W = C - 2 * TB;
+    const uint32_t tiles_x = (uint32_t)((a.p.nx + W - 1) / W);
+    const uint32_t segs = (uint32_t)((a.p.ny + a.seg_rows - 1) / a.seg_rows);
+    const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
+    AdjStates<T> S;
+    for (int l = 0; l < 4; ++l) S.s[l] = static_cast<const T*>(a.states[l]);
+    const T* ain = static_cast<const T*>(a.adj_in);
+    T* aout = static_cast<T*>(a.dst);
+    const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
+    if (walls)
+      hipLaunchKernelGGL((k_adjoint_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, S,
+                         ain, aout, cst, a.seg_rows, tiles_x, a.partials);
+    else
+      hipLaunchKernelGGL((k_adjoint_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p,
+                         S, ain, aout, cst, a.seg_rows, tiles_x, a.partials);
+    return hipSuccess;
+  }
+}
+
+template <int M, typename T>
+hipError_t launch_adjoint_blocked(const LaunchArgs& a) {
+  if (a.tb == 2) return launch_adjoint_blocked_tb<M, T, 2>(a);
+  if (a.tb == 3) return launch_adjoint_blocked_tb<M, T, 3>(a);
+  if (a.tb == 4) return launch_adjoint_blocked_tb<M, T, 4>(a);
+  return hipErrorInvalidValue;
+}
+
+template <int M, typename T, int TB>
 hipError_t launch_blocked_tb(const LaunchArgs& a) {
   constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
   if constexpr (C == 0) {
@@ -968,10 +1229,10 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
     if (walls)
       hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
-                         dst, cst, a.seg_rows, tiles_x, a.nontemporal);
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     else
       hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
-                         dst, cst, a.seg_rows, tiles_x, a.nontemporal);
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     return hipSuccess;
   }
 }
@@ -1113,7 +1374,8 @@ hipError_t run(Op op, const LaunchArgs& a) {
     }
     case Op::AdjointDD: {
       const Tiling tl = make_tiling(a, kAdjointNodesPerThread);
-      hipLaunchKernelGGL((k_adjoint_dD<LAT, M>), dim3(1), dim3(64), 0, a.stream, a.p, a.partials, tl.tiles,
+      const uint32_t slots = a.accum_slots > 0 ? (uint32_t)a.accum_slots : tl.tiles;
+      hipLaunchKernelGGL((k_adjoint_dD<LAT, M>), dim3(1), dim3(64), 0, a.stream, a.p, a.partials, slots,
                          a.diag_out);
       break;
     }
@@ -1123,6 +1385,14 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::StepBlocked:
       if constexpr (LAT == 2) {
         const hipError_t e = launch_blocked<M, T>(a);
+        if (e != hipSuccess) return e;
+      } else {
+        return hipErrorInvalidValue;
+      }
+      break;
+    case Op::AdjointBlocked:
+      if constexpr (LAT == 2) {
+        const hipError_t e = launch_adjoint_blocked<M, T>(a);
         if (e != hipSuccess) return e;
       } else {
         return hipErrorInvalidValue;

@@ -10,7 +10,8 @@ namespace msd {
 
 enum class Op {
   Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
-  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked, BatchStepBlocked
+  AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked, BatchStepBlocked,
+  AdjointBlocked
 };
 
 // Constants block written once per problem by the setup kernel and read by
@@ -59,6 +60,9 @@ struct LaunchArgs {
   int tb = 0;                // steps per pass of the temporally blocked sweep
   int seg_rows = 32;         // rows per workgroup segment of the blocked sweep
   int walls = 0;             // blocked batch launch: some mixture has a non-periodic face
+  int64_t rec_stride = 0;    // blocked sweep: elements between recorded states (0: no recording)
+  const void* states[4] = {nullptr, nullptr, nullptr, nullptr};   // blocked adjoint: s_{t-1}, ..., s_{t-TB}
+  int64_t accum_slots = 0;   // adjoint: workgroup slots of the dL/dR accumulator
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;
@@ -98,7 +102,18 @@ constexpr int blocked_cols(int m, int tb, int bytes) {
              : 0;
 }
 
-// Nodes per thread of the adjoint sweep (see k_adjoint_step).
+// Temporally blocked adjoint sweep (k_adjoint_blocked): workgroup width for m
+// evolved species, tb adjoint steps per pass and value size, or 0 when its
+// register window (7m values per level) next to the pulled state, the incoming
+// adjoint and the transposed collision (3 x 5m values) would exceed 80 VGPRs.
+constexpr int adjoint_blocked_cols(int m, int tb, int bytes) {
+  return (tb >= 2 && tb <= 4 && (7 * m * tb + 15 * m) * bytes / 4 <= 80 &&
+          tb * 2 * 2 * m * kBlockedCols * bytes <= 64 * 1024)
+             ? kBlockedCols
+             : 0;
+}
+
+// Nodes per thread of the adjoint sweep// Nodes per thread of the adjoint sweep (see k_adjoint_step).
 constexpr int kAdjointNodesPerThread = 4;
 
 // Largest domain (nodes) the single-workgroup LDS-resident sweep accepts for a

@@ -11,11 +11,13 @@ from oracle import twin
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_grads(lattice, D, shape, precision, xi0, target, steps, every, **kw):
+def _gpu_grads(lattice, D, shape, precision, xi0, target, steps, every, launch=None, **kw):
     from paper_1808_06787_amd import adjoint
     from paper_1808_06787_amd.sim import Sim
 
     sim = Sim(lattice, D, shape, precision, **kw)
+    if launch:
+        sim.set_launch(**launch)
     sim.init(torch.from_numpy(xi0))
     ckpts = adjoint.forward_with_checkpoints(sim, steps, every)
     xi, _, _ = sim.read(torch.float64, flux=False, grad=False)
@@ -164,3 +166,55 @@ def test_autograd_function():
     np.testing.assert_allclose(Dt.grad.numpy() + Dt.grad.numpy().T, gD0, rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(x.grad.cpu().numpy()[: N - 1], gx0, rtol=1e-10, atol=1e-14 * np.abs(gx0).max())
     assert np.all(x.grad.cpu().numpy()[N - 1] == 0)
+
+
+BLOCKED_CASES = [
+    ((300, 11), (("periodic", "periodic"), ("periodic", "periodic"))),
+    ((260, 9), (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"))),
+    ((7, 40), (("zero_flux", "zero_flux"), ("periodic", "periodic"))),
+]
+
+
+def _blocked_problem(case, N, seed):
+    rng = np.random.default_rng(seed)
+    shape, bc = BLOCKED_CASES[case]
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for side, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, side)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    return shape, bc, walls, D, xi0, target
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
+@pytest.mark.parametrize("tb", [2, 3, 4])
+def test_blocked_adjoint_and_recording_fp64(case, tb):
+    """Binary mixture in FP64: recomputation by blocked passes that store every
+    step, and blocked adjoint passes (2 or 3 steps), across column tiles and
+    4-row segments, every face kind, segments of 8 steps with remainders."""
+    N = 2
+    shape, bc, walls, D, xi0, target = _blocked_problem(case, N, 400 + case)
+    steps, every = 23, 8
+    p = oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls)
+    ref = twin.misfit_gradients(p, xi0, target, steps)
+    got = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, steps, every,
+                     launch=dict(temporal=tb, seg_rows=4), bc=bc, xi_wall=walls)
+    _compare(ref, got, 1e-10, f"blocked tb={tb} case {case}")
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
+@pytest.mark.parametrize("tb", [2, 3])
+def test_blocked_adjoint_fp32_ternary(case, tb):
+    """Ternary FP32 with blocked passes against the FP64 result of one step per
+    pass (the FP32 tolerance of the adjoint)."""
+    N = 3
+    shape, bc, walls, D, xi0, target = _blocked_problem(case, N, 410 + case)
+    steps, every = 30, 13
+    ref = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, steps, every, launch=dict(temporal=0),
+                     bc=bc, xi_wall=walls)
+    got = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=dict(temporal=tb, seg_rows=4),
+                     bc=bc, xi_wall=walls)
+    _compare(ref, got, 2e-4, f"fp32 blocked tb={tb} case {case}")
