@@ -246,9 +246,10 @@ typedef struct msd_launch {
                                FP64: m = 1 up to 4, m = 2 up to 2; else one step per pass).
                                Default 4 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
-                               automatic, 16 rows, or 8 when 16 give fewer than 512
-                               workgroups, and one step per pass when 8 still give fewer
-                               than 512 (small domains run faster unblocked); negative or
+                               automatic, segments sized so that the launch holds about 1.35
+                               times the workgroups the device runs at once, at least 8 rows,
+                               and one step per pass when 8-row segments give fewer than 512
+                               workgroups (small domains run faster unblocked); negative or
                                above 2^20 is MSD_EINVAL */
 } msd_launch;
 

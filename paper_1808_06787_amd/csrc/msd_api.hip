@@ -189,6 +189,9 @@ struct msd_sim {
   int64_t t = 0;
   bool initialised = false;
   msd_launch launch{};
+  // resident workgroups of the blocked kernels by steps per pass (0: not queried)
+  mutable int resident_fwd[5] = {0, 0, 0, 0, 0};
+  mutable int resident_adj[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -210,13 +213,14 @@ msd::LaunchArgs base_args(const msd_sim* s) {
   return a;
 }
 
-// Plan of the blocked sweep for this handle: steps per pass (the largest count
-// up to the requested one whose on-chip window fits; 0: one step per pass) and
-// rows per workgroup segment.  Automatic segments (seg_rows = 0): 16 rows, or
-// 8 when 16 leave fewer than 512 workgroups (two per CU); if 8-row segments
-// still leave fewer than 512, one step per pass is faster (measured on 512^2
-// to 4096^2 ternary FP32 lattices).  32-bit in-plane offsets need plane bytes
-// < 4 GiB.
+// Plan of the blocked sweep (or of the blocked adjoint) for this handle: steps
+// per pass (the largest count up to the requested one whose on-chip window
+// fits; 0: one step per pass) and rows per workgroup segment.  Automatic
+// segments (seg_rows = 0) give the launch about 1.35 rounds of the workgroups
+// the device holds at once (long segments re-read few halo rows), but at
+// least 8 rows; if 8-row segments leave fewer than 512 workgroups, one step per
+// pass is faster (small domains: measured on 512^2 to 4096^2 ternary FP32
+// lattices).  32-bit in-plane offsets need plane bytes < 4 GiB.
 struct BlockedPlan {
   int tb = 0;
   int seg = 0;
@@ -239,8 +243,21 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   auto groups = [&](int64_t seg) { return tiles_x * ((s->prob.ny + seg - 1) / seg); };
   int seg = s->launch.seg_rows;
   if (seg <= 0) {
-    seg = groups(16) >= 512 ? 16 : 8;
-    if (groups(seg) < 512) return pl;
+    if (groups(8) < 512) return pl;
+    int& cached = (adjoint ? s->resident_adj : s->resident_fwd)[tb];
+    if (cached == 0) {
+      msd::LaunchArgs a = base_args(s);
+      a.tb = tb;
+      a.adjoint = adjoint ? 1 : 0;
+      int slots = 0;
+      a.out_int = &slots;
+      if (dispatch(msd::Op::BlockedResident, a) != hipSuccess || slots <= 0) slots = 1024;
+      cached = slots;
+    }
+    // about 1.35 rounds: measured best on 4096^2 (one exact round is 6 % slower)
+    const int64_t target = (int64_t)cached * 27 / 20;
+    const int64_t rows = (tiles_x * s->prob.ny + target - 1) / target;
+    seg = (int)std::max<int64_t>(8, std::min<int64_t>(rows, s->prob.ny));
   }
   pl.tb = tb;
   pl.seg = seg;

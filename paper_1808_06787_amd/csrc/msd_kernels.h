@@ -1206,6 +1206,36 @@ hipError_t launch_adjoint_blocked_tb(const LaunchArgs& a) {
   }
 }
 
+// Workgroups of a blocked kernel (sweep or adjoint) that the whole device holds
+// at once: resident workgroups per CU (registers and LDS) times the CU count.
+template <int M, typename T, int TB>
+hipError_t blocked_resident(const LaunchArgs& a, int* out) {
+  *out = 0;
+  constexpr int C = blocked_cols(M, TB, (int)sizeof(T)), CA = adjoint_blocked_cols(M, TB, (int)sizeof(T));
+  const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
+  int per_cu = 0;
+  hipError_t e = hipSuccess;
+  if (a.adjoint) {
+    if constexpr (CA > 0) {
+      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint_blocked<M, T, TB, CA, true>, CA, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint_blocked<M, T, TB, CA, false>, CA, 0);
+    }
+  } else {
+    if constexpr (C > 0) {
+      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true>, C, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false>, C, 0);
+    }
+  }
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  *out = per_cu * cus;
+  return hipSuccess;
+}
+
 template <int M, typename T>
 hipError_t launch_adjoint_blocked(const LaunchArgs& a) {
   if (a.tb == 2) return launch_adjoint_blocked_tb<M, T, 2>(a);
@@ -1390,6 +1420,16 @@ hipError_t run(Op op, const LaunchArgs& a) {
         return hipErrorInvalidValue;
       }
       break;
+    case Op::BlockedResident:
+      if constexpr (LAT == 2) {
+        hipError_t e = hipErrorInvalidValue;
+        if (a.tb == 2) e = blocked_resident<M, T, 2>(a, a.out_int);
+        if (a.tb == 3) e = blocked_resident<M, T, 3>(a, a.out_int);
+        if (a.tb == 4) e = blocked_resident<M, T, 4>(a, a.out_int);
+        return e;
+      } else {
+        return hipErrorInvalidValue;
+      }
     case Op::AdjointBlocked:
       if constexpr (LAT == 2) {
         const hipError_t e = launch_adjoint_blocked<M, T>(a);

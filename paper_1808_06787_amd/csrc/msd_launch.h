@@ -11,7 +11,7 @@ namespace msd {
 enum class Op {
   Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
   AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked, BatchStepBlocked,
-  AdjointBlocked
+  AdjointBlocked, BlockedResident
 };
 
 // Constants block written once per problem by the setup kernel and read by
@@ -63,6 +63,8 @@ struct LaunchArgs {
   int64_t rec_stride = 0;    // blocked sweep: elements between recorded states (0: no recording)
   const void* states[4] = {nullptr, nullptr, nullptr, nullptr};   // blocked adjoint: s_{t-1}, ..., s_{t-TB}
   int64_t accum_slots = 0;   // adjoint: workgroup slots of the dL/dR accumulator
+  int adjoint = 0;           // BlockedResident: query the adjoint kernel
+  int* out_int = nullptr;    // BlockedResident: result
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;
