@@ -300,6 +300,31 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
     }
 }
 
+// Global-memory access from a uniform base and a 32-bit per-lane byte offset.
+// scalar_base hides the base behind an empty asm with an SGPR operand, so the
+// compiler keeps it in scalar registers and emits the base + 32-bit-offset
+// form instead of re-associating it into 64-bit per-lane address arithmetic.
+using gbyte = __attribute__((address_space(1))) char;
+__device__ __forceinline__ uint64_t scalar_base(const void* p) {
+  uint64_t a = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(a));
+  return a;
+}
+template <typename T>
+__device__ __forceinline__ T gload(uint64_t base, uint32_t off, bool nt) {
+  const auto* q = reinterpret_cast<const __attribute__((address_space(1))) T*>(
+      reinterpret_cast<const gbyte*>(base) + off);
+  return nt ? __builtin_nontemporal_load(q) : *q;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(uint64_t base, uint32_t off, T v, int nt) {
+  auto* q = reinterpret_cast<__attribute__((address_space(1))) T*>(reinterpret_cast<gbyte*>(base) + off);
+  if (nt)
+    __builtin_nontemporal_store(v, q);
+  else
+    *q = v;
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked D2Q5 sweep: TB time steps per pass over HBM.
 //
@@ -344,7 +369,8 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   const int y0 = (int)seg * seg_rows;
   const int y1 = min(y0 + seg_rows, ny);
   const int x = x0 - TB + c;
-  const bool px = p.bc[0] == BC_PERIODIC, py = p.bc[2] == BC_PERIODIC;
+  // WALLS = false is only launched on a fully periodic domain
+  const bool px = !WALLS || p.bc[0] == BC_PERIODIC, py = !WALLS || p.bc[2] == BC_PERIODIC;
   const bool x_in = x >= 0 && x < nx;
   const bool col_ok = x_in || px;
   const uint32_t xl = (uint32_t)(x_in ? x : (((x % nx) + nx) % nx));
@@ -368,7 +394,10 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
     }
 
-  auto plane_src = [&](int pl) { return reinterpret_cast<const char*>(src + (int64_t)pl * p.plane); };
+  // Start of plane pl of a buffer (uniform).  The empty asm keeps it an opaque
+  // scalar, so that every access is that scalar base plus the lane's 32-bit
+  // offset rather than 64-bit address arithmetic per lane and plane.
+  auto plane_at = [&](const T* base, int pl) { return scalar_base(base + (int64_t)pl * p.plane); };
 
   T ld_row[P];
   auto load_row = [&](int r) {
@@ -377,7 +406,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     if (col_ok && (r_in || py)) {
       const uint32_t off = ((uint32_t)rl * (uint32_t)nx + xl) * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) ld_row[pl] = ld(reinterpret_cast<const T*>(plane_src(pl) + off), nt_ld);
+      for (int pl = 0; pl < P; ++pl) ld_row[pl] = gload<T>(plane_at(src, pl), off, nt_ld);
     } else {
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
@@ -468,8 +497,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
         for (int i = 0; i < M; ++i)
 #pragma unroll
           for (int k = 0; k < Q; ++k)
-            store_value(reinterpret_cast<T*>(reinterpret_cast<char*>(out + (int64_t)(i * Q + k) * p.plane) + off),
-                        f[i][k], nt_st);
+            gstore<T>(plane_at(out, i * Q + k), off, f[i][k], nt_st);
       }
     }
   }
@@ -492,13 +520,26 @@ __global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __res
                                                           char* __restrict__ ws, int cur, int seg_rows,
                                                           int nontemporal) {
   constexpr int W = C - 2 * TB;
-  const BatchTile bt = tiles[tile_begin + blockIdx.x];
+  // The table entries are uniform but read by vector loads: move the fields the
+  // tile uses to scalar registers (the tile addresses planes from scalar bases).
+  auto u32 = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+  auto u64 = [&](uint64_t v) { return ((uint64_t)u32((uint32_t)(v >> 32)) << 32) | u32((uint32_t)v); };
+  const BatchTile btv = tiles[tile_begin + blockIdx.x];
+  const BatchTile bt{u32(btv.inst), u32(btv.tile)};
   const BatchInst* I = insts + bt.inst;
-  const Problem& p = I->p;
+  Problem p;
+  p.nx = (int32_t)u32((uint32_t)I->p.nx);
+  p.ny = (int32_t)u32((uint32_t)I->p.ny);
+  p.nz = 1;
+  p.relax = (int32_t)u32((uint32_t)I->p.relax);
+  p.linearized = (int32_t)u32((uint32_t)I->p.linearized);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) p.bc[f] = (int32_t)u32((uint32_t)I->p.bc[f]);
+  p.plane = (int64_t)u64((uint64_t)I->p.plane);
   const uint32_t tiles_x = (uint32_t)((p.nx + W - 1) / W);
-  const T* src = reinterpret_cast<const T*>(ws + I->half_off[cur]);
-  T* dst = reinterpret_cast<T*>(ws + I->half_off[1 - cur]);
-  const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + I->consts_off);
+  const T* src = reinterpret_cast<const T*>(ws + u64(I->half_off[cur]));
+  T* dst = reinterpret_cast<T*>(ws + u64(I->half_off[1 - cur]));
+  const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + u64(I->consts_off));
   blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, bt.tile % tiles_x, bt.tile / tiles_x, nontemporal);
 }
 
@@ -931,7 +972,8 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   const int y0 = (int)seg * seg_rows;
   const int y1 = min(y0 + seg_rows, ny);
   const int x = x0 - TB + c;
-  const bool px = p.bc[0] == BC_PERIODIC, py = p.bc[2] == BC_PERIODIC;
+  // WALLS = false is only launched on a fully periodic domain
+  const bool px = !WALLS || p.bc[0] == BC_PERIODIC, py = !WALLS || p.bc[2] == BC_PERIODIC;
   const bool x_in = x >= 0 && x < nx;
   const bool col_ok = x_in || px;
   const bool col_own = c >= TB && c < C - TB && x_in;
@@ -959,9 +1001,10 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
 #pragma unroll
       for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
     }
+  // value of plane pl at (row, col): an opaque scalar plane start plus a 32-bit lane offset
   auto at = [&](const T* base, int pl, int row, int col) {
     const uint32_t off = ((uint32_t)row * (uint32_t)nx + (uint32_t)col) * (uint32_t)sizeof(T);
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + (int64_t)pl * p.plane) + off);
+    return gload<T>(scalar_base(base + (int64_t)pl * p.plane), off, false);
   };
   T ld_row[P];
   auto load_row = [&](int r) {
@@ -1097,7 +1140,7 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
         for (int i = 0; i < M; ++i)
 #pragma unroll
           for (int k = 0; k < Q; ++k)
-            *reinterpret_cast<T*>(reinterpret_cast<char*>(adj_out + (int64_t)(i * Q + k) * p.plane) + off) = g[i][k];
+            gstore<T>(scalar_base(adj_out + (int64_t)(i * Q + k) * p.plane), off, g[i][k], 0);
       }
     }
   }
