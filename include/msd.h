@@ -217,6 +217,26 @@ MSD_API int msd_adjoint_steps(msd_sim* sim, int64_t t_hi, int64_t t_lo, const vo
 MSD_API int msd_adjoint_finish(msd_sim* sim, const void* d_adj0, const void* d_accum, double* d_dL_dxi0,
                                double* h_dL_dD);
 
+/* One-call reverse mode.  msd_forward_checkpointed advances a handle that
+ * msd_init has just initialised (time 0) by nsteps, storing the state at the
+ * start of every segment of `every` steps: ceil(nsteps / every) states of
+ * msd_state_bytes bytes, segment j's at d_ckpts + j * msd_state_bytes (device
+ * memory, caller-owned).  msd_adjoint then takes dL/dxi at time nsteps (N FP64
+ * planes, the handle must still be at that time) and returns dL/dxi(0) (N-1
+ * FP64 device planes, or NULL) and dL/dD (host N x N, or NULL) as
+ * msd_adjoint_finish does, recomputing each segment once (msd_record) and
+ * running its adjoint steps backwards (msd_adjoint_steps).  d_scratch
+ * (caller-owned, 256-byte aligned, at least msd_adjoint_scratch_bytes for the
+ * same `every` and launch configuration) holds the accumulator, two adjoint
+ * buffers and the recomputation stack.  The handle's state is left at an
+ * intermediate time.  Errors: MSD_EINVAL (NULL, nsteps < 0, every < 1),
+ * MSD_ESTATE (not at time 0 / not at time nsteps), MSD_ENOMEM (scratch too
+ * small); msd_adjoint_scratch_bytes returns 0 for invalid arguments. */
+MSD_API size_t msd_adjoint_scratch_bytes(const msd_sim* sim, int64_t every);
+MSD_API int msd_forward_checkpointed(msd_sim* sim, int64_t nsteps, int64_t every, void* d_ckpts);
+MSD_API int msd_adjoint(msd_sim* sim, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
+                        double* d_dL_dxi0, double* h_dL_dD, void* d_scratch, size_t scratch_bytes);
+
 /* ---------------------------------------------------------------------------
  * Launch tuning of the single-mixture sweep
  * ------------------------------------------------------------------------- */

@@ -125,6 +125,9 @@ def lib():
         "msd_adjoint_step": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "msd_adjoint_finish": (C.c_int, [vp, vp, vp, vp, P(C.c_double)]),
         "msd_adjoint_steps": (C.c_int, [vp, i64, i64, vp, vp, vp, vp, vp, P(i32)]),
+        "msd_adjoint_scratch_bytes": (sz, [vp, i64]),
+        "msd_forward_checkpointed": (C.c_int, [vp, i64, i64, vp]),
+        "msd_adjoint": (C.c_int, [vp, i64, i64, vp, vp, vp, P(C.c_double), vp, sz]),
         "msd_batch_workspace_bytes": (sz, [P(MsdProblem), i32, P(i32)]),
         "msd_batch_create": (C.c_int, [P(MsdProblem), i32, vp, sz, vp, P(vp)]),
         "msd_batch_init": (C.c_int, [vp, i32, vp, i32]),

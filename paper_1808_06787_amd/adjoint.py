@@ -1,9 +1,11 @@
-"""Gradients through the sweep: checkpointed forward run, segment recompute and
-the hand-written adjoint kernels, plus a torch.autograd.Function around them.
+"""Gradients through the sweep: the library's checkpointed forward run and its
+one-call adjoint (segment recomputation and the hand-written adjoint kernels),
+plus a torch.autograd.Function around them.
 
-Memory: one checkpoint (msd_state_bytes) every `every` steps, a recompute stack
-of every-1 states, two adjoint buffers and the dL/dD accumulator.  Cost: the
-forward run, one recompute of it, and one adjoint launch per step.
+Memory: one checkpoint (msd_state_bytes) every `every` steps, and scratch for
+a recomputation stack of every-1 states, two adjoint buffers and the dL/dD
+accumulator.  Cost: the forward run, one recomputation of it, and the adjoint
+steps.
 """
 from __future__ import annotations
 
@@ -16,62 +18,41 @@ from . import _ffi as F
 from .sim import Sim
 
 
-def _p(t: torch.Tensor):
-    return C.c_void_p(t.data_ptr())
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
 def forward_with_checkpoints(sim: Sim, steps: int, every: int) -> dict:
-    """Advance an initialised sim by `steps`, saving its state at every multiple of
-    `every` (from its current time) before stepping on.  Returns {time: state}."""
+    """Advance a sim that was just initialised (time 0) by `steps`, keeping the state
+    at the start of every segment of `every` steps on the device.  Returns the
+    checkpoint record that `gradients` takes."""
+    steps, every = int(steps), int(every)
     if every < 1:
         raise ValueError("every must be >= 1")
-    ckpts = {}
-    t_end = sim.time + int(steps)
-    while sim.time < t_end:
-        state, t = sim.save()
-        ckpts[t] = state
-        sim.step(min(every, t_end - sim.time))
-    return ckpts
+    n = (steps + every - 1) // every
+    buf = torch.empty(max(n, 1) * sim.state_bytes(), dtype=torch.uint8, device=sim.device) if n else None
+    F.check(sim.lib.msd_forward_checkpointed(sim._h, steps, every, _p(buf)), "msd_forward_checkpointed")
+    return {"buffer": buf, "steps": steps, "every": every}
 
 
 def gradients(sim: Sim, ckpts: dict, T: int, dL_dxi: torch.Tensor, every: int):
     """dL/dxi(0) (N-1 FP64 planes, device) and the N x N matrix of pair derivatives
-    dL/dD (numpy) for dL/dxi(T) given as N FP64 planes.  `ckpts` are the states
-    saved by forward_with_checkpoints (starting at time 0).  The handle's state
-    is left at an intermediate time afterwards."""
-    lib = sim.lib
-    h = sim._h
+    dL/dD (numpy) for dL/dxi(T) given as N FP64 planes, after
+    forward_with_checkpoints(sim, T, every).  The handle's state is left at an
+    intermediate time afterwards."""
+    if ckpts["steps"] != T or ckpts["every"] != every:
+        raise ValueError("checkpoints were taken for another run")
     if sim.time != T:
         raise ValueError(f"sim is at time {sim.time}, expected {T}")
     g = dL_dxi.to(device=sim.device, dtype=torch.float64).contiguous()
     if tuple(g.shape) != (sim.N,) + sim.nodes_shape:
         raise ValueError("dL_dxi must hold N planes")
-    sb = sim.state_bytes()
-    acc = torch.empty(int(lib.msd_adjoint_accum_bytes(h)), dtype=torch.uint8, device=sim.device)
-    a_cur = torch.empty(sb, dtype=torch.uint8, device=sim.device)
-    a_nxt = torch.empty(sb, dtype=torch.uint8, device=sim.device)
-    stack = torch.empty(max(every - 1, 1) * sb, dtype=torch.uint8, device=sim.device)
-    F.check(lib.msd_adjoint_begin(h, _p(acc)), "msd_adjoint_begin")
-    F.check(lib.msd_adjoint_seed(h, _p(g), _p(a_cur)), "msd_adjoint_seed")
-    starts = sorted(t for t in ckpts if t < T)
-    if T > 0 and (not starts or starts[0] != 0):
-        raise ValueError("checkpoints must start at time 0")
-    for i in range(len(starts) - 1, -1, -1):
-        t0 = starts[i]
-        t1 = starts[i + 1] if i + 1 < len(starts) else T
-        if t1 - t0 > every:
-            raise ValueError("checkpoints further apart than `every`")
-        if t1 - t0 > 1:
-            sim.restore(ckpts[t0], t0)
-            F.check(lib.msd_record(h, t1 - t0 - 1, _p(stack)), "msd_record")
-        in_b = C.c_int32(0)
-        F.check(lib.msd_adjoint_steps(h, t1, t0, _p(ckpts[t0]), _p(stack), _p(a_cur), _p(a_nxt), _p(acc),
-                                      C.byref(in_b)), "msd_adjoint_steps")
-        if in_b.value:
-            a_cur, a_nxt = a_nxt, a_cur
+    nbytes = int(sim.lib.msd_adjoint_scratch_bytes(sim._h, int(every)))
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=sim.device)
     dxi0 = torch.empty((sim.m,) + sim.nodes_shape, dtype=torch.float64, device=sim.device)
     dD = (C.c_double * (sim.N * sim.N))()
-    F.check(lib.msd_adjoint_finish(h, _p(a_cur), _p(acc), _p(dxi0), dD), "msd_adjoint_finish")
+    F.check(sim.lib.msd_adjoint(sim._h, int(T), int(every), _p(ckpts["buffer"]), _p(g), _p(dxi0), dD, _p(scratch),
+                                C.c_size_t(nbytes)), "msd_adjoint")
     return dxi0, np.array(dD[:]).reshape(sim.N, sim.N)
 
 

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "../../include/msd.h"
 #include "msd_host.h"
@@ -675,6 +676,86 @@ int msd_adjoint_finish(msd_sim* s, const void* d_adj0, const void* d_accum, doub
     if (e != hipSuccess) return hip_fail(e, "adjoint synchronise");
   }
   return MSD_OK;
+}
+
+// Scratch of msd_adjoint: the dL/dR accumulator, two adjoint buffers and a
+// recomputation stack of every - 1 states, each 256-byte aligned.
+struct AdjointScratch {
+  size_t acc = 0, a0 = 0, a1 = 0, stack = 0, total = 0;
+};
+
+static AdjointScratch adjoint_scratch(const msd_sim* s, int64_t every) {
+  AdjointScratch L;
+  const size_t sb = align_up(msd_state_bytes(s), 256);
+  L.acc = 0;
+  L.a0 = align_up(msd_adjoint_accum_bytes(s), 256);
+  L.a1 = L.a0 + sb;
+  L.stack = L.a1 + sb;
+  L.total = L.stack + (size_t)std::max<int64_t>(every - 1, 1) * msd_state_bytes(s);
+  return L;
+}
+
+size_t msd_adjoint_scratch_bytes(const msd_sim* s, int64_t every) {
+  if (!s || every < 1) return 0;
+  return adjoint_scratch(s, every).total;
+}
+
+int msd_forward_checkpointed(msd_sim* s, int64_t nsteps, int64_t every, void* d_ckpts) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  if (nsteps < 0 || every < 1) return fail(MSD_EINVAL, "nsteps = %lld, every = %lld", (long long)nsteps,
+                                           (long long)every);
+  if (nsteps > 0 && !d_ckpts) return fail(MSD_EINVAL, "checkpoint buffer is NULL");
+  if (!s->initialised || s->t != 0) return fail(MSD_ESTATE, "checkpointed runs start right after msd_init");
+  const size_t sb = msd_state_bytes(s);
+  char* ck = static_cast<char*>(d_ckpts);
+  for (int64_t j = 0; s->t < nsteps; ++j) {
+    int st = msd_save(s, ck + (size_t)j * sb, nullptr);
+    if (st != MSD_OK) return st;
+    st = msd_step(s, std::min(every, nsteps - s->t));
+    if (st != MSD_OK) return st;
+  }
+  return MSD_OK;
+}
+
+int msd_adjoint(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
+                double* d_dL_dxi0, double* h_dL_dD, void* d_scratch, size_t scratch_bytes) {
+  if (!s || !d_dL_dxi || !d_scratch) return fail(MSD_EINVAL, "NULL argument");
+  if (nsteps < 0 || every < 1) return fail(MSD_EINVAL, "nsteps = %lld, every = %lld", (long long)nsteps,
+                                           (long long)every);
+  if (nsteps > 0 && !d_ckpts) return fail(MSD_EINVAL, "checkpoint buffer is NULL");
+  if (!s->initialised || s->t != nsteps)
+    return fail(MSD_ESTATE, "the handle is at time %lld, not at the end (%lld) of the checkpointed run",
+                (long long)s->t, (long long)nsteps);
+  if (reinterpret_cast<uintptr_t>(d_scratch) % 256) return fail(MSD_EINVAL, "scratch must be 256-byte aligned");
+  const AdjointScratch L = adjoint_scratch(s, every);
+  if (scratch_bytes < L.total) return fail(MSD_ENOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, L.total);
+  char* w = static_cast<char*>(d_scratch);
+  void* acc = w + L.acc;
+  void* a = w + L.a0;
+  void* b = w + L.a1;
+  void* stack = w + L.stack;
+  const size_t sb = msd_state_bytes(s);
+  const char* ck = static_cast<const char*>(d_ckpts);
+  int st = msd_adjoint_begin(s, acc);
+  if (st != MSD_OK) return st;
+  st = msd_adjoint_seed(s, d_dL_dxi, a);
+  if (st != MSD_OK) return st;
+  const int64_t segs = (nsteps + every - 1) / every;
+  for (int64_t j = segs - 1; j >= 0; --j) {
+    const int64_t t0 = j * every, t1 = std::min(t0 + every, nsteps);
+    const void* c0 = ck + (size_t)j * sb;
+    if (t1 - t0 > 1) {
+      st = msd_restore(s, c0, t0);
+      if (st != MSD_OK) return st;
+      st = msd_record(s, t1 - t0 - 1, stack);
+      if (st != MSD_OK) return st;
+    }
+    int32_t in_b = 0;
+    st = msd_adjoint_steps(s, t1, t0, c0, stack, a, b, acc, &in_b);
+    if (st != MSD_OK) return st;
+    if (in_b) std::swap(a, b);
+  }
+  return msd_adjoint_finish(s, a, acc, d_dL_dxi0, h_dL_dD);
 }
 
 int msd_destroy(msd_sim* s) {

@@ -140,3 +140,13 @@ def test_batch_validation_codes():
     h = C.c_void_p()
     assert lib.msd_batch_create(arr, 2, C.c_void_p(1 << 40), C.c_size_t(n - 1), None, C.byref(h)) == -7
     assert lib.msd_batch_step(None, 1) == -1
+
+
+def test_adjoint_and_query_calls_reject_null_handles():
+    lib = F.lib()
+    assert lib.msd_adjoint_scratch_bytes(None, 5) == 0
+    assert lib.msd_forward_checkpointed(None, 10, 5, None) == -1
+    g = C.c_void_p(1 << 40)          # never dereferenced: validation fails first
+    assert lib.msd_adjoint(None, 10, 5, g, g, None, None, g, C.c_size_t(1 << 20)) == -1
+    assert lib.msd_steps_per_pass(None) == -1
+    assert lib.msd_record(None, 3, g) == -1
