@@ -276,6 +276,26 @@ typedef struct msd_launch {
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);
 MSD_API int msd_get_launch(const msd_sim* sim, msd_launch* launch);
 
+/* Tuning by measurement.  Each candidate launch is applied, run for one
+ * warm-up step and `steps` timed steps (HIP events on the handle's stream) from
+ * the current state, which is saved to d_scratch (caller-owned device memory of
+ * at least msd_state_bytes) and restored with the time after every trial, so
+ * tuning leaves the simulation unchanged.  candidates: `count` launches, or
+ * count = 0 for the library's list (tile shapes, vector widths, XCD remapping,
+ * streaming hints, and for D2Q5 steps per pass and segment heights).
+ * budget_ms > 0 stops once that much timed GPU work is spent.  The fastest
+ * launch is applied and returned in *h_best with its milliseconds per step;
+ * h_trial_ms (NULL, or one entry per candidate) receives every trial's time
+ * (-1 if not run).  cache_path (NULL: none) is a text file of lines "<key>
+ * <8 launch fields> <ms>" keyed by GPU architecture, lattice, precision,
+ * species count, extents and faces: a hit is applied without timing (unless
+ * flags has MSD_TUNE_IGNORE_CACHE) and a new result is appended.  Errors:
+ * MSD_EINVAL, MSD_ESTATE (not initialised), MSD_ENOMEM (scratch too small). */
+enum { MSD_TUNE_IGNORE_CACHE = 1 };
+MSD_API int msd_tune(msd_sim* sim, const msd_launch* candidates, int32_t count, int32_t steps, double budget_ms,
+                     const char* cache_path, int32_t flags, void* d_scratch, size_t scratch_bytes,
+                     msd_launch* h_best, double* h_ms_per_step, double* h_trial_ms);
+
 /* Time steps the sweep advances per pass over HBM (one kernel launch) under the
  * current launch configuration: the temporally blocked count (2..4) or 1.  The
  * step from time 0 (from the state msd_init writes) and a remainder shorter
@@ -362,6 +382,15 @@ MSD_API int msd_batch_get_schedule(const msd_batch* batch, msd_schedule* schedul
 MSD_API size_t msd_batch_state_bytes(const msd_batch* batch);
 MSD_API int msd_batch_save(const msd_batch* batch, void* d_dst, int64_t* h_step);
 MSD_API int msd_batch_restore(msd_batch* batch, const void* d_src, int64_t step);
+
+/* Tuning of the tile schedule by measurement, as msd_tune does for one mixture:
+ * candidates are schedules (count = 0: the library's list of tile shapes,
+ * fused or per-class launches, tile orders, XCD remapping, and for D2Q5 steps
+ * per pass and segment heights), d_scratch holds msd_batch_state_bytes, and
+ * the cache key hashes every mixture's species count, extents and faces. */
+MSD_API int msd_batch_tune(msd_batch* batch, const msd_schedule* candidates, int32_t count, int32_t steps,
+                           double budget_ms, const char* cache_path, int32_t flags, void* d_scratch,
+                           size_t scratch_bytes, msd_schedule* h_best, double* h_ms_per_step, double* h_trial_ms);
 
 /* Number of workgroups of one msd_batch_step launch under the current schedule
  * (all classes together). */

@@ -74,6 +74,7 @@ class MsdSchedule(C.Structure):
 
 
 BATCH_FUSED, BATCH_PER_CLASS = 0, 1
+TUNE_IGNORE_CACHE = 1
 ORDER_INSTANCE, ORDER_INTERLEAVED = 0, 1
 
 
@@ -142,6 +143,10 @@ def lib():
         "msd_batch_save": (C.c_int, [vp, vp, P(i64)]),
         "msd_batch_restore": (C.c_int, [vp, vp, i64]),
         "msd_batch_tiles": (i64, [vp]),
+        "msd_batch_tune": (C.c_int, [vp, P(MsdSchedule), i32, i32, C.c_double, C.c_char_p, i32, vp, sz,
+                                     P(MsdSchedule), P(C.c_double), P(C.c_double)]),
+        "msd_tune": (C.c_int, [vp, P(MsdLaunch), i32, i32, C.c_double, C.c_char_p, i32, vp, sz, P(MsdLaunch),
+                               P(C.c_double), P(C.c_double)]),
         "msd_batch_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():

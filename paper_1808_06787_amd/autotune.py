@@ -1,132 +1,96 @@
-"""Autotuning of launch parameters by timing candidates on the real problem.
+"""Autotuning by measurement: argument marshalling around msd_tune and
+msd_batch_tune.
 
 `tune_batch` picks the tile schedule of a Batch (tile shape, fused or per-N
-launches, tile order, XCD remapping); `tune_sim` picks the launch of a single
-Sim (tile shape, vector width, XCD remapping, streaming hints).  Each candidate
-runs a few steps from a saved state, timed with HIP events on the handle's
-stream; the state and the time are restored afterwards, so tuning does not
-change the simulation.  Results are cached in a JSON file keyed by GPU
+launches, tile order, XCD remapping, steps per pass and segment height);
+`tune_sim` picks the launch of a single Sim (tile shape, vector width, XCD
+remapping, streaming hints, steps per pass and segment height).  The library
+times each candidate (one warm-up step, then `steps` steps between HIP events)
+from a saved state and restores state and time afterwards, so tuning does not
+change the simulation.  Results are cached in a text file keyed by GPU
 architecture, lattice, precision and problem sizes.
 """
 from __future__ import annotations
 
-import hashlib
-import itertools
-import json
-import os
+import ctypes as C
 from typing import Optional
 
 import torch
 
-BATCH_BLOCKS = [(64, 4), (128, 2), (256, 1), (64, 2), (64, 1)]
-SIM_BLOCKS = [(256, 1), (128, 2), (64, 4), (128, 1), (64, 1)]
+from . import _ffi as F
+from .batch import MODES, ORDERS
+
+LAUNCH_FIELDS = ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec", "temporal", "seg_rows")
+MAX_LIBRARY_CANDIDATES = 256
 
 
-def _arch() -> str:
-    try:
-        return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
-    except Exception:
-        return "unknown"
+def _schedule_struct(batch, cand: dict) -> F.MsdSchedule:
+    cur = batch.get_schedule()
+    cur.update(cand)
+    s = F.MsdSchedule()
+    s.block_x, s.block_y = int(cur["block_x"]), int(cur["block_y"])
+    s.mode = MODES[cur["mode"]] if isinstance(cur["mode"], str) else int(cur["mode"])
+    s.order = ORDERS[cur["order"]] if isinstance(cur["order"], str) else int(cur["order"])
+    s.xcd_remap, s.nontemporal = int(cur["xcd_remap"]), int(cur["nontemporal"])
+    s.temporal, s.seg_rows = int(cur["temporal"]), int(cur["seg_rows"])
+    return s
 
 
-def _load(path):
-    if path and os.path.exists(path):
-        try:
-            with open(path) as fh:
-                return json.load(fh)
-        except (OSError, ValueError):
-            return {}
-    return {}
+def _schedule_dict(s: F.MsdSchedule) -> dict:
+    inv_m = {v: k for k, v in MODES.items()}
+    inv_o = {v: k for k, v in ORDERS.items()}
+    return dict(block_x=s.block_x, block_y=s.block_y, mode=inv_m[s.mode], order=inv_o[s.order],
+                xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows)
 
 
-def _store(path, cache):
-    if not path:
-        return
-    tmp = path + ".tmp"
-    with open(tmp, "w") as fh:
-        json.dump(cache, fh, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+def _launch_struct(sim, cand: dict) -> F.MsdLaunch:
+    cur = sim.get_launch()
+    cur.update(cand)
+    l = F.MsdLaunch()
+    for k in LAUNCH_FIELDS:
+        setattr(l, k, int(cur[k]))
+    return l
 
 
-def _time(stream, fn, steps):
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record(stream)
-    fn(steps)
-    b.record(stream)
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / 1e3 / steps
+def _launch_dict(l: F.MsdLaunch) -> dict:
+    return {k: getattr(l, k) for k in LAUNCH_FIELDS}
 
 
-def batch_key(batch) -> str:
-    sizes = sorted((n, s) for n, s in zip(batch.N, batch.shapes))
-    h = hashlib.sha256(repr(sizes).encode()).hexdigest()[:16]
-    return f"{_arch()}|batch|{batch.lattice}|{batch.precision}|{batch.count}|{h}"
-
-
-def tune_batch(batch, cache_path: Optional[str] = None, steps: int = 8, warmup: int = 2, candidates=None,
-               force: bool = False) -> dict:
-    """Choose and apply the fastest schedule; returns {'best': schedule, 'seconds_per_step': t, 'trials': [...]}."""
-    cache = _load(cache_path)
-    key = batch_key(batch)
-    if not force and key in cache:
-        batch.set_schedule(**cache[key]["best"])
-        return cache[key]
-    if candidates is None:
-        candidates = [dict(block_x=bx, block_y=by, mode=mode, order=order, xcd_remap=xcd, temporal=0)
-                      for (bx, by), mode, order, xcd in itertools.product(
-                          BATCH_BLOCKS, ("fused", "per_class"), ("instance", "interleaved"), (0, 1))]
-        if batch.lattice == "D2Q5":
-            candidates += [dict(block_x=64, block_y=4, mode="per_class", order=order, temporal=tb, seg_rows=seg)
-                           for tb, seg, order in itertools.product((2, 3, 4), (8, 16, 32), ("instance", "interleaved"))]
-    state, t0 = batch.save()
+def _run(fn, handle, struct_t, to_dict, cands, steps, budget_ms, cache_path, force, scratch, what):
+    n = len(cands)
+    arr = (struct_t * n)(*cands) if n else None
+    times = (C.c_double * (n if n else MAX_LIBRARY_CANDIDATES))()
+    for i in range(len(times)):
+        times[i] = -1.0
+    best = struct_t()
+    ms = C.c_double(0.0)
+    path = cache_path.encode() if cache_path else None
+    F.check(fn(handle, arr, n, int(steps), float(budget_ms), path, F.TUNE_IGNORE_CACHE if force else 0,
+               C.c_void_p(scratch.data_ptr()), C.c_size_t(scratch.numel()), C.byref(best), C.byref(ms), times), what)
     trials = []
-    for cand in candidates:
-        batch.set_schedule(**cand)
-        batch.step(warmup)
-        sec = _time(batch.stream, batch.step, steps)
-        batch.restore(state, t0)
-        trials.append(dict(schedule=cand, seconds_per_step=sec))
-    best = min(trials, key=lambda r: r["seconds_per_step"])
-    batch.set_schedule(**best["schedule"])
-    out = dict(best=best["schedule"], seconds_per_step=best["seconds_per_step"], trials=trials)
-    cache[key] = out
-    _store(cache_path, cache)
-    del state
-    return out
+    for i, t in enumerate(times):
+        if t >= 0:
+            trials.append(dict(candidate=to_dict(arr[i]) if n else i, seconds_per_step=t / 1e3))
+    return dict(best=to_dict(best), seconds_per_step=ms.value / 1e3, trials=trials)
 
 
-def sim_key(sim) -> str:
-    return f"{_arch()}|sim|{sim.lattice}|{sim.precision}|N{sim.N}|{'x'.join(map(str, sim.shape))}"
+def tune_batch(batch, cache_path: Optional[str] = None, steps: int = 8, warmup: int = 1, candidates=None,
+               force: bool = False, budget_ms: float = 0.0) -> dict:
+    """Choose and apply the fastest schedule (candidates: partial schedule dicts, or
+    None for the library's list).  Returns {'best': schedule, 'seconds_per_step': t,
+    'trials': [...]} (no trials on a cache hit).  The library runs one warm-up step
+    per candidate; `warmup` is accepted for compatibility."""
+    cands = [_schedule_struct(batch, c) for c in candidates] if candidates else []
+    scratch = torch.empty(max(batch.state_bytes(), 1), dtype=torch.uint8, device=batch.device)
+    return _run(batch.lib.msd_batch_tune, batch._h, F.MsdSchedule, _schedule_dict, cands, steps, budget_ms,
+                cache_path, force, scratch, "msd_batch_tune")
 
 
-def tune_sim(sim, cache_path: Optional[str] = None, steps: int = 10, warmup: int = 2, candidates=None,
-             force: bool = False) -> dict:
-    """Choose and apply the fastest launch of the single-mixture sweep."""
-    cache = _load(cache_path)
-    key = sim_key(sim)
-    if not force and key in cache:
-        sim.set_launch(**cache[key]["best"])
-        return cache[key]
-    if candidates is None:
-        candidates = [dict(block_x=bx, block_y=by, vec=vec, xcd_remap=xcd, nontemporal=nt, temporal=0)
-                      for (bx, by), vec, xcd, nt in itertools.product(SIM_BLOCKS, (0, 1, 4), (0, 1), (0, 7))]
-        if sim.lattice == "D2Q5":
-            candidates += [dict(temporal=tb, seg_rows=seg, nontemporal=nt)
-                           for tb, seg, nt in itertools.product((2, 3, 4), (16, 32, 64), (0, 1))]
-    state, t0 = sim.save()
-    trials = []
-    for cand in candidates:
-        sim.set_launch(**cand)
-        sim.step(warmup)
-        sec = _time(sim.stream, sim.step, steps)
-        sim.restore(state, t0)
-        trials.append(dict(launch=cand, seconds_per_step=sec))
-    best = min(trials, key=lambda r: r["seconds_per_step"])
-    sim.set_launch(**best["launch"])
-    out = dict(best=best["launch"], seconds_per_step=best["seconds_per_step"], trials=trials)
-    cache[key] = out
-    _store(cache_path, cache)
-    del state
-    return out
+def tune_sim(sim, cache_path: Optional[str] = None, steps: int = 10, warmup: int = 1, candidates=None,
+             force: bool = False, budget_ms: float = 0.0) -> dict:
+    """Choose and apply the fastest launch of the single-mixture sweep (candidates:
+    partial launch dicts, or None for the library's list)."""
+    cands = [_launch_struct(sim, c) for c in candidates] if candidates else []
+    scratch = torch.empty(max(sim.state_bytes(), 1), dtype=torch.uint8, device=sim.device)
+    return _run(sim.lib.msd_tune, sim._h, F.MsdLaunch, _launch_dict, cands, steps, budget_ms, cache_path, force,
+                scratch, "msd_tune")

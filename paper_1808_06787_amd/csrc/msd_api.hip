@@ -8,10 +8,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "../../include/msd.h"
 #include "msd_host.h"
@@ -34,6 +36,51 @@ int fail(int status, const char* fmt, ...) {
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(MSD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+bool cache_lookup(const char* path, const std::string& key, int k, int64_t* vals, double* ms) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char* save = nullptr;
+    const char* tok = strtok_r(line, " \t\n", &save);
+    if (!tok || key != tok) continue;
+    int64_t v[16];
+    int got = 0;
+    while (got <= k && (tok = strtok_r(nullptr, " \t\n", &save))) {
+      if (got < k) v[got] = std::strtoll(tok, nullptr, 10);
+      else *ms = std::strtod(tok, nullptr);
+      ++got;
+    }
+    if (got == k + 1) {   // the last matching line wins
+      for (int i = 0; i < k; ++i) vals[i] = v[i];
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, int k, const int64_t* vals, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s", key.c_str());
+  for (int i = 0; i < k; ++i) std::fprintf(f, " %lld", (long long)vals[i]);
+  std::fprintf(f, " %.6f\n", ms);
+  std::fclose(f);
 }
 
 int validate(const msd_problem* p) {
@@ -756,6 +803,96 @@ int msd_adjoint(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, 
     if (in_b) std::swap(a, b);
   }
   return msd_adjoint_finish(s, a, acc, d_dL_dxi0, h_dL_dD);
+}
+
+int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t steps, double budget_ms,
+             const char* cache_path, int32_t flags, void* d_scratch, size_t scratch_bytes, msd_launch* h_best,
+             double* h_ms_per_step, double* h_trial_ms) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  if (steps < 1) return fail(MSD_EINVAL, "steps = %d", steps);
+  if (count < 0 || (count > 0 && !candidates)) return fail(MSD_EINVAL, "count = %d", count);
+  if (!s->initialised) return fail(MSD_ESTATE, "tuning before msd_init");
+  // key: architecture, lattice, precision, species, extents, faces
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|sim|%d|%d|N%d|%lldx%lldx%lld|%d%d%d%d%d%d", device_arch().c_str(),
+                s->prob.lattice, s->prob.precision, s->prob.n_species, (long long)s->prob.nx, (long long)s->prob.ny,
+                (long long)s->prob.nz, s->prob.bc[0], s->prob.bc[1], s->prob.bc[2], s->prob.bc[3], s->prob.bc[4],
+                s->prob.bc[5]);
+  const std::string key = buf;
+  constexpr int K = 8;
+  auto pack = [](const msd_launch& l, int64_t* v) {
+    v[0] = l.block_x; v[1] = l.block_y; v[2] = l.xcd_remap; v[3] = l.lds_resident;
+    v[4] = l.nontemporal; v[5] = l.vec; v[6] = l.temporal; v[7] = l.seg_rows;
+  };
+  auto unpack = [](const int64_t* v) {
+    msd_launch l;
+    l.block_x = (int32_t)v[0]; l.block_y = (int32_t)v[1]; l.xcd_remap = (int32_t)v[2]; l.lds_resident = (int32_t)v[3];
+    l.nontemporal = (int32_t)v[4]; l.vec = (int32_t)v[5]; l.temporal = (int32_t)v[6]; l.seg_rows = (int32_t)v[7];
+    return l;
+  };
+  int64_t cached[K];
+  double cms = 0.0;
+  if (!(flags & MSD_TUNE_IGNORE_CACHE) && cache_lookup(cache_path, key, K, cached, &cms)) {
+    const msd_launch l = unpack(cached);
+    const int st = msd_set_launch(s, &l);
+    if (st == MSD_OK) {
+      if (h_best) *h_best = l;
+      if (h_ms_per_step) *h_ms_per_step = cms;
+      return MSD_OK;
+    }
+  }
+  std::vector<msd_launch> cand;
+  if (count > 0) {
+    cand.assign(candidates, candidates + count);
+  } else {
+    const int blocks[5][2] = {{256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 1}};
+    msd_launch base = s->launch;
+    for (auto& b : blocks)
+      for (int vec : {0, 1, 4})
+        for (int xcd : {0, 1})
+          for (int nt : {0, 7}) {
+            msd_launch l = base;
+            l.block_x = b[0]; l.block_y = b[1]; l.vec = vec; l.xcd_remap = xcd; l.nontemporal = nt; l.temporal = 0;
+            cand.push_back(l);
+          }
+    if (s->prob.lattice == MSD_D2Q5)
+      for (int tb : {2, 3, 4})
+        for (int seg : {0, 16, 32, 48})
+          for (int nt : {0, 1}) {
+            msd_launch l = base;
+            l.temporal = tb; l.seg_rows = seg; l.nontemporal = nt; l.vec = 0;
+            cand.push_back(l);
+          }
+  }
+  const size_t sb = msd_state_bytes(s);
+  if (!d_scratch || scratch_bytes < sb) return fail(MSD_ENOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, sb);
+  const msd_launch keep = s->launch;
+  int64_t t0 = 0;
+  int st = msd_save(s, d_scratch, &t0);
+  if (st != MSD_OK) return st;
+  std::vector<double> ms(cand.size(), -1.0);
+  int best = -1;
+  st = time_candidates(
+      s->stream, (int)cand.size(), steps, budget_ms, [&](int i) { return msd_set_launch(s, &cand[i]); },
+      [&](int n) { return msd_step(s, n); }, [&]() { return msd_restore(s, d_scratch, t0); }, ms.data(), &best);
+  if (h_trial_ms)
+    for (size_t i = 0; i < cand.size(); ++i) h_trial_ms[i] = ms[i];
+  if (st != MSD_OK) {
+    msd_set_launch(s, &keep);
+    return st;
+  }
+  if (best < 0) {
+    msd_set_launch(s, &keep);
+    return fail(MSD_EINVAL, "no candidate launch could run");
+  }
+  st = msd_set_launch(s, &cand[best]);
+  if (st != MSD_OK) return st;
+  int64_t v[K];
+  pack(s->launch, v);
+  cache_store(cache_path, key, K, v, ms[best]);
+  if (h_best) *h_best = s->launch;
+  if (h_ms_per_step) *h_ms_per_step = ms[best];
+  return MSD_OK;
 }
 
 int msd_destroy(msd_sim* s) {

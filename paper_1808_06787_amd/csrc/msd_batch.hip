@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -508,6 +510,98 @@ int msd_batch_restore(msd_batch* b, const void* d_src, int64_t step) {
     src += M.state_bytes;
   }
   b->t = step;
+  return MSD_OK;
+}
+
+int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, int32_t steps, double budget_ms,
+                   const char* cache_path, int32_t flags, void* d_scratch, size_t scratch_bytes, msd_schedule* h_best,
+                   double* h_ms_per_step, double* h_trial_ms) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (steps < 1) return fail(MSD_EINVAL, "steps = %d", steps);
+  if (count < 0 || (count > 0 && !candidates)) return fail(MSD_EINVAL, "count = %d", count);
+  int st = all_initialised(b);
+  if (st != MSD_OK) return st;
+  // key: architecture, lattice, precision, mixture count and a hash of the
+  // sorted (N, extents, faces) of the mixtures
+  std::vector<std::array<int64_t, 10>> sig;
+  for (const Member& M : b->mem)
+    sig.push_back({M.m + 1, M.prob.nx, M.prob.ny, M.prob.nz, M.prob.bc[0], M.prob.bc[1], M.prob.bc[2], M.prob.bc[3],
+                   M.prob.bc[4], M.prob.bc[5]});
+  std::sort(sig.begin(), sig.end());
+  const uint64_t h = fnv1a(sig.data(), sig.size() * sizeof(sig[0]));
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|batch|%d|%d|%d|%016llx", device_arch().c_str(), b->lattice, b->prec, b->count,
+                (unsigned long long)h);
+  const std::string key = buf;
+  constexpr int K = 8;
+  auto pack = [](const msd_schedule& c, int64_t* v) {
+    v[0] = c.block_x; v[1] = c.block_y; v[2] = c.mode; v[3] = c.order;
+    v[4] = c.xcd_remap; v[5] = c.nontemporal; v[6] = c.temporal; v[7] = c.seg_rows;
+  };
+  auto unpack = [](const int64_t* v) {
+    msd_schedule c;
+    c.block_x = (int32_t)v[0]; c.block_y = (int32_t)v[1]; c.mode = (int32_t)v[2]; c.order = (int32_t)v[3];
+    c.xcd_remap = (int32_t)v[4]; c.nontemporal = (int32_t)v[5]; c.temporal = (int32_t)v[6]; c.seg_rows = (int32_t)v[7];
+    return c;
+  };
+  int64_t cached[K];
+  double cms = 0.0;
+  if (!(flags & MSD_TUNE_IGNORE_CACHE) && cache_lookup(cache_path, key, K, cached, &cms)) {
+    const msd_schedule c = unpack(cached);
+    if (msd_batch_set_schedule(b, &c) == MSD_OK) {
+      if (h_best) *h_best = c;
+      if (h_ms_per_step) *h_ms_per_step = cms;
+      return MSD_OK;
+    }
+  }
+  std::vector<msd_schedule> cand;
+  if (count > 0) {
+    cand.assign(candidates, candidates + count);
+  } else {
+    const int blocks[5][2] = {{64, 4}, {128, 2}, {256, 1}, {64, 2}, {64, 1}};
+    for (auto& bl : blocks)
+      for (int mode : {MSD_BATCH_FUSED, MSD_BATCH_PER_CLASS})
+        for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED})
+          for (int xcd : {0, 1}) {
+            msd_schedule c{};
+            c.block_x = bl[0]; c.block_y = bl[1]; c.mode = mode; c.order = order; c.xcd_remap = xcd;
+            cand.push_back(c);
+          }
+    if (b->lattice == MSD_D2Q5)
+      for (int tb : {2, 3, 4})
+        for (int seg : {8, 16, 32})
+          for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED}) {
+            msd_schedule c{};
+            c.block_x = 64; c.block_y = 4; c.mode = MSD_BATCH_PER_CLASS; c.order = order;
+            c.temporal = tb; c.seg_rows = seg;
+            cand.push_back(c);
+          }
+  }
+  const size_t sb = msd_batch_state_bytes(b);
+  if (!d_scratch || scratch_bytes < sb) return fail(MSD_ENOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, sb);
+  const msd_schedule keep = b->sched;
+  int64_t t0 = 0;
+  st = msd_batch_save(b, d_scratch, &t0);
+  if (st != MSD_OK) return st;
+  std::vector<double> ms(cand.size(), -1.0);
+  int best = -1;
+  st = time_candidates(
+      b->stream, (int)cand.size(), steps, budget_ms, [&](int i) { return msd_batch_set_schedule(b, &cand[i]); },
+      [&](int n) { return msd_batch_step(b, n); }, [&]() { return msd_batch_restore(b, d_scratch, t0); }, ms.data(),
+      &best);
+  if (h_trial_ms)
+    for (size_t i = 0; i < cand.size(); ++i) h_trial_ms[i] = ms[i];
+  if (st != MSD_OK || best < 0) {
+    msd_batch_set_schedule(b, &keep);
+    return st != MSD_OK ? st : fail(MSD_EINVAL, "no candidate schedule could run");
+  }
+  st = msd_batch_set_schedule(b, &cand[best]);
+  if (st != MSD_OK) return st;
+  int64_t v[K];
+  pack(b->sched, v);
+  cache_store(cache_path, key, K, v, ms[best]);
+  if (h_best) *h_best = b->sched;
+  if (h_ms_per_step) *h_ms_per_step = ms[best];
   return MSD_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/msd.h"
 #include "msd_launch.h"
@@ -34,6 +35,60 @@ Layout layout_for(const msd_problem* p);
 void fill_kernel_problem(const msd_problem* problem, int64_t plane, Problem* out);
 hipError_t dispatch(Op op, const LaunchArgs& a);
 void default_launch(const msd_problem* p, msd_launch* l);
+
+// --- tuning ------------------------------------------------------------------
+// 64-bit FNV-1a hash (keys of the tuning cache).
+inline uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+// GPU architecture name of the current device ("gfx950"), "unknown" on error.
+std::string device_arch();
+// Tuning cache: a text file of lines "<key> <v1> ... <vk> <ms per step>".
+// lookup returns true and fills vals/ms when the key is present with k values.
+bool cache_lookup(const char* path, const std::string& key, int k, int64_t* vals, double* ms);
+void cache_store(const char* path, const std::string& key, int k, const int64_t* vals, double ms);
+
+// Times candidates 0..n-1: apply(i) selects one (nonzero status: skipped, time
+// -1), then one warm-up step, `steps` steps between two events on `stream`, and
+// restore() puts state and time back.  Stops once budget_ms of timed GPU work
+// is spent (<= 0: no limit; untried candidates get -1).  Returns the index of
+// the fastest candidate in *best (-1 if none ran) or a status.
+template <class Apply, class Step, class Restore>
+int time_candidates(hipStream_t stream, int n, int steps, double budget_ms, Apply apply, Step step, Restore restore,
+                    double* ms, int* best) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "tuning events");
+  *best = -1;
+  double spent = 0.0;
+  int st = MSD_OK;
+  for (int i = 0; i < n; ++i) ms[i] = -1.0;
+  for (int i = 0; i < n && st == MSD_OK; ++i) {
+    if (budget_ms > 0 && spent >= budget_ms) break;
+    if (apply(i) != MSD_OK) continue;
+    st = step(1);
+    if (st != MSD_OK) break;
+    e = hipEventRecord(e0, stream);
+    if (e != hipSuccess) { st = hip_fail(e, "tuning event"); break; }
+    st = step(steps);
+    if (st != MSD_OK) break;
+    e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) { st = hip_fail(e, "tuning timing"); break; }
+    spent += t;
+    ms[i] = (double)t / steps;
+    if (*best < 0 || ms[i] < ms[*best]) *best = i;
+    st = restore();
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
 
 }  // namespace host
 }  // namespace msd

@@ -160,7 +160,11 @@ def test_batch_checkpoint_and_autotuner_keep_the_state(tmp_path):
             np.testing.assert_allclose(x, y, rtol=0, atol=1e-13)
     # cached result is applied without re-timing
     res2 = autotune.tune_batch(b, cache_path=str(tmp_path / "tune.json"))
-    assert res2["best"] == res["best"] and b.get_schedule()["block_x"] == res["best"]["block_x"]
+    assert res2["best"] == res["best"] and b.get_schedule() == res["best"] and res2["trials"] == []
+    # explicit candidates, cache ignored
+    res3 = autotune.tune_batch(b, cache_path=str(tmp_path / "tune.json"), steps=2, force=True,
+                               candidates=[dict(temporal=0, mode="fused"), dict(temporal=2, seg_rows=8)])
+    assert len(res3["trials"]) == 2 and b.get_schedule() == res3["best"]
     b.close()
 
 

@@ -160,3 +160,32 @@ def test_table_I_on_the_gpu():
                 np.testing.assert_allclose(xi[:, :4], oxi, rtol=0, atol=1e-12)
                 np.testing.assert_allclose(J[:, :, :4], oJ, rtol=0, atol=1e-12 * np.abs(oJ).max())
         s.close()
+
+
+def test_sim_autotuner_keeps_state_and_caches(tmp_path):
+    """msd_tune times candidate launches from a saved state and restores it: the
+    run continues as if untuned (to FP32 rounding: the chosen launch may take
+    passes of another length); a second call is served by the cache."""
+    from paper_1808_06787_amd import autotune
+
+    rng = np.random.default_rng(76)
+    D = rand_D(rng, 3)
+    shape = (600, 300)
+    xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
+    ref = _sim("D2Q5", D, shape, "f32", xi0)
+    ref.step(17)
+    want = ref.read()[0].cpu().numpy()
+    ref.close()
+    s = _sim("D2Q5", D, shape, "f32", xi0)
+    s.step(5)
+    cache = str(tmp_path / "tune.txt")
+    res = autotune.tune_sim(s, cache_path=cache, steps=2)
+    assert s.time == 5 and len(res["trials"]) > 20 and s.get_launch() == res["best"]
+    s.step(12)
+    np.testing.assert_allclose(s.read()[0].cpu().numpy(), want, rtol=0, atol=2e-6)
+    res2 = autotune.tune_sim(s, cache_path=cache)
+    assert res2["best"] == res["best"] and res2["trials"] == []
+    res3 = autotune.tune_sim(s, cache_path=cache, steps=2, force=True,
+                             candidates=[dict(temporal=0, block_x=128, block_y=2), dict(temporal=2, seg_rows=8)])
+    assert len(res3["trials"]) == 2 and s.get_launch() == res3["best"]
+    s.close()
