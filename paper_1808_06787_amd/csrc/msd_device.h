@@ -85,15 +85,12 @@ struct Problem {
   double xi_ref[kMaxSpecies];
 };
 
-// 1/x.  FP32: the hardware reciprocal (within 1 ulp) refined by one
-// Newton-Raphson step r <- r + r (1 - x r), which lands within about an ulp of
-// the correctly rounded quotient at a third of the instructions of an IEEE
-// division; FP64: the IEEE quotient.
+// 1/x.  FP32: the hardware reciprocal, within 1 ulp of the quotient (an IEEE
+// FP32 division costs about ten instructions); FP64: the IEEE quotient.
 template <typename T>
 __device__ __forceinline__ T recip(T x) {
   if constexpr (sizeof(T) == 4) {
-    const float r = __builtin_amdgcn_rcpf(x);
-    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+    return __builtin_amdgcn_rcpf(x);
   } else {
     return T(1) / x;
   }
@@ -240,7 +237,10 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T
   }
 
   // f^+_k = f_k - Lambda_1 neq_k - delta * even_k   (Lambda_2 = Lambda_1 + diag(delta)),
-  // even_k = (neq_k + neq_kbar) / 2, so delta * even_k = hd * (neq_k + neq_kbar).
+  // even_k = (neq_k + neq_kbar) / 2, so delta * even_k = hd * (neq_k + neq_kbar):
+  // f^+_k = f_k - G neq_k - hd * neq_kbar with G = Lambda_1 + diag(hd) (k = kbar for the rest).
+#pragma unroll
+  for (int i = 0; i < M; ++i) L1[i][i] += hd[i];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int kb = L::opp(k);
@@ -249,8 +249,8 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T
       T acc = L1[i][0] * neq[0][k];
 #pragma unroll
       for (int j = 1; j < M; ++j) acc += L1[i][j] * neq[j][k];
-      const T pair = (k == kb) ? T(2) * neq[i][k] : neq[i][k] + neq[i][kb];
-      f[i][k] = f[i][k] - (acc + hd[i] * pair);
+      acc += hd[i] * neq[i][kb];
+      f[i][k] = f[i][k] - acc;
     }
   }
 }
