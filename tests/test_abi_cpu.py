@@ -150,3 +150,47 @@ def test_adjoint_and_query_calls_reject_null_handles():
     assert lib.msd_adjoint(None, 10, 5, g, g, None, None, g, C.c_size_t(1 << 20)) == -1
     assert lib.msd_steps_per_pass(None) == -1
     assert lib.msd_record(None, 3, g) == -1
+
+
+def test_blocked_plan_limits_without_device():
+    """Steps per pass from the host plan alone (explicit segment height: no device
+    query; the handle is created over a workspace address that is never touched):
+    the species count and precision cap the pass, and planes of 4 GiB or more (32-bit
+    in-plane offsets) fall back to one step per pass."""
+    lib = F.lib()
+    rng = np.random.default_rng(5)
+
+    def D(n):
+        m = np.ones((n, n))
+        iu = np.triu_indices(n, 1)
+        m[iu] = rng.uniform(0.05, 0.3, size=len(iu[0]))
+        return np.triu(m, 1) + np.triu(m, 1).T + np.eye(n)
+
+    cases = [
+        ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 4),
+        ("D2Q5", 3, "f32", (32768, 32768), dict(seg_rows=16), 1),
+        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 3),
+        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 2),
+        ("D2Q5", 6, "f32", (4096, 1024), dict(seg_rows=16), 1),
+        ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 4),
+        ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16), 2),
+        ("D2Q5", 4, "f64", (4096, 1024), dict(seg_rows=16), 1),
+        ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=3), 3),
+        ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=0), 1),
+        ("D2Q5", 3, "f32", (5, 3), dict(seg_rows=16), 4),
+        ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
+        ("D1Q3", 3, "f64", (256,), dict(seg_rows=16), 1),
+    ]
+    for lattice, N, prec, shape, launch, want in cases:
+        p, keep = make_problem(lattice, D(N), shape, prec)
+        n, st = _ws(p)
+        assert st == 0
+        h = C.c_void_p()
+        assert lib.msd_create(C.byref(p), C.c_void_p(1 << 40), C.c_size_t(n), None, C.byref(h)) == 0
+        l = F.MsdLaunch()
+        assert lib.msd_get_launch(h, C.byref(l)) == 0
+        for k, v in launch.items():
+            setattr(l, k, v)
+        assert lib.msd_set_launch(h, C.byref(l)) == 0
+        assert lib.msd_steps_per_pass(h) == want, (lattice, N, prec, shape, launch)
+        lib.msd_destroy(h)

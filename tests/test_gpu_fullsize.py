@@ -76,8 +76,60 @@ def _sampled_parity(w, steps, nsamples, seed):
 
 
 def test_ternary_2d_full_size_sampled():
+    """9 steps: the first from the initial state, then two blocked passes of 4."""
     w = workloads.ternary_2d()
-    print("worst |dxi|", _sampled_parity(w, 4, 24, 1))
+    print("worst |dxi|", _sampled_parity(w, 9, 24, 1))
+
+
+def _wave_field(x, y, n, N, xp):
+    """Smooth periodic ternary field on an n x n lattice (x, y: node indices, any
+    array module xp): three plane waves per species about 1/N, normalised."""
+    comps = []
+    for i in range(N):
+        v = 1.0 / N + 0.03 * (xp.cos(2 * np.pi * ((i + 1) * x / n + 2 * y / n) + i)
+                              + xp.cos(2 * np.pi * (3 * x / n - (i + 2) * y / n) + 0.5 * i)
+                              + xp.sin(2 * np.pi * ((i + 4) * y / n) + 0.3))
+        comps.append(v)
+    tot = sum(comps)
+    return [c / tot for c in comps]
+
+
+def test_largest_blocked_planes_sampled():
+    """A 16384^2 ternary FP32 lattice (planes of 1 GiB, state of 10.7 GB per buffer:
+    the blocked sweep's 32-bit in-plane offsets at their largest power-of-two
+    square) after 9 steps, sampled against the oracle on light cones; the field is
+    built on the device and, for the patches, on the host from the same formula."""
+    from paper_1808_06787_amd.sim import Sim
+
+    n, N, steps = 16384, 3, 9
+    rng = np.random.default_rng(9)
+    Dm = np.ones((N, N))
+    for i in range(N):
+        for j in range(i + 1, N):
+            Dm[i, j] = Dm[j, i] = float(np.exp(rng.uniform(np.log(0.05), np.log(0.5))))
+    dev = torch.device("cuda", 0)
+    yy, xx = torch.meshgrid(torch.arange(n, dtype=torch.float64, device=dev),
+                            torch.arange(n, dtype=torch.float64, device=dev), indexing="ij")
+    xi0 = torch.stack(_wave_field(xx, yy, n, N, torch))
+    del xx, yy
+    sim = Sim("D2Q5", Dm, (n, n), "f32")
+    assert sim.steps_per_pass() == 4
+    sim.init(xi0)
+    del xi0
+    sim.step(steps)
+    xi, J, _ = sim.read(torch.float32, grad=False)
+    h = steps + 1
+    nodes = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(10)] + [(0, 0), (n - 1, n - 1)]
+    for (x, y) in nodes:
+        ix = np.arange(x - h, x + h + 1) % n
+        iy = np.arange(y - h, y + h + 1) % n
+        X, Y = np.meshgrid(ix.astype(np.float64), iy.astype(np.float64))
+        sub = np.stack(_wave_field(X, Y, n, N, np))
+        p = lbm.Problem("D2Q5", Dm, (2 * h + 1, 2 * h + 1), bc=((lbm.ZERO_FLUX, lbm.ZERO_FLUX),) * 2)
+        oxi, _, oJ = lbm.observables(p, lbm.run(p, sub, steps))
+        assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= 1e-5, (x, y)
+        assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= 2e-6, (x, y)
+    sim.close()
 
 
 def test_quaternary_3d_full_size_sampled():

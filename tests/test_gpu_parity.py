@@ -237,6 +237,7 @@ BLOCKED_CASES = [
     ((257, 40), (("periodic", "periodic"), ("dirichlet", "zero_flux"))),
     ((70, 130), (("dirichlet", "dirichlet"), ("zero_flux", "dirichlet"))),
     ((3, 700), (("periodic", "periodic"), ("periodic", "periodic"))),
+    ((2, 50), (("zero_flux", "zero_flux"), ("dirichlet", "zero_flux"))),
 ]
 
 
