@@ -257,14 +257,14 @@ typedef struct msd_launch {
                                vector accesses; used when nx % vec == 0, else the largest
                                power of two dividing nx); 0 (default) selects the general
                                one-node-per-thread kernel */
-  int32_t temporal;         /* D2Q5 only: at most this many steps (2, 3 or 4) per pass over
-                               HBM (temporally blocked sweep: each workgroup marches along y
+  int32_t temporal;         /* D2Q5 only: at most this many steps (2 .. 6) per pass over HBM
+                               (temporally blocked sweep: each workgroup marches along y
                                with the intermediate time levels of a few rows on chip); 0 or
                                1: one step per pass.  The library takes the largest count up
                                to this one whose on-chip window fits the species count and
-                               precision (FP32: m <= 2 up to 4, m = 3 up to 3, m = 4 up to 2;
-                               FP64: m = 1 up to 4, m = 2 up to 2; else one step per pass).
-                               Default 4 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
+                               precision (FP32: m <= 2 up to 6, m = 3 up to 4, m = 4 up to 2;
+                               FP64: m = 1 up to 6, m = 2 up to 2; else one step per pass).
+                               Default 6 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
                                automatic, segments sized so that the launch holds about 1.35
                                times the workgroups the device runs at once, at least 8 rows,
@@ -297,9 +297,9 @@ MSD_API int msd_tune(msd_sim* sim, const msd_launch* candidates, int32_t count, 
                      msd_launch* h_best, double* h_ms_per_step, double* h_trial_ms);
 
 /* Time steps the sweep advances per pass over HBM (one kernel launch) under the
- * current launch configuration: the temporally blocked count (2..4) or 1.  The
- * step from time 0 (from the state msd_init writes) and a remainder shorter
- * than a pass run one step per launch.  Negative status (MSD_EINVAL) for a NULL
+ * current launch configuration: the temporally blocked count (2..6) or 1.  The
+ * step from time 0 (from the state msd_init writes) runs alone, and a remainder
+ * shorter than a pass runs as one shorter pass (a single step if it is one).  Negative status (MSD_EINVAL) for a NULL
  * handle. */
 MSD_API int msd_steps_per_pass(const msd_sim* sim);
 
@@ -330,12 +330,12 @@ typedef struct msd_schedule {
   int32_t order;            /* enum msd_tile_order */
   int32_t xcd_remap;        /* 1: consecutive tiles of a launch on one XCD */
   int32_t nontemporal;      /* streaming-hint mask, as in msd_launch */
-  int32_t temporal;         /* D2Q5: at most this many steps (2..4) per pass over HBM with the
+  int32_t temporal;         /* D2Q5: at most this many steps (2..6) per pass over HBM with the
                                temporally blocked sweep, as in msd_launch (each class of equal
                                N takes the largest count its on-chip window allows; classes
                                then launch separately whatever `mode` says, and block_x,
                                block_y, order apply to their single steps); 0 or 1: one step
-                               per launch.  Default 4 for D2Q5, 0 otherwise */
+                               per launch.  Default 6 for D2Q5, 0 otherwise */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep (0: 16) */
 } msd_schedule;
 

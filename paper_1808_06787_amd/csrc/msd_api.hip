@@ -206,9 +206,10 @@ Layout layout_for(const msd_problem* p) {
 // one-node-per-thread kernel with 256-thread row tiles runs at the speed of a
 // plain copy of the same planes; vector widths 2/4, streaming hints and plane
 // padding do not improve on it.  Remapping tiles onto XCDs helps in 3D (+1.5 %)
-// and costs 3 % in 2D.  In 2D the temporally blocked sweep with four steps per
-// pass and 16-row segments is 2.7x faster than one step per pass (ternary,
-// FP32); the species count and precision may lower the steps per pass.
+// and costs 3 % in 2D.  In 2D the temporally blocked sweep with six steps per
+// pass is 3.6x faster than one step per pass (4096^2 ternary FP32: 68.7 vs
+// 245 us per step; four steps per pass 84.8 us, five 74.4 us); the species
+// count and precision may lower the steps per pass.
 void default_launch(const msd_problem* p, msd_launch* l) {
   std::memset(l, 0, sizeof(*l));
   l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
@@ -217,7 +218,7 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
-  l->temporal = p->lattice == MSD_D2Q5 ? 4 : 0;
+  l->temporal = p->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass : 0;
   l->seg_rows = 0;
 }
 
@@ -238,8 +239,8 @@ struct msd_sim {
   bool initialised = false;
   msd_launch launch{};
   // resident workgroups of the blocked kernels by steps per pass (0: not queried)
-  mutable int resident_fwd[5] = {0, 0, 0, 0, 0};
-  mutable int resident_adj[5] = {0, 0, 0, 0, 0};
+  mutable int resident_fwd[msd::kMaxStepsPerPass + 1] = {};
+  mutable int resident_adj[msd::kMaxStepsPerPass + 1] = {};
 };
 
 namespace {
@@ -393,7 +394,8 @@ int msd_set_launch(msd_sim* s, const msd_launch* l) {
     v.block_y = d.block_y;
   }
   if (v.nontemporal < 0 || v.nontemporal > 7) return fail(MSD_EINVAL, "nontemporal mask %d", v.nontemporal);
-  if (v.temporal < 0 || v.temporal > 4) return fail(MSD_EINVAL, "temporal = %d must be 0..4", v.temporal);
+  if (v.temporal < 0 || v.temporal > msd::kMaxStepsPerPass)
+    return fail(MSD_EINVAL, "temporal = %d must be 0..%d", v.temporal, msd::kMaxStepsPerPass);
   if (v.seg_rows < 0 || v.seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", v.seg_rows);
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4)
     return fail(MSD_EINVAL, "vec = %d must be 0, 1, 2 or 4", v.vec);
@@ -460,13 +462,15 @@ int msd_step(msd_sim* s, int64_t nsteps) {
     a.pull = s->t > 0 ? 1 : 0;
     int64_t done = 1;
     hipError_t e;
-    if (tb >= 2 && s->t > 0 && nsteps - n >= tb) {
-      // tb steps in one pass; the first step after msd_init reads pre-collision
-      // values and is always a single step
-      a.tb = tb;
+    const int pass = (int)std::min<int64_t>(tb, nsteps - n);
+    if (tb >= 2 && s->t > 0 && pass >= 2) {
+      // tb steps in one pass (a remainder of two or more in one shorter pass);
+      // the first step after msd_init reads pre-collision values and is always
+      // a single step
+      a.tb = pass;
       a.seg_rows = plan.seg;
       e = dispatch(msd::Op::StepBlocked, a);
-      done = tb;
+      done = pass;
     } else {
       e = dispatch(msd::Op::Step, a);
     }
@@ -571,14 +575,15 @@ int msd_record(msd_sim* s, int64_t nsteps, void* d_stack) {
     a.pull = (s->t + n) > 0 ? 1 : 0;
     int64_t done = 1;
     hipError_t e;
-    if (plan.tb >= 2 && s->t + n > 0 && nsteps - n >= plan.tb) {
+    const int pass = (int)std::min<int64_t>(plan.tb, nsteps - n);
+    if (plan.tb >= 2 && s->t + n > 0 && pass >= 2) {
       // one pass writes the states after each of its steps into consecutive slots
-      a.tb = plan.tb;
+      a.tb = pass;
       a.seg_rows = plan.seg;
       a.rec_stride = (int64_t)(sb / (size_t)s->prob.precision);
       e = dispatch(msd::Op::StepBlocked, a);
       a.rec_stride = 0;
-      done = plan.tb;
+      done = pass;
     } else {
       e = dispatch(msd::Op::Step, a);
     }
@@ -856,7 +861,7 @@ int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t st
             cand.push_back(l);
           }
     if (s->prob.lattice == MSD_D2Q5)
-      for (int tb : {2, 3, 4})
+      for (int tb : {2, 3, 4, 5, 6})
         for (int seg : {0, 16, 32, 48})
           for (int nt : {0, 1}) {
             msd_launch l = base;

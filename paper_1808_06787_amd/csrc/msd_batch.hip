@@ -295,7 +295,7 @@ int msd_batch_create(const msd_problem* problems, int32_t count, void* d_ws, siz
   b->sched.order = MSD_ORDER_INSTANCE;
   b->sched.xcd_remap = 0;
   b->sched.nontemporal = 0;
-  b->sched.temporal = b->lattice == MSD_D2Q5 ? 4 : 0;
+  b->sched.temporal = b->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass : 0;
   b->sched.seg_rows = 0;
   const int s2 = build_tiles(b);
   if (s2 != MSD_OK) {
@@ -314,7 +314,8 @@ int msd_batch_set_schedule(msd_batch* b, const msd_schedule* sc) {
   if (sc->order != MSD_ORDER_INSTANCE && sc->order != MSD_ORDER_INTERLEAVED)
     return fail(MSD_EINVAL, "order %d", sc->order);
   if (sc->nontemporal < 0 || sc->nontemporal > 7) return fail(MSD_EINVAL, "nontemporal %d", sc->nontemporal);
-  if (sc->temporal < 0 || sc->temporal > 4) return fail(MSD_EINVAL, "temporal = %d must be 0..4", sc->temporal);
+  if (sc->temporal < 0 || sc->temporal > msd::kMaxStepsPerPass)
+    return fail(MSD_EINVAL, "temporal = %d must be 0..%d", sc->temporal, msd::kMaxStepsPerPass);
   if (sc->seg_rows < 0 || sc->seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", sc->seg_rows);
   b->sched = *sc;
   return build_tiles(b);
@@ -568,7 +569,7 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
             cand.push_back(c);
           }
     if (b->lattice == MSD_D2Q5)
-      for (int tb : {2, 3, 4})
+      for (int tb : {2, 3, 4, 5, 6})
         for (int seg : {8, 16, 32})
           for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED}) {
             msd_schedule c{};

@@ -359,8 +359,10 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   static_assert(L::axis(1) == 0 && L::sgn(1) > 0 && L::axis(3) == 0 && L::sgn(3) < 0, "x directions");
   static_assert(L::axis(2) == 1 && L::sgn(2) > 0 && L::axis(4) == 1 && L::sgn(4) < 0, "y directions");
   constexpr int KXP = 1, KYP = 2, KXM = 3, KYM = 4;
-  // x-direction populations of each level's two most recent rows: [level][row parity][+x/-x][species][column]
-  __shared__ T xs[TB][2][2][M][C];
+  // x-direction populations of the two most recent rows of levels 1 .. TB-1:
+  // [level - 1][row parity][+x/-x][species][column].  Level 0 (the input rows)
+  // takes its x-neighbours straight from memory instead.
+  __shared__ T xs[TB - 1][2][2][M][C];
 
   const int c = (int)threadIdx.x;
   const int cm = c > 0 ? c - 1 : 0, cp = c < C - 1 ? c + 1 : C - 1;
@@ -374,6 +376,8 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   const bool x_in = x >= 0 && x < nx;
   const bool col_ok = x_in || px;
   const uint32_t xl = (uint32_t)(x_in ? x : (((x % nx) + nx) % nx));
+  // neighbour columns (wrapped; at a wall the face rule replaces what they give)
+  const uint32_t xlm = xl > 0 ? xl - 1 : (uint32_t)nx - 1, xlp = xl + 1 < (uint32_t)nx ? xl + 1 : 0;
   // a tile that reaches an x wall (uniform): only there do x-pulls need the face rule
   const bool tile_xwall = !px && (x0 - TB <= 0 || x0 - TB + C - 1 >= nx - 1);
   const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
@@ -393,23 +397,40 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
 #pragma unroll
       for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
     }
+  // Level 0 also keeps, for rows r and r+1, the +x population of the left
+  // neighbour and the -x population of the right one (what level 1 pulls), and
+  // its own +x/-x (what the face rule at an x wall reads).
+  T nbc[2][M], nbn[2][M], ownc[2][M], ownn[2][M];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int i = 0; i < M; ++i) nbc[d][i] = nbn[d][i] = ownc[d][i] = ownn[d][i] = T(0);
 
   // Start of plane pl of a buffer (uniform).  The empty asm keeps it an opaque
   // scalar, so that every access is that scalar base plus the lane's 32-bit
   // offset rather than 64-bit address arithmetic per lane and plane.
   auto plane_at = [&](const T* base, int pl) { return scalar_base(base + (int64_t)pl * p.plane); };
 
-  T ld_row[P];
+  T ld_row[P], ld_nb[2][M];
   auto load_row = [&](int r) {
     const bool r_in = r >= 0 && r < ny;
     const int rl = r_in ? r : (((r % ny) + ny) % ny);
     if (col_ok && (r_in || py)) {
-      const uint32_t off = ((uint32_t)rl * (uint32_t)nx + xl) * (uint32_t)sizeof(T);
+      const uint32_t row = (uint32_t)rl * (uint32_t)nx;
+      const uint32_t off = (row + xl) * (uint32_t)sizeof(T);
+      const uint32_t offm = (row + xlm) * (uint32_t)sizeof(T), offp = (row + xlp) * (uint32_t)sizeof(T);
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) ld_row[pl] = gload<T>(plane_at(src, pl), off, nt_ld);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        ld_nb[0][i] = gload<T>(plane_at(src, i * Q + KXP), offm, nt_ld);
+        ld_nb[1][i] = gload<T>(plane_at(src, i * Q + KXM), offp, nt_ld);
+      }
     } else {
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) ld_nb[0][i] = ld_nb[1][i] = T(0);
     }
   };
   // Advance level l's window by one row; a computed row r also enters it (and LDS).
@@ -425,8 +446,10 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     const int s = r & 1;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      xs[l][s][0][i][c] = f[i][KXP];
-      xs[l][s][1][i][c] = f[i][KXM];
+      if (l > 0) {
+        xs[l - 1][s][0][i][c] = f[i][KXP];
+        xs[l - 1][s][1][i][c] = f[i][KXM];
+      }
       nxt[l][0][i] = f[i][0];
       nxt[l][1][i] = f[i][KYP];
       nxt[l][2][i] = f[i][KYM];
@@ -450,6 +473,17 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
         for (int k = 0; k < Q; ++k) f[i][k] = ld_row[i * Q + k];
       advance(0);
       enter(0, r_in, f);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          nbc[d][i] = nbn[d][i];
+          nbn[d][i] = ld_nb[d][i];
+          ownc[d][i] = ownn[d][i];
+        }
+        ownn[0][i] = f[i][KXP];
+        ownn[1][i] = f[i][KXM];
+      }
     }
     if (r_in < r_last) load_row(r_in + 1);
 #pragma unroll
@@ -464,8 +498,8 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         f[i][0] = cur[lp][0][i];
-        f[i][KXP] = xs[lp][s][0][i][cm];
-        f[i][KXM] = xs[lp][s][1][i][cp];
+        f[i][KXP] = lp == 0 ? nbc[0][i] : xs[lp > 0 ? lp - 1 : 0][s][0][i][cm];
+        f[i][KXM] = lp == 0 ? nbc[1][i] : xs[lp > 0 ? lp - 1 : 0][s][1][i][cp];
         f[i][KYP] = yprev[lp][i];
         f[i][KYM] = nxt[lp][2][i];
       }
@@ -473,8 +507,10 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
         if (tile_xwall) {
 #pragma unroll
           for (int i = 0; i < M; ++i) {
-            if (wall_xlo) f[i][KXP] = face(0, KXM, i, xs[lp][s][1][i][c]);
-            if (wall_xhi) f[i][KXM] = face(1, KXP, i, xs[lp][s][0][i][c]);
+            const T own_xm = lp == 0 ? ownc[1][i] : xs[lp > 0 ? lp - 1 : 0][s][1][i][c];
+            const T own_xp = lp == 0 ? ownc[0][i] : xs[lp > 0 ? lp - 1 : 0][s][0][i][c];
+            if (wall_xlo) f[i][KXP] = face(0, KXM, i, own_xm);
+            if (wall_xhi) f[i][KXM] = face(1, KXP, i, own_xp);
           }
         }
         if (!py && r == 0) {
@@ -1332,6 +1368,8 @@ hipError_t launch_batch_blocked(const LaunchArgs& a) {
   if (a.tb == 2) return launch_batch_blocked_tb<M, T, 2>(a);
   if (a.tb == 3) return launch_batch_blocked_tb<M, T, 3>(a);
   if (a.tb == 4) return launch_batch_blocked_tb<M, T, 4>(a);
+  if (a.tb == 5) return launch_batch_blocked_tb<M, T, 5>(a);
+  if (a.tb == 6) return launch_batch_blocked_tb<M, T, 6>(a);
   return hipErrorInvalidValue;
 }
 
@@ -1340,6 +1378,8 @@ hipError_t launch_blocked(const LaunchArgs& a) {
   if (a.tb == 2) return launch_blocked_tb<M, T, 2>(a);
   if (a.tb == 3) return launch_blocked_tb<M, T, 3>(a);
   if (a.tb == 4) return launch_blocked_tb<M, T, 4>(a);
+  if (a.tb == 5) return launch_blocked_tb<M, T, 5>(a);
+  if (a.tb == 6) return launch_blocked_tb<M, T, 6>(a);
   return hipErrorInvalidValue;
 }
 
@@ -1469,6 +1509,8 @@ hipError_t run(Op op, const LaunchArgs& a) {
         if (a.tb == 2) e = blocked_resident<M, T, 2>(a, a.out_int);
         if (a.tb == 3) e = blocked_resident<M, T, 3>(a, a.out_int);
         if (a.tb == 4) e = blocked_resident<M, T, 4>(a, a.out_int);
+        if (a.tb == 5) e = blocked_resident<M, T, 5>(a, a.out_int);
+        if (a.tb == 6) e = blocked_resident<M, T, 6>(a, a.out_int);
         return e;
       } else {
         return hipErrorInvalidValue;

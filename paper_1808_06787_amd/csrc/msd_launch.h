@@ -93,13 +93,15 @@ struct LaunchArgs {
 // Temporally blocked D2Q5 sweep (k_step_blocked): workgroup width in columns
 // for m evolved species, tb steps per pass and value size `bytes`, or 0 when
 // the per-thread register window (7m values per time level plus one input row
-// of 5m) would take more than 90 VGPRs, so that the kernel keeps several waves
-// per SIMD without spilling.  The LDS exchange of the x-directions takes
-// tb * 2 rows * 2 directions * m * cols values.
+// of 5m) would take more than 100 VGPRs, so that the kernel keeps four or more
+// waves per SIMD without spilling (m <= 4: beyond that the collision alone
+// leaves too few waves).  The LDS exchange of the x-directions takes
+// (tb - 1) levels * 2 rows * 2 directions * m * cols values.
 constexpr int kBlockedCols = 256;
+constexpr int kMaxStepsPerPass = 6;
 constexpr int blocked_cols(int m, int tb, int bytes) {
-  return (tb >= 2 && tb <= 4 && (7 * m * tb + 5 * m) * bytes / 4 <= 90 &&
-          tb * 2 * 2 * m * kBlockedCols * bytes <= 64 * 1024)
+  return (m <= 4 && tb >= 2 && tb <= kMaxStepsPerPass && (7 * m * tb + 5 * m) * bytes / 4 <= 100 &&
+          (tb - 1) * 2 * 2 * m * kBlockedCols * bytes <= 64 * 1024)
              ? kBlockedCols
              : 0;
 }

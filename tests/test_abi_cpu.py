@@ -167,17 +167,17 @@ def test_blocked_plan_limits_without_device():
         return np.triu(m, 1) + np.triu(m, 1).T + np.eye(n)
 
     cases = [
-        ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 4),
+        ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f32", (32768, 32768), dict(seg_rows=16), 1),
-        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 3),
+        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 4),
         ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 2),
         ("D2Q5", 6, "f32", (4096, 1024), dict(seg_rows=16), 1),
-        ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 4),
+        ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16), 2),
         ("D2Q5", 4, "f64", (4096, 1024), dict(seg_rows=16), 1),
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=3), 3),
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=0), 1),
-        ("D2Q5", 3, "f32", (5, 3), dict(seg_rows=16), 4),
+        ("D2Q5", 3, "f32", (5, 3), dict(seg_rows=16), 6),
         ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
         ("D1Q3", 3, "f64", (256,), dict(seg_rows=16), 1),
     ]

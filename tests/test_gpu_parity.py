@@ -242,7 +242,7 @@ BLOCKED_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
-@pytest.mark.parametrize("tb", [2, 3, 4])
+@pytest.mark.parametrize("tb", [2, 3, 4, 6])
 @pytest.mark.parametrize("N", [2, 3, 5])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_temporally_blocked_sweep(case, tb, N, precision):
@@ -272,7 +272,7 @@ def test_blocked_sweep_matches_single_step_sweep():
     shape = (500, 97)
     xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
     ref = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(lds_resident=0, temporal=0))
-    for tb in (2, 3, 4):
+    for tb in (2, 3, 4, 5, 6):
         got = gpu_run("D2Q5", D, shape, "f32", xi0, 41, launch=dict(temporal=tb, seg_rows=16, lds_resident=0))
         for a, b in zip(ref, got):
             np.testing.assert_allclose(a, b, rtol=0, atol=2e-6)
@@ -287,10 +287,10 @@ def test_steps_per_pass_plan():
 
     rng = np.random.default_rng(320)
     cases = [  # (N, precision, shape, launch, expected steps per pass)
-        (3, "f32", (4096, 512), {}, 4),
+        (3, "f32", (4096, 512), {}, 6),
         (3, "f32", (4096, 4096), dict(temporal=4, seg_rows=0), 4),
-        (2, "f64", (2048, 512), {}, 4),
-        (4, "f32", (2048, 1024), {}, 3),
+        (2, "f64", (2048, 512), {}, 6),
+        (4, "f32", (2048, 1024), {}, 4),
         (5, "f32", (2048, 1024), {}, 2),
         (3, "f64", (2048, 1024), {}, 2),
         (4, "f64", (2048, 1024), {}, 1),
@@ -298,8 +298,8 @@ def test_steps_per_pass_plan():
         (3, "f32", (2048, 1024), dict(temporal=0), 1),
         (3, "f32", (200, 100), {}, 1),
         (3, "f32", (512, 512), {}, 1),
-        (3, "f32", (1024, 1024), {}, 4),
-        (3, "f32", (200, 100), dict(seg_rows=8), 4),
+        (3, "f32", (1024, 1024), {}, 6),
+        (3, "f32", (200, 100), dict(seg_rows=8), 6),
     ]
     for N, prec, shape, launch, want in cases:
         sim = Sim("D2Q5", rand_D(rng, N), shape, prec)
