@@ -310,6 +310,12 @@ __device__ __forceinline__ uint64_t scalar_base(const void* p) {
   asm volatile("" : "+s"(a));
   return a;
 }
+// A uniform 64-bit value the compiler must re-read where it is used (so that
+// products with it are not hoisted and kept live across a loop).
+__device__ __forceinline__ uint64_t opaque_u64(uint64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
 template <typename T>
 __device__ __forceinline__ T gload(uint64_t base, uint32_t off, bool nt) {
   const auto* q = reinterpret_cast<const __attribute__((address_space(1))) T*>(
@@ -406,10 +412,11 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
 #pragma unroll
     for (int i = 0; i < M; ++i) nbc[d][i] = nbn[d][i] = ownc[d][i] = ownn[d][i] = T(0);
 
-  // Start of plane pl of a buffer (uniform).  The empty asm keeps it an opaque
-  // scalar, so that every access is that scalar base plus the lane's 32-bit
-  // offset rather than 64-bit address arithmetic per lane and plane.
-  auto plane_at = [&](const T* base, int pl) { return scalar_base(base + (int64_t)pl * p.plane); };
+  // Planes are walked from an opaque scalar base (scalar_base) in steps of the
+  // plane stride: every access is that scalar base plus the lane's 32-bit
+  // offset, and no per-plane base is hoisted out of the row loop (which would
+  // hold one SGPR pair per plane and level for the whole kernel).
+  const uint64_t pstride = (uint64_t)p.plane * sizeof(T);
 
   T ld_row[P], ld_nb[2][M];
   auto load_row = [&](int r) {
@@ -419,12 +426,13 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       const uint32_t row = (uint32_t)rl * (uint32_t)nx;
       const uint32_t off = (row + xl) * (uint32_t)sizeof(T);
       const uint32_t offm = (row + xlm) * (uint32_t)sizeof(T), offp = (row + xlp) * (uint32_t)sizeof(T);
+      uint64_t b = scalar_base(src);
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) ld_row[pl] = gload<T>(plane_at(src, pl), off, nt_ld);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        ld_nb[0][i] = gload<T>(plane_at(src, i * Q + KXP), offm, nt_ld);
-        ld_nb[1][i] = gload<T>(plane_at(src, i * Q + KXM), offp, nt_ld);
+      for (int pl = 0; pl < P; ++pl, b += pstride) {
+        ld_row[pl] = gload<T>(b, off, nt_ld);
+        // the left neighbour's +x and the right neighbour's -x of the same plane
+        if (pl % Q == KXP) ld_nb[0][pl / Q] = gload<T>(b, offm, nt_ld);
+        if (pl % Q == KXM) ld_nb[1][pl / Q] = gload<T>(b, offp, nt_ld);
       }
     } else {
 #pragma unroll
@@ -528,12 +536,12 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       // also stores every intermediate level, level l at dst + (l - 1) rec_stride
       if ((lvl == TB || rec_stride > 0) && c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
         const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
-        T* out = dst + (rec_stride > 0 ? (int64_t)(lvl - 1) * rec_stride : 0);
+        uint64_t b = scalar_base(dst);
+        if (rec_stride > 0) b += (uint64_t)(lvl - 1) * (uint64_t)rec_stride * sizeof(T);
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-          for (int k = 0; k < Q; ++k)
-            gstore<T>(plane_at(out, i * Q + k), off, f[i][k], nt_st);
+          for (int k = 0; k < Q; ++k, b += pstride) gstore<T>(b, off, f[i][k], nt_st);
       }
     }
   }
@@ -1038,9 +1046,10 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
       for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
     }
   // value of plane pl at (row, col): an opaque scalar plane start plus a 32-bit lane offset
+  const uint64_t pstride = (uint64_t)p.plane * sizeof(T);
   auto at = [&](const T* base, int pl, int row, int col) {
     const uint32_t off = ((uint32_t)row * (uint32_t)nx + (uint32_t)col) * (uint32_t)sizeof(T);
-    return gload<T>(scalar_base(base + (int64_t)pl * p.plane), off, false);
+    return gload<T>(scalar_base(base) + (uint64_t)pl * opaque_u64(pstride), off, false);
   };
   T ld_row[P];
   auto load_row = [&](int r) {
@@ -1176,7 +1185,7 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
         for (int i = 0; i < M; ++i)
 #pragma unroll
           for (int k = 0; k < Q; ++k)
-            gstore<T>(scalar_base(adj_out + (int64_t)(i * Q + k) * p.plane), off, g[i][k], 0);
+            gstore<T>(scalar_base(adj_out) + (uint64_t)(i * Q + k) * opaque_u64(pstride), off, g[i][k], 0);
       }
     }
   }
