@@ -43,8 +43,9 @@ extern "C" {
 #define MSD_ABI_VERSION 1
 #define MSD_MAX_SPECIES 8
 
-/* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10). */
-enum msd_lattice { MSD_D1Q3 = 1, MSD_D2Q5 = 2, MSD_D3Q7 = 3 };
+/* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10),
+ * and the lattices without a rest direction, Eqs. (3-4), (3-6), (3-9). */
+enum msd_lattice { MSD_D1Q3 = 1, MSD_D2Q5 = 2, MSD_D3Q7 = 3, MSD_D1Q2 = 4, MSD_D2Q4 = 5, MSD_D3Q6 = 6 };
 
 /* Storage and arithmetic precision of the sweep (bytes per value). */
 enum msd_precision { MSD_F32 = 4, MSD_F64 = 8 };

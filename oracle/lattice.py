@@ -2,15 +2,18 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Velocity sets and weights follow Sec. 3.1, Eqs. (3-5) (D1Q3), (3-7) (D2Q5) and
-(3-10) (D3Q7), in the paper's direction order.  Velocities are in lattice units
+Velocity sets and weights follow Sec. 3.1, Eqs. (3-4) (D1Q2), (3-5) (D1Q3),
+(3-6) (D2Q4), (3-7) (D2Q5), (3-9) (D3Q6) and (3-10) (D3Q7), in the paper's
+direction order.  Velocities are in lattice units
 (c = dx/dt = 1; the scale invariance M0^-1 Lambda M0 = M^-1 Lambda M after
 Eq. (3-14) makes the C_d factor irrelevant).
 
-The moment matrix M0 is given by the paper only for D2Q5 (Eq. (3-14)).  For
-D1Q3 and D3Q7 we use matrices built the same way: row 0 is the conserved zeroth
-moment, then one row per first-order moment (the velocity components), then
-second-order rows.  Every row is either even or odd under k -> opposite(k).
+The moment matrix M0 is given by the paper only for D2Q5 (Eq. (3-14)).  For the
+other lattices we use matrices built the same way: row 0 is the conserved
+zeroth moment, then one row per first-order moment (the velocity components),
+then second-order rows.  Every row is either even or odd under k -> opposite(k).
+The lattices without a rest direction (D1Q2, D2Q4, D3Q6) have q = 2d: D1Q2 has
+no second-order row, D2Q4 one (c_x^2 - c_y^2), D3Q6 two.
 """
 from __future__ import annotations
 
@@ -49,7 +52,7 @@ class Lattice:
         The Chapman-Enskog analysis of Sec. 3.2 is carried out on D2Q5, where the
         second moment of the weights is c^2/3 (Eqs. (3-22), (3-26), (3-27)).  On a
         general lattice the same derivation produces sum_k w_k c_kx^2 in that
-        place: 1/3 on D1Q3 and D2Q5, 1/4 on D3Q7.
+        place: 1/3 on D1Q3, D2Q5 and D3Q6, 1/4 on D3Q7, 1/2 on D2Q4, 1 on D1Q2.
         """
         return float(np.sum(self.w * self.c[:, 0] ** 2))
 
@@ -116,7 +119,58 @@ D3Q7 = Lattice(
     row_order=(0, 1, 1, 1, 2, 2, 2),
 )
 
-LATTICES = {"D1Q3": D1Q3, "D2Q5": D2Q5, "D3Q7": D3Q7}
+# Eq. (3-4): D1Q2, w = (1/2, 1/2), c = (1, -1).
+D1Q2 = Lattice(
+    name="D1Q2",
+    d=1,
+    c=_vel([(1,), (-1,)]),
+    w=np.array([0.5, 0.5]),
+    M0=np.array(
+        [
+            [1.0, 1.0],     # zeroth moment
+            [1.0, -1.0],    # c_x
+        ]
+    ),
+    row_order=(0, 1),
+)
+
+# Eq. (3-6): D2Q4, w = 1/4; directions (1,0), (0,1), (-1,0), (0,-1).
+D2Q4 = Lattice(
+    name="D2Q4",
+    d=2,
+    c=_vel([(1, 0), (0, 1), (-1, 0), (0, -1)]),
+    w=np.array([0.25] * 4),
+    M0=np.array(
+        [
+            [1.0, 1.0, 1.0, 1.0],
+            [1.0, 0.0, -1.0, 0.0],
+            [0.0, 1.0, 0.0, -1.0],
+            [1.0, -1.0, 1.0, -1.0],    # c_x^2 - c_y^2
+        ]
+    ),
+    row_order=(0, 1, 1, 2),
+)
+
+# Eq. (3-9): D3Q6, w = 1/6; directions +x, -x, +y, -y, +z, -z.
+D3Q6 = Lattice(
+    name="D3Q6",
+    d=3,
+    c=_vel([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]),
+    w=np.array([1.0 / 6.0] * 6),
+    M0=np.array(
+        [
+            [1.0, 1.0, 1.0, 1.0, 1.0, 1.0],
+            [1.0, -1.0, 0.0, 0.0, 0.0, 0.0],
+            [0.0, 0.0, 1.0, -1.0, 0.0, 0.0],
+            [0.0, 0.0, 0.0, 0.0, 1.0, -1.0],
+            [2.0, 2.0, -1.0, -1.0, -1.0, -1.0],   # 2 c_x^2 - c_y^2 - c_z^2
+            [0.0, 0.0, 1.0, 1.0, -1.0, -1.0],     # c_y^2 - c_z^2
+        ]
+    ),
+    row_order=(0, 1, 1, 1, 2, 2),
+)
+
+LATTICES = {"D1Q2": D1Q2, "D1Q3": D1Q3, "D2Q4": D2Q4, "D2Q5": D2Q5, "D3Q6": D3Q6, "D3Q7": D3Q7}
 
 
 def get(name: str) -> Lattice:

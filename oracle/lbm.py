@@ -39,7 +39,7 @@ DIRICHLET = "dirichlet"     # half-way anti-bounce-back (Sec. 4)
 class Problem:
     """One mixture on one lattice, in lattice units (dx = dt = 1).
 
-    lattice : "D1Q3" | "D2Q5" | "D3Q7"
+    lattice : "D1Q2" | "D1Q3" | "D2Q4" | "D2Q5" | "D3Q6" | "D3Q7"
     D       : (N, N) symmetric Maxwell-Stefan diffusivities in lattice units
     shape   : (nx,), (nx, ny) or (nx, ny, nz)
     bc      : per axis a pair (low face, high face) of PERIODIC / ZERO_FLUX /
@@ -198,7 +198,7 @@ def stream(prob: Problem, fpost: np.ndarray) -> np.ndarray:
         if not axes:
             out[:, k] = fpost[:, k]
             continue
-        (a,) = axes   # D1Q3, D2Q5 and D3Q7 directions move along one axis only
+        (a,) = axes   # every direction of these lattices moves along one axis only
         ax = 1 + _array_axis(prob, a)   # axis in (m, *nodes) arrays
         out[:, k] = np.roll(fpost[:, k], shift=int(ck[a]), axis=ax)
         side = 0 if ck[a] > 0 else 1        # face whose boundary nodes miss their source

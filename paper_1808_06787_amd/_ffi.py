@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libmsd.so")
 ABI_VERSION = 1
 MAX_SPECIES = 8
 
-D1Q3, D2Q5, D3Q7 = 1, 2, 3
+D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6 = 1, 2, 3, 4, 5, 6
 F32, F64 = 4, 8
 RELAX_PAPER, RELAX_SRT = 0, 1
 BC_PERIODIC, BC_ZERO_FLUX, BC_DIRICHLET = 0, 1, 2

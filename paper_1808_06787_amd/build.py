@@ -24,6 +24,9 @@ SOURCES = [
     "msd_lat_d1q3.hip",
     "msd_lat_d2q5.hip",
     "msd_lat_d3q7.hip",
+    "msd_lat_d1q2.hip",
+    "msd_lat_d2q4.hip",
+    "msd_lat_d3q6.hip",
 ]
 ARCH = "gfx950"
 

@@ -86,7 +86,7 @@ void cache_store(const char* path, const std::string& key, int k, const int64_t*
 int validate(const msd_problem* p) {
   if (!p) return fail(MSD_EINVAL, "problem is NULL");
   if (p->abi != MSD_ABI_VERSION) return fail(MSD_EABI, "problem.abi = %d, library ABI = %d", p->abi, MSD_ABI_VERSION);
-  if (p->lattice != MSD_D1Q3 && p->lattice != MSD_D2Q5 && p->lattice != MSD_D3Q7)
+  if (p->lattice < MSD_D1Q3 || p->lattice > MSD_D3Q6)
     return fail(MSD_EINVAL, "unknown lattice %d", p->lattice);
   if (p->n_species < 2 || p->n_species > MSD_MAX_SPECIES)
     return fail(MSD_EINVAL, "n_species = %d outside [2, %d]", p->n_species, MSD_MAX_SPECIES);
@@ -173,6 +173,9 @@ hipError_t dispatch(Op op, const LaunchArgs& a) {
     case MSD_D1Q3: return msd::dispatch<1>(op, a);
     case MSD_D2Q5: return msd::dispatch<2>(op, a);
     case MSD_D3Q7: return msd::dispatch<3>(op, a);
+    case MSD_D1Q2: return msd::dispatch<4>(op, a);
+    case MSD_D2Q4: return msd::dispatch<5>(op, a);
+    case MSD_D3Q6: return msd::dispatch<6>(op, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -214,7 +217,7 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   std::memset(l, 0, sizeof(*l));
   l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
   l->block_y = std::max(1, (int)std::min<int64_t>(256 / l->block_x, p->ny));
-  l->xcd_remap = p->lattice == MSD_D3Q7 ? 1 : 0;
+  l->xcd_remap = (p->lattice == MSD_D3Q7 || p->lattice == MSD_D3Q6) ? 1 : 0;
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;

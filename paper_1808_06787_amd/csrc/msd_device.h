@@ -68,6 +68,39 @@ template <> struct Lattice<3> {
   static constexpr double cs2 = 0.25;
 };
 
+// Lattices without a rest direction (q = 2d, equal weights 1/(2d)); their
+// second moments sum_k w_k c_kx^2 are 1 (D1Q2), 1/2 (D2Q4) and 1/3 (D3Q6).
+// Lattice ids 4, 5, 6 follow the ABI's enum.
+// Eq. (3-4): c = (1, -1), w = 1/2.
+template <> struct Lattice<4> {
+  static constexpr int D = 1, Q = 2;
+  __host__ __device__ static constexpr int axis(int) { return 0; }
+  __host__ __device__ static constexpr int sgn(int k) { return k == 0 ? 1 : -1; }
+  __host__ __device__ static constexpr int opp(int k) { return 1 - k; }
+  __host__ __device__ static constexpr double w(int) { return 0.5; }
+  static constexpr double cs2 = 1.0;
+};
+
+// Eq. (3-6): directions (1,0), (0,1), (-1,0), (0,-1); w = 1/4.
+template <> struct Lattice<5> {
+  static constexpr int D = 2, Q = 4;
+  __host__ __device__ static constexpr int axis(int k) { return k & 1; }
+  __host__ __device__ static constexpr int sgn(int k) { return k < 2 ? 1 : -1; }
+  __host__ __device__ static constexpr int opp(int k) { return (k + 2) & 3; }
+  __host__ __device__ static constexpr double w(int) { return 0.25; }
+  static constexpr double cs2 = 0.5;
+};
+
+// Eq. (3-9): directions +x, -x, +y, -y, +z, -z; w = 1/6.
+template <> struct Lattice<6> {
+  static constexpr int D = 3, Q = 6;
+  __host__ __device__ static constexpr int axis(int k) { return k >> 1; }
+  __host__ __device__ static constexpr int sgn(int k) { return (k & 1) ? -1 : 1; }
+  __host__ __device__ static constexpr int opp(int k) { return k ^ 1; }
+  __host__ __device__ static constexpr double w(int) { return 1.0 / 6.0; }
+  static constexpr double cs2 = 1.0 / 3.0;
+};
+
 // ---------------------------------------------------------------------------
 // Kernel parameters (passed by value in the kernel argument segment).
 // Host arrays of the problem are copied in verbatim; every derived quantity
@@ -465,8 +498,9 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
 #pragma unroll
     for (int j = 0; j < M; ++j) L1[i][j] = (i == j ? T(2) : T(0)) - T(2) * K[i][j];
     const T l = L1[i][i];
-    delta[i] = srt ? T(0) : (T(8) * (l - T(2)) / (l - T(8)) - l);
-    dphi[i] = srt ? T(0) : (T(-48) / ((l - T(8)) * (l - T(8))) - T(1));   // d delta / d lambda
+    const T r8 = recip(l - T(8));
+    delta[i] = srt ? T(0) : (T(8) * (l - T(2)) * r8 - l);
+    dphi[i] = srt ? T(0) : (T(-48) * r8 * r8 - T(1));   // d delta / d lambda
   }
   T neq[M][Q], ev[M][Q];
 #pragma unroll

@@ -345,9 +345,10 @@ __device__ __forceinline__ void gstore(uint64_t base, uint32_t off, T v, int nt)
 // Pull propagation takes the y-directions from the same column, so each level
 // keeps them in registers: the +y population of row r - 1, and the rest, +y
 // and -y populations of rows r and r + 1.  Only the two x-directions cross
-// columns; they go through LDS, two rows per level (ping-pong by row parity),
-// so one barrier per input row orders every LDS write after the reads of the
-// previous occupant of its slot.  Level l is valid on columns [l, C - l) and
+// columns: level 0 (the input) loads its neighbours' values from memory, and
+// levels 1 .. TB-1 pass theirs through LDS, two rows per level (ping-pong by
+// row parity), so one barrier per input row orders every LDS write after the
+// reads of the previous occupant of its slot.  Level l is valid on columns [l, C - l) and
 // rows [y0 - TB + l, y1 - 1 + TB - l]: a row outside that range (a uniform
 // condition) is skipped but still advances the register window; invalid
 // columns compute values that no valid node reads.  Nodes beyond a wall are
@@ -666,7 +667,8 @@ __global__ __launch_bounds__(256) void k_read(Problem p, const T* __restrict__ s
 #pragma unroll
     for (int d = 0; d < DD; ++d) m1[i][d] = T(0);
 #pragma unroll
-    for (int k = 1; k < Q; ++k) m1[i][L::axis(k)] += (L::sgn(k) > 0) ? f[i][k] : -f[i][k];
+    for (int k = 0; k < Q; ++k)
+      if (L::axis(k) >= 0) m1[i][L::axis(k) >= 0 ? L::axis(k) : 0] += (L::sgn(k) > 0) ? f[i][k] : -f[i][k];
   }
 #pragma unroll
   for (int i = 0; i < M; ++i) oxi[(int64_t)i * nodes + n.idx] = TO(xi[i]);

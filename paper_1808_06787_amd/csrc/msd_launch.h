@@ -132,5 +132,8 @@ hipError_t dispatch(Op op, const LaunchArgs& a);
 extern template hipError_t dispatch<1>(Op, const LaunchArgs&);
 extern template hipError_t dispatch<2>(Op, const LaunchArgs&);
 extern template hipError_t dispatch<3>(Op, const LaunchArgs&);
+extern template hipError_t dispatch<4>(Op, const LaunchArgs&);
+extern template hipError_t dispatch<5>(Op, const LaunchArgs&);
+extern template hipError_t dispatch<6>(Op, const LaunchArgs&);
 
 }  // namespace msd

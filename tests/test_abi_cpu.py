@@ -60,6 +60,13 @@ def test_workspace_size_model():
     plane = (100 * 37 + 63) // 64 * 64
     # two halves of m*q planes plus < 1 MiB of constants and reduction scratch
     assert 2 * 2 * 5 * plane * 4 <= n < 2 * 2 * 5 * plane * 4 + (1 << 20)
+    # lattices without a rest direction: q = 2d
+    for lattice, shape, q in (("D1Q2", (300,), 2), ("D2Q4", (100, 37), 4), ("D3Q6", (20, 9, 7), 6)):
+        p, keep = make_problem(lattice, D, shape, "f64")
+        n, st = _ws(p)
+        assert st == 0
+        plane = (int(np.prod(shape)) + 63) // 64 * 64
+        assert 2 * 2 * q * plane * 8 <= n < 2 * 2 * q * plane * 8 + (1 << 20), lattice
 
 
 @pytest.mark.parametrize(

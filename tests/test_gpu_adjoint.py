@@ -43,6 +43,9 @@ CASES = [
     ("D2Q5", (17, 6), 4, (("periodic", "periodic"), ("zero_flux", "zero_flux"))),
     ("D1Q3", (23,), 4, (("zero_flux", "dirichlet"),)),
     ("D3Q7", (6, 5, 4), 3, (("zero_flux", "zero_flux"), ("periodic", "periodic"), ("dirichlet", "dirichlet"))),
+    ("D1Q2", (19,), 3, (("dirichlet", "zero_flux"),)),
+    ("D2Q4", (11, 8), 4, (("zero_flux", "dirichlet"), ("periodic", "periodic"))),
+    ("D3Q6", (5, 6, 4), 3, (("periodic", "periodic"), ("zero_flux", "dirichlet"), ("zero_flux", "zero_flux"))),
 ]
 
 

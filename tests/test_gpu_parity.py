@@ -13,8 +13,10 @@ from gpu_cases import (assert_parity, gpu_run, oracle_problem, oracle_run, rand_
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"D1Q3": (301,), "D2Q5": (97, 45), "D3Q7": (37, 19, 11)}
-WALLS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3}
+SHAPES = {"D1Q3": (301,), "D2Q5": (97, 45), "D3Q7": (37, 19, 11),
+          "D1Q2": (301,), "D2Q4": (97, 45), "D3Q6": (37, 19, 11)}
+WALLS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3}
+ALL = ["D1Q3", "D2Q5", "D3Q7", "D1Q2", "D2Q4", "D3Q6"]
 
 
 def _bc(lattice, kinds):
@@ -22,7 +24,7 @@ def _bc(lattice, kinds):
     return tuple(kinds[a % len(kinds)] for a in range(d))
 
 
-@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("lattice", ALL)
 @pytest.mark.parametrize("N", [2, 3, 4, 5])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_periodic_and_zero_flux(lattice, N, precision):
@@ -38,7 +40,7 @@ def test_periodic_and_zero_flux(lattice, N, precision):
     print(f"{lattice} N={N} {precision}: max |dxi| = {err:.3e}")
 
 
-@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("lattice", ALL)
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("relax", ["paper", "srt"])
 def test_dirichlet_faces(lattice, precision, relax):
@@ -70,7 +72,7 @@ def test_many_species(N, precision):
     assert_parity(gpu, orc, precision, f"N={N} {precision}")
 
 
-@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("lattice", ALL)
 @pytest.mark.parametrize("relax", ["paper", "srt"])
 def test_linearised_mode(lattice, relax):
     rng = np.random.default_rng(31)
@@ -144,9 +146,10 @@ def test_ternary_1d_workload_full_length():
     assert_parity(gpu, orc, "f64", w.name)
 
 
+@pytest.mark.parametrize("rest", [True, False])
 @pytest.mark.parametrize("shape", [(1,), (2,), (1, 1), (1, 5), (3, 1, 2)])
-def test_degenerate_extents(shape):
-    lattice = {1: "D1Q3", 2: "D2Q5", 3: "D3Q7"}[len(shape)]
+def test_degenerate_extents(shape, rest):
+    lattice = ({1: "D1Q3", 2: "D2Q5", 3: "D3Q7"} if rest else {1: "D1Q2", 2: "D2Q4", 3: "D3Q6"})[len(shape)]
     rng = np.random.default_rng(8)
     D = rand_D(rng, 3)
     xi0 = rand_field(rng, 3, shape[::-1])
@@ -166,10 +169,11 @@ def test_zero_steps_reads_initial_state():
     np.testing.assert_allclose(gpu[0], xi0, rtol=0, atol=1e-15)
 
 
-VEC_SHAPES = {"D1Q3": (1028,), "D2Q5": (1028, 13), "D3Q7": (68, 9, 5)}
+VEC_SHAPES = {"D1Q3": (1028,), "D2Q5": (1028, 13), "D3Q7": (68, 9, 5),
+              "D1Q2": (1028,), "D2Q4": (1028, 13), "D3Q6": (68, 9, 5)}
 
 
-@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("lattice", ALL)
 @pytest.mark.parametrize("vec", [0, 1, 2, 4])
 @pytest.mark.parametrize("xface", ["periodic", "zero_flux", "dirichlet"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])

@@ -145,7 +145,7 @@ def test_lambda1_roundtrip_eq_3_26():
     """Eq. (3-26) as printed maps the oracle's Lambda_1 back to D~ (self-consistency only;
     the physics of the map is pinned by the continuum-decay tests)."""
     rng = np.random.default_rng(15)
-    for name in ("D1Q3", "D2Q5", "D3Q7"):
+    for name in ("D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"):
         cs2 = lat.get(name).cs2
         D = _rand_D(rng, 4, 0.02, 0.3)
         Dt = ms.fick_matrix(ms.ms_B(_rand_xi(rng, 4, 30), D))
@@ -168,7 +168,8 @@ def test_lambda2_rule_eq_3_16():
 def test_lattice_weights_and_sound_speed():
     """Eqs. (3-5), (3-7), (3-10): weights sum to one, velocity sets are symmetric,
     and sum_k w_k c_k c_k = cs2 I with cs2 = 1/3, 1/3, 1/4."""
-    for name, cs2 in (("D1Q3", 1 / 3), ("D2Q5", 1 / 3), ("D3Q7", 1 / 4)):
+    for name, cs2 in (("D1Q2", 1.0), ("D1Q3", 1 / 3), ("D2Q4", 1 / 2), ("D2Q5", 1 / 3), ("D3Q6", 1 / 3),
+                      ("D3Q7", 1 / 4)):
         L = lat.get(name)
         np.testing.assert_allclose(L.w.sum(), 1.0, rtol=1e-15)
         d = L.d
@@ -214,7 +215,7 @@ def test_d2q5_streaming_operator_in_moment_space():
     np.testing.assert_allclose(cy, expect_y, atol=1e-14)
 
 
-@pytest.mark.parametrize("name", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
 def test_moment_rows_have_definite_parity(name):
     """Every M0 row is even or odd under k -> kbar, odd rows are exactly the first-order
     ones, and M0 is invertible (needed for Eq. (3-13b))."""

@@ -201,12 +201,14 @@ def test_loschmidt_tube_extremum_time():
     np.testing.assert_allclose(means[:2], [g["loschmidt_xi1_eq"], g["loschmidt_xi2_eq"]], atol=1e-12)
 
 
-@pytest.mark.parametrize("name", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
 def test_binary_fourier_decay_matches_continuum(name):
     """Eq. (2-13) with constant D (Remark I): a mode cos(k x) decays as exp(-D k^2 t)."""
     L = lat.get(name)
-    n = 64
-    shape = {"D1Q3": (n,), "D2Q5": (n, 2), "D3Q7": (n, 2, 2)}[name]
+    # D1Q2 (c_s^2 = 1) runs this D at lambda_1 = 1.82, where the O(k^2) lattice
+    # correction is about twice that of the other lattices: a longer wave
+    n = 96 if name == "D1Q2" else 64
+    shape = {1: (n,), 2: (n, 2), 3: (n, 2, 2)}[int(name[1])]
     d_lat = 0.05
     p = lbm.Problem(name, np.array([[1, d_lat], [d_lat, 1.0]]), shape)
     k = 2 * np.pi / n
@@ -222,13 +224,13 @@ def test_binary_fourier_decay_matches_continuum(name):
     del L
 
 
-@pytest.mark.parametrize("name", ["D1Q3", "D2Q5", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
 @pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT])
 def test_linearised_multicomponent_decay_matches_eigen_decomposition(name, relax):
     """Linearised Eq. (2-13) (D~ frozen at a reference composition): a mode with
     amplitude vector a0 evolves as a(t) = exp(-k^2 D~ t) a0, coupling included."""
-    n = 48
-    shape = {"D1Q3": (n,), "D2Q5": (n, 2), "D3Q7": (n, 2, 2)}[name]
+    n = 64 if name == "D1Q2" else 48      # D1Q2: larger O(k^2) correction (see above)
+    shape = {1: (n,), 2: (n, 2), 3: (n, 2, 2)}[int(name[1])]
     D = np.array([[1, 0.02, 0.09, 0.05], [0.02, 1, 0.04, 0.08], [0.09, 0.04, 1, 0.03], [0.05, 0.08, 0.03, 1.0]])
     xref = np.array([0.3, 0.2, 0.1, 0.4])
     p = lbm.Problem(name, D, shape, xi_ref=xref, relax=relax)

@@ -16,7 +16,7 @@ import pytest
 from oracle import lbm, ms, naive
 from oracle import lattice as lat
 
-LATS = ["D1Q3", "D2Q5", "D3Q7"]
+LATS = ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"]
 
 
 def _rand_D(rng, n, lo, hi):
@@ -33,7 +33,7 @@ def _rand_field(rng, N, nodes, base_lo=0.2):
 
 
 def _shape(name, sizes):
-    return {"D1Q3": sizes[:1], "D2Q5": sizes[:2], "D3Q7": sizes[:3]}[name]
+    return sizes[: int(name[1])]
 
 
 @pytest.mark.parametrize("name", LATS)

@@ -6,7 +6,7 @@ import torch
 
 from oracle import lbm, ms, twin
 
-LATS = ["D1Q3", "D2Q5", "D3Q7"]
+LATS = ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"]
 
 
 def _rand_D(rng, n, lo=0.03, hi=0.3):
@@ -18,7 +18,7 @@ def _rand_D(rng, n, lo=0.03, hi=0.3):
 
 
 def _problem(name, rng, N, relax=ms.RELAX_PAPER, walls=True, lin=False):
-    shape = {"D1Q3": (7,), "D2Q5": (6, 5), "D3Q7": (4, 3, 3)}[name]
+    shape = {1: (7,), 2: (6, 5), 3: (4, 3, 3)}[int(name[1])]
     d = len(shape)
     bc = [("periodic", "periodic")] * d
     xi_wall = {}
