@@ -130,16 +130,16 @@ __device__ __forceinline__ T recip(T x) {
 }
 
 // ---------------------------------------------------------------------------
-// Small dense inverse of A = I + (a/2) B.  The eigenvalues of B are real and
+// Small dense inverse of A = I + (a/2) B, times `scale`.  The eigenvalues of B are real and
 // positive for compositions on the simplex, so A is never singular; its
 // off-diagonal entries can exceed the diagonal, hence the pivoting for m >= 4.
 // ---------------------------------------------------------------------------
 template <int M, typename T>
-__device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M]) {
+__device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M], T scale = T(1)) {
   if constexpr (M == 1) {
-    K[0][0] = recip(A[0][0]);
+    K[0][0] = scale * recip(A[0][0]);
   } else if constexpr (M == 2) {
-    const T inv = recip(A[0][0] * A[1][1] - A[0][1] * A[1][0]);
+    const T inv = scale * recip(A[0][0] * A[1][1] - A[0][1] * A[1][0]);
     K[0][0] = A[1][1] * inv;
     K[0][1] = -A[0][1] * inv;
     K[1][0] = -A[1][0] * inv;
@@ -148,7 +148,7 @@ __device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M]) {
     const T c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
     const T c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
     const T c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
-    const T inv = recip(A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02);
+    const T inv = scale * recip(A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02);
     K[0][0] = c00 * inv;
     K[1][0] = c01 * inv;
     K[2][0] = c02 * inv;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M]) {
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         W[i][j] = A[i][j];
-        W[i][M + j] = (i == j) ? T(1) : T(0);
+        W[i][M + j] = (i == j) ? scale : T(0);
       }
     }
 #pragma unroll
@@ -223,10 +223,41 @@ __device__ __forceinline__ void ms_inverse(const T (&xb)[M], const T (&R)[M][M +
   invert_small<M, T>(A, K);
 }
 
+// Fused multiply-add in the sweep's precision.
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Per-problem collision coefficients (uniform values, computed once by the
+// setup kernel).  A = I + (a/2) B(xb) of Eq. (2-10) is affine in the
+// composition:
+//   A_ii = a0_i + sum_{k != i} xi_k da_ik,   A_ik = xi_i ea_ik + ga_ik   (k != i)
+// with da_ik = (a/2)(R_ik - R_iN) = -ea_ik, ga_ik = 0, a0_i = 1 + (a/2) R_iN;
+// the linearised mode freezes A at xi_ref (da = ea = 0, a0 and ga hold
+// A(xi_ref)).  rule[] switches the relaxation rule without a branch: with
+// sigma = 1 for Eq. (3-16) and 0 for SRT it holds
+// (4 sigma, sigma/2, -sigma, 1 - sigma/2, sigma - 2) (see collide_node).
+template <int M, typename T>
+struct CollideCoef {
+  T a0[M];
+  T da[M][M];
+  T ea[M][M];
+  T ga[M][M];
+  T rule[5];
+};
+
 // Collision of one node in place: f[i][k] <- f^+ (Eq. (3-13a) + back-transform).
+//
+// With K2 = 2 A^-1, Lambda_1 = 2 (I - K) = 2I - K2.  Eq. (3-16) in terms of
+// kd = K2_ii (lambda_1 = 2 - kd):  lambda_2 = 8 (2 - lambda_1)/(8 - lambda_1)
+// = 8 kd / (6 + kd), so hd = (lambda_2 - lambda_1)/2 = 4 kd/(6 + kd) + kd/2 - 1.
+// The relaxation f^+_k = f_k - G neq_k - hd * neq_kbar with G = Lambda_1 +
+// diag(hd) (the pair form of Lambda_1 odd + Lambda_2 even) runs as a chain of
+// FMAs with nG = -G:  nG_ij = K2_ij (i != j), nG_ii = kd - 2 - hd.
+// Direction 0 takes what the others leave of xi: sum_k f^+_k = xi exactly in
+// real arithmetic (sum_k neq_k = 0 because sum_k w_k = 1), so the species
+// totals change only by unbiased rounding, never by the rounded weights.
 template <int LAT, int M, typename T>
-__device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T (&R)[M][M + 1],
-                                             const T (&xref)[M], bool linearized, bool srt) {
+__device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const CollideCoef<M, T>& cc) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
   T xi[M];
@@ -237,54 +268,49 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const T
     for (int k = 1; k < Q; ++k) s += f[i][k];
     xi[i] = s;
   }
-  T xb[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) xb[i] = linearized ? xref[i] : xi[i];
-  T K[M][M];
-  ms_inverse<M, T>(xb, R, T(0.5 * L::cs2), K);
-
-  // Lambda_1 = 2 (I - K); hd_i = (lambda_2^ii - lambda_1^ii) / 2 (zero in SRT mode),
-  // with lambda_2 from lambda_1 by Eq. (3-16).
-  T L1[M][M], hd[M];
+  T A[M][M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
+    T d = cc.a0[i];
 #pragma unroll
-    for (int j = 0; j < M; ++j) L1[i][j] = (i == j) ? T(2) - T(2) * K[i][j] : T(-2) * K[i][j];
-    const T l1 = L1[i][i];
-    hd[i] = srt ? T(0) : T(0.5) * (T(8) * (l1 - T(2)) * recip(l1 - T(8)) - l1);
+    for (int k = 0; k < M; ++k) {
+      if (k == i) continue;
+      d = mad(xi[k], cc.da[i][k], d);
+      A[i][k] = mad(xi[i], cc.ea[i][k], cc.ga[i][k]);
+    }
+    A[i][i] = d;
+  }
+  T nG[M][M], nhd[M];
+  invert_small<M, T>(A, nG, T(2));
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const T kd = nG[i][i];
+    const T r = recip(kd + T(6));
+    const T t = kd * cc.rule[0];
+    const T hd = mad(t, r, mad(kd, cc.rule[1], cc.rule[2]));
+    nG[i][i] = mad(-t, r, mad(kd, cc.rule[3], cc.rule[4]));
+    nhd[i] = -hd;
   }
 
-  // Non-equilibrium parts f_k - w_k xi.  The rest population's part closes the
-  // sum to zero (exact in real arithmetic since sum_k w_k = 1), so the rounded
-  // weights cannot bias the species totals step after step.
   T neq[M][Q];
 #pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k > 0 || L::opp(k) != 0) neq[i][k] = mad(T(-L::w(k)), xi[i], f[i][k]);
+#pragma unroll
   for (int i = 0; i < M; ++i) {
-    T s;
+    T rest = xi[i];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
-      neq[i][k] = f[i][k] - T(L::w(k)) * xi[i];
-      s = (k == 1) ? neq[i][k] : s + neq[i][k];
+      T acc = f[i][k];
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc = mad(nG[i][j], neq[j][k], acc);
+      acc = mad(nhd[i], neq[i][L::opp(k)], acc);
+      f[i][k] = acc;
+      rest -= acc;
     }
-    neq[i][0] = -s;
-  }
-
-  // f^+_k = f_k - Lambda_1 neq_k - delta * even_k   (Lambda_2 = Lambda_1 + diag(delta)),
-  // even_k = (neq_k + neq_kbar) / 2, so delta * even_k = hd * (neq_k + neq_kbar):
-  // f^+_k = f_k - G neq_k - hd * neq_kbar with G = Lambda_1 + diag(hd) (k = kbar for the rest).
-#pragma unroll
-  for (int i = 0; i < M; ++i) L1[i][i] += hd[i];
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    const int kb = L::opp(k);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      T acc = L1[i][0] * neq[0][k];
-#pragma unroll
-      for (int j = 1; j < M; ++j) acc += L1[i][j] * neq[j][k];
-      acc += hd[i] * neq[i][kb];
-      f[i][k] = f[i][k] - acc;
-    }
+    f[i][0] = rest;
   }
 }
 

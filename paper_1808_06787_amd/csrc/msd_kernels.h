@@ -46,6 +46,7 @@ struct NodeConsts {
   T R[M][M + 1];
   T wall[6][M];
   T xref[M];
+  CollideCoef<M, T> cc;
 };
 
 template <int M, typename T>
@@ -60,20 +61,71 @@ __device__ __forceinline__ void load_consts(const Consts<T>* __restrict__ c, Nod
     for (int i = 0; i < M; ++i) nc.wall[f][i] = c->wall[f][i];
 #pragma unroll
   for (int i = 0; i < M; ++i) nc.xref[i] = c->xref[i];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    nc.cc.a0[i] = c->a0[i];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      if (k == i) continue;
+      nc.cc.da[i][k] = c->da[i][k];
+      nc.cc.ea[i][k] = c->ea[i][k];
+      nc.cc.ga[i][k] = c->ga[i][k];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) nc.cc.rule[j] = c->rule[j];
 }
 
 // ---------------------------------------------------------------------------
-// Setup: reciprocal diffusivities and face data in the sweep's precision.
+// Setup: reciprocal diffusivities, face data and the collision coefficients in
+// the sweep's precision (computed in FP64, rounded once).  With h = cs2/2
+// (a = cs2 dt, dt = 1) and S_ik = R_ik - R_iN, Eq. (2-10) gives
+//   A_ii = 1 + h (R_iN + sum_{k != i} xb_k S_ik),  A_ik = -h xb_i S_ik.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <int LAT, int M, typename T>
 __global__ void k_constants(Problem p, int n_species, Consts<T>* out) {
   const int t = threadIdx.x;
   if (t < kMaxSpecies * kMaxSpecies) {
     const int i = t / kMaxSpecies, j = t % kMaxSpecies;
     out->R[i][j] = (i != j && i < n_species && j < n_species) ? T(1.0 / p.D[i][j]) : T(0);
+    double da = 0.0, ea = 0.0, ga = 0.0;
+    if (i < M && j < M && i != j) {
+      const double h = 0.5 * Lattice<LAT>::cs2;
+      const double S = 1.0 / p.D[i][j] - 1.0 / p.D[i][M];
+      if (p.linearized) {
+        ga = -h * p.xi_ref[i] * S;
+      } else {
+        da = h * S;
+        ea = -h * S;
+      }
+    }
+    out->da[i][j] = T(da);
+    out->ea[i][j] = T(ea);
+    out->ga[i][j] = T(ga);
   }
   if (t < 6 * kMaxSpecies) out->wall[t / kMaxSpecies][t % kMaxSpecies] = T(p.wall[t / kMaxSpecies][t % kMaxSpecies]);
-  if (t < kMaxSpecies) out->xref[t] = T(p.xi_ref[t]);
+  if (t < kMaxSpecies) {
+    out->xref[t] = T(p.xi_ref[t]);
+    double a0 = 1.0;
+    if (t < M) {
+      const double h = 0.5 * Lattice<LAT>::cs2;
+      const double rN = 1.0 / p.D[t][M];
+      double d = rN;
+      if (p.linearized)
+        for (int k = 0; k < M; ++k)
+          if (k != t) d += p.xi_ref[k] * (1.0 / p.D[t][k] - rN);
+      a0 = 1.0 + h * d;
+    }
+    out->a0[t] = T(a0);
+  }
+  if (t == 0) {
+    const double sg = p.relax == 0 ? 1.0 : 0.0;   // Eq. (3-16) or SRT
+    out->rule[0] = T(4.0 * sg);
+    out->rule[1] = T(0.5 * sg);
+    out->rule[2] = T(-sg);
+    out->rule[3] = T(1.0 - 0.5 * sg);
+    out->rule[4] = T(sg - 2.0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -121,7 +173,7 @@ __global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ s
   load_consts<M, T>(cst, nc);
   T f[M][Q];
   gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
-  collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+  collide_node<LAT, M, T>(f, nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -288,7 +340,7 @@ __global__ __launch_bounds__(256) void k_step_vec(Problem p, const T* __restrict
     }
   }
 #pragma unroll
-  for (int j = 0; j < V; ++j) collide_node<LAT, M, T>(f[j], nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+  for (int j = 0; j < V; ++j) collide_node<LAT, M, T>(f[j], nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -390,7 +442,6 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
-  const bool lin = p.linearized != 0, srt = p.relax != 0;
   const bool nt_ld = (nontemporal & NT_LOAD_ALIGNED) != 0;
   const int nt_st = nontemporal & NT_STORE;
 
@@ -531,7 +582,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
           for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, cur[lp][1][i]);
         }
       }
-      collide_node<2, M, T>(f, nc.R, nc.xref, lin, srt);
+      collide_node<2, M, T>(f, nc.cc);
       if (lvl < TB) enter(lvl, r, f);
       // the last level is the pass's output; recording (rec_stride > 0, uniform)
       // also stores every intermediate level, level l at dst + (l - 1) rec_stride
@@ -621,7 +672,7 @@ __global__ __launch_bounds__(256) void k_step_lds(Problem p, const T* __restrict
       n.c[2] = (int32_t)(r / p.ny);
       T f[M][Q];
       gather_node<LAT, M, T>(lp, (const T*)A, n, pull, f, nc.wall);
-      collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+      collide_node<LAT, M, T>(f, nc.cc);
 #pragma unroll
       for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -839,7 +890,7 @@ __device__ __forceinline__ void batch_tile_body(const Problem& p, const T* __res
   load_consts<M, T>(cst, nc);
   T f[M][Q];
   gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
-  collide_node<LAT, M, T>(f, nc.R, nc.xref, p.linearized != 0, p.relax != 0);
+  collide_node<LAT, M, T>(f, nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -1411,7 +1462,7 @@ hipError_t run(Op op, const LaunchArgs& a) {
   const int64_t nodes = (int64_t)a.p.nx * a.p.ny * a.p.nz;
   switch (op) {
     case Op::Constants:
-      hipLaunchKernelGGL(k_constants<T>, dim3(1), dim3(64), 0, a.stream, a.p, a.n_species,
+      hipLaunchKernelGGL((k_constants<LAT, M, T>), dim3(1), dim3(64), 0, a.stream, a.p, a.n_species,
                          static_cast<Consts<T>*>(a.consts_out));
       break;
     case Op::Init: {

@@ -23,8 +23,15 @@ struct Consts {
   T R[kMaxSpecies][kMaxSpecies];
   T wall[6][kMaxSpecies];
   T xref[kMaxSpecies];
+  // collision coefficients (CollideCoef): A = I + (a/2) B as an affine map of
+  // the composition, and the relaxation-rule factors
+  T a0[kMaxSpecies];
+  T da[kMaxSpecies][kMaxSpecies];
+  T ea[kMaxSpecies][kMaxSpecies];
+  T ga[kMaxSpecies][kMaxSpecies];
+  T rule[5];
 };
-constexpr size_t kConstsBytes = 1024;   // >= sizeof(Consts<double>) = 960
+constexpr size_t kConstsBytes = 4096;   // >= sizeof(Consts<double>) = 2632
 static_assert(sizeof(Consts<double>) <= kConstsBytes, "constants block too small");
 
 // One mixture of a batch, as the batched sweep sees it (device array, read
