@@ -244,6 +244,8 @@ struct msd_sim {
   // resident workgroups of the blocked kernels by steps per pass (0: not queried)
   mutable int resident_fwd[msd::kMaxStepsPerPass + 1] = {};
   mutable int resident_adj[msd::kMaxStepsPerPass + 1] = {};
+  mutable int n_cu = 0;
+  mutable int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
 };
 
 namespace {
@@ -262,17 +264,27 @@ msd::LaunchArgs base_args(const msd_sim* s) {
   a.xcd_remap = s->launch.xcd_remap;
   a.nontemporal = s->launch.nontemporal;
   a.vec = s->launch.vec;
+  if (s->lds_per_cu < 0) {
+    int dev = 0, v = 0;
+    s->lds_per_cu = (hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+                        ? v
+                        : 0;
+  }
+  // the forward blocked sweep runs fastest with at most two workgroups per CU
+  // (measured on 2048^2 to 16384^2 lattices): each reserves over a third of the LDS
+  a.blocked_lds_floor = s->lds_per_cu > 0 ? s->lds_per_cu / 3 + 1 : 0;
   return a;
 }
 
 // Plan of the blocked sweep (or of the blocked adjoint) for this handle: steps
 // per pass (the largest count up to the requested one whose on-chip window
 // fits; 0: one step per pass) and rows per workgroup segment.  Automatic
-// segments (seg_rows = 0) give the launch about 1.35 rounds of the workgroups
-// the device holds at once (long segments re-read few halo rows), but at
-// least 8 rows; if 8-row segments leave fewer than 512 workgroups, one step per
-// pass is faster (small domains: measured on 512^2 to 4096^2 ternary FP32
-// lattices).  32-bit in-plane offsets need plane bytes < 4 GiB.
+// segments (seg_rows = 0) are sized from the number of workgroups the device
+// holds at once (see below; measured on 1024^2 to 16384^2 lattices with 3 to 5
+// species), at least 8 rows; if 8-row segments leave fewer than 512
+// workgroups, one step per pass is faster (small domains: measured on 512^2 to
+// 4096^2 ternary FP32 lattices).  32-bit in-plane offsets need plane bytes < 4 GiB.
 struct BlockedPlan {
   int tb = 0;
   int seg = 0;
@@ -301,15 +313,41 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
       msd::LaunchArgs a = base_args(s);
       a.tb = tb;
       a.adjoint = adjoint ? 1 : 0;
-      int slots = 0;
-      a.out_int = &slots;
-      if (dispatch(msd::Op::BlockedResident, a) != hipSuccess || slots <= 0) slots = 1024;
-      cached = slots;
+      int res[2] = {0, 0};
+      a.out_int = res;
+      if (dispatch(msd::Op::BlockedResident, a) != hipSuccess || res[0] <= 0 || res[1] <= 0) {
+        res[0] = 1024;
+        res[1] = 256;
+      }
+      cached = res[0];
+      s->n_cu = res[1];
     }
-    // about 1.35 rounds: measured best on 4096^2 (one exact round is 6 % slower)
-    const int64_t target = (int64_t)cached * 27 / 20;
-    const int64_t rows = (tiles_x * s->prob.ny + target - 1) / target;
-    seg = (int)std::max<int64_t>(8, std::min<int64_t>(rows, s->prob.ny));
+    if (adjoint) {
+      // about 1.35 rounds of the resident workgroups
+      const int64_t target = (int64_t)cached * 27 / 20;
+      const int64_t rows = (tiles_x * s->prob.ny + target - 1) / target;
+      seg = (int)std::max<int64_t>(8, std::min<int64_t>(rows, s->prob.ny));
+    } else {
+      // Forward sweep: about k * 2 workgroups per CU in all (at most what the
+      // device holds at once for k = 1), with the segments as tall as that
+      // allows; k doubles while segments stay at least 128 rows tall.  Two
+      // waves per SIMD nearly saturate the VALU here, so tall segments (few
+      // halo rows) win over occupancy on small lattices, and more workgroups
+      // balance better on large ones.
+      const int64_t half = std::max(1, std::min(cached, 2 * std::max(s->n_cu, 1)));
+      const int64_t ny = s->prob.ny;
+      auto seg_for = [&](int64_t k) {
+        const int64_t per_tile = std::max<int64_t>(1, k * half / tiles_x);
+        return (ny + per_tile - 1) / per_tile;
+      };
+      int64_t rows = seg_for(1);
+      for (int64_t k = 2; k <= 64; k *= 2) {
+        const int64_t r = seg_for(k);
+        if (r < 128) break;
+        rows = r;
+      }
+      seg = (int)std::max<int64_t>(8, std::min<int64_t>(rows, ny));
+    }
   }
   pl.tb = tb;
   pl.seg = seg;

@@ -1349,9 +1349,22 @@ hipError_t launch_adjoint_blocked_tb(const LaunchArgs& a) {
 
 // Workgroups of a blocked kernel (sweep or adjoint) that the whole device holds
 // at once: resident workgroups per CU (registers and LDS) times the CU count.
+// Dynamic LDS the forward blocked sweep adds to its own so that each
+// workgroup holds at least a.blocked_lds_floor bytes: the host sets the floor
+// to keep at most two workgroups on a CU, where the sweep runs fastest.
+template <int M, typename T, int TB, int C>
+constexpr int blocked_lds_bytes() {
+  return (TB - 1) * 2 * 2 * M * C * (int)sizeof(T);
+}
+template <int M, typename T, int TB, int C>
+size_t blocked_lds_pad(const LaunchArgs& a) {
+  constexpr int own = blocked_lds_bytes<M, T, TB, C>();
+  return a.blocked_lds_floor > own ? (size_t)(a.blocked_lds_floor - own) : 0;
+}
+
 template <int M, typename T, int TB>
 hipError_t blocked_resident(const LaunchArgs& a, int* out) {
-  *out = 0;
+  out[0] = out[1] = 0;
   constexpr int C = blocked_cols(M, TB, (int)sizeof(T)), CA = adjoint_blocked_cols(M, TB, (int)sizeof(T));
   const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
   int per_cu = 0;
@@ -1363,8 +1376,9 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
     }
   } else {
     if constexpr (C > 0) {
-      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true>, C, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false>, C, 0);
+      const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
+      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true>, C, pad)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false>, C, pad);
     }
   }
   if (e != hipSuccess) return e;
@@ -1373,7 +1387,8 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  *out = per_cu * cus;
+  out[0] = per_cu * cus;
+  out[1] = cus;
   return hipSuccess;
 }
 
@@ -1398,11 +1413,12 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     const T* src = static_cast<const T*>(a.src);
     T* dst = static_cast<T*>(a.dst);
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
+    const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
     if (walls)
-      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
                          dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     else
-      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), 0, a.stream, a.p, src,
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
                          dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     return hipSuccess;
   }

@@ -70,8 +70,9 @@ struct LaunchArgs {
   int64_t rec_stride = 0;    // blocked sweep: elements between recorded states (0: no recording)
   const void* states[4] = {nullptr, nullptr, nullptr, nullptr};   // blocked adjoint: s_{t-1}, ..., s_{t-TB}
   int64_t accum_slots = 0;   // adjoint: workgroup slots of the dL/dR accumulator
+  int blocked_lds_floor = 0; // blocked sweep: LDS bytes each workgroup reserves at least (caps residency)
   int adjoint = 0;           // BlockedResident: query the adjoint kernel
-  int* out_int = nullptr;    // BlockedResident: result
+  int* out_int = nullptr;    // BlockedResident: [0] workgroups resident at once, [1] CUs
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
   // init
   const void* xi0 = nullptr;
