@@ -105,6 +105,7 @@ struct msd_batch {
   std::vector<Range> ranges;
   msd_schedule sched{};
   int64_t t = 0;
+  int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
 };
 
 namespace {
@@ -373,6 +374,15 @@ int msd_batch_step(msd_batch* b, int64_t nsteps) {
   a.block_y = b->sched.block_y;
   a.xcd_remap = b->sched.xcd_remap;
   a.nontemporal = b->sched.nontemporal;
+  if (b->lds_per_cu < 0) {
+    int dev = 0, v = 0;
+    b->lds_per_cu = (hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+                        ? v
+                        : 0;
+  }
+  // at most two workgroups of the blocked sweep per CU, as for one mixture
+  a.blocked_lds_floor = b->lds_per_cu > 0 ? b->lds_per_cu / 3 + 1 : 0;
   // each range runs its own sequence of launches (the mixtures are independent)
   for (const Range& r : b->ranges) {
     int cur = b->mem[r.members[0]].cur;

@@ -1432,10 +1432,10 @@ hipError_t launch_batch_blocked_tb(const LaunchArgs& a) {
   } else {
     if (a.ntiles == 0) return hipSuccess;
     if (a.walls)
-      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), dim3(a.ntiles), dim3(C), 0, a.stream, a.insts,
+      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), dim3(a.ntiles), dim3(C), (blocked_lds_pad<M, T, TB, C>(a)), a.stream, a.insts,
                          a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
     else
-      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), dim3(a.ntiles), dim3(C), 0, a.stream, a.insts,
+      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), dim3(a.ntiles), dim3(C), (blocked_lds_pad<M, T, TB, C>(a)), a.stream, a.insts,
                          a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
     return hipSuccess;
   }
