@@ -10,6 +10,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "msd_launch.h"
 
@@ -383,6 +384,20 @@ __device__ __forceinline__ void gstore(uint64_t base, uint32_t off, T v, int nt)
     *q = v;
 }
 
+// Range-checked store: a raw buffer over [base, base + bytes) drops a store
+// whose offset is outside it (an offset of 0xFFFFFFFF writes nothing).
+template <typename T>
+__device__ __forceinline__ void bstore(uint64_t base, uint32_t bytes, uint32_t off, T v) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)off, 0, 0);
+  } else {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)off, 0, 0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked D2Q5 sweep: TB time steps per pass over HBM.
 //
@@ -469,16 +484,18 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   // offset, and no per-plane base is hoisted out of the row loop (which would
   // hold one SGPR pair per plane and level for the whole kernel).
   const uint64_t pstride = (uint64_t)p.plane * sizeof(T);
+  const uint32_t plane_bytes = (uint32_t)pstride;   // < 4 GiB (checked by the host)
 
   T ld_row[P], ld_nb[2][M];
   auto load_row = [&](int r) {
     const bool r_in = r >= 0 && r < ny;
     const int rl = r_in ? r : (((r % ny) + ny) % ny);
+    // the scalar base is taken outside the (lane-divergent with walls) branch
+    uint64_t b = scalar_base(src);
     if (col_ok && (r_in || py)) {
       const uint32_t row = (uint32_t)rl * (uint32_t)nx;
       const uint32_t off = (row + xl) * (uint32_t)sizeof(T);
       const uint32_t offm = (row + xlm) * (uint32_t)sizeof(T), offp = (row + xlp) * (uint32_t)sizeof(T);
-      uint64_t b = scalar_base(src);
 #pragma unroll
       for (int pl = 0; pl < P; ++pl, b += pstride) {
         ld_row[pl] = gload<T>(b, off, nt_ld);
@@ -520,10 +537,15 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     return (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
   };
 
+  // The march has a prologue of 2 TB input rows, during which the output
+  // level has no row yet, and a main part in which every output row exists:
+  // there the output level runs unconditionally and stores through
+  // range-checked buffer stores (lanes outside the output are masked by
+  // offset, not by a branch), so that every iteration issues the same stores
+  // and the wait for the next input row does not also wait for them.
   const int r_last = y1 - 1 + TB;
-  int r_in = y0 - TB;
-  load_row(r_in);
-  for (; r_in <= r_last; ++r_in) {
+  auto iteration = [&](int r_in, auto main_c) __attribute__((always_inline)) {
+    constexpr bool MAIN = decltype(main_c)::value;
     __syncthreads();
     {
       T f[M][Q];
@@ -551,7 +573,10 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       const int r = r_in - lvl;
       const int lp = lvl - 1;
       const int s = r & 1;
-      const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
+      // in the main part every level's row is inside the segment's range; rows
+      // beyond a y wall are skipped (never the output level's)
+      const bool row_ok = MAIN ? (lvl == TB || py || (r >= 0 && r < ny))
+                               : (lvl < TB && r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny)));
       if (lvl < TB) advance(lvl);
       if (!row_ok) continue;
       T f[M][Q];
@@ -584,19 +609,33 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       }
       collide_node<2, M, T>(f, nc.cc);
       if (lvl < TB) enter(lvl, r, f);
-      // the last level is the pass's output; recording (rec_stride > 0, uniform)
-      // also stores every intermediate level, level l at dst + (l - 1) rec_stride
-      if ((lvl == TB || rec_stride > 0) && c >= TB && c < C - TB && x_in && r >= y0 && r < y1) {
-        const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+      // The output level (main part only) stores the pass's output; recording
+      // (rec_stride > 0, uniform) also stores every intermediate level, level
+      // l at dst + (l - 1) rec_stride.
+      const bool out_col = c >= TB && c < C - TB && x_in;
+      if (lvl == TB) {
+        const uint32_t off = out_col ? ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T) : 0xFFFFFFFFu;
         uint64_t b = scalar_base(dst);
-        if (rec_stride > 0) b += (uint64_t)(lvl - 1) * (uint64_t)rec_stride * sizeof(T);
+        if (rec_stride > 0) b += (uint64_t)(TB - 1) * (uint64_t)rec_stride * sizeof(T);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int k = 0; k < Q; ++k, b += pstride) bstore<T>(b, plane_bytes, off, f[i][k]);
+      } else if (rec_stride > 0 && out_col && r >= y0 && r < y1) {
+        const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+        uint64_t b = scalar_base(dst) + (uint64_t)(lvl - 1) * (uint64_t)rec_stride * sizeof(T);
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
           for (int k = 0; k < Q; ++k, b += pstride) gstore<T>(b, off, f[i][k], nt_st);
       }
     }
-  }
+  };
+  const int r_main = y0 + TB;
+  load_row(y0 - TB);
+  int r_in = y0 - TB;
+  for (; r_in < r_main; ++r_in) iteration(r_in, std::false_type{});
+  for (; r_in <= r_last; ++r_in) iteration(r_in, std::true_type{});
 }
 
 template <int M, typename T, int TB, int C, bool WALLS>
@@ -1347,8 +1386,6 @@ hipError_t launch_adjoint_blocked_tb(const LaunchArgs& a) {
   }
 }
 
-// Workgroups of a blocked kernel (sweep or adjoint) that the whole device holds
-// at once: resident workgroups per CU (registers and LDS) times the CU count.
 // Dynamic LDS the forward blocked sweep adds to its own so that each
 // workgroup holds at least a.blocked_lds_floor bytes: the host sets the floor
 // to keep at most two workgroups on a CU, where the sweep runs fastest.
@@ -1362,6 +1399,9 @@ size_t blocked_lds_pad(const LaunchArgs& a) {
   return a.blocked_lds_floor > own ? (size_t)(a.blocked_lds_floor - own) : 0;
 }
 
+// Workgroups of a blocked kernel (sweep or adjoint) that the whole device holds
+// at once: resident workgroups per CU (registers and LDS, with the sweep's
+// reservation) times the CU count; out[1] is the CU count.
 template <int M, typename T, int TB>
 hipError_t blocked_resident(const LaunchArgs& a, int* out) {
   out[0] = out[1] = 0;
