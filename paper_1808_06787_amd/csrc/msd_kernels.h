@@ -405,24 +405,42 @@ __device__ __forceinline__ void bstore(uint64_t base, uint32_t bytes, uint32_t o
 // output rows [y0, y1).  Thread c holds column x = x0 - TB + c (a halo of TB
 // columns each side; wrapped for periodic x) at every time level.  The
 // workgroup marches over the input rows y0 - TB .. y1 - 1 + TB (wrapped for
-// periodic y); when input row r_in arrives, level l produces row r_in - l from
-// rows r - 1, r, r + 1 of level l - 1 (one pull-propagation + collision), and
-// level TB writes the output row.
+// periodic y); in iteration j the input row r_in = y0 - TB + j arrives and
+// level l produces row r_in - l from rows r - 1, r, r + 1 of level l - 1 (one
+// pull-propagation + collision); level TB writes the output row.
 //
 // Pull propagation takes the y-directions from the same column, so each level
-// keeps them in registers: the +y population of row r - 1, and the rest, +y
-// and -y populations of rows r and r + 1.  Only the two x-directions cross
-// columns: level 0 (the input) loads its neighbours' values from memory, and
-// levels 1 .. TB-1 pass theirs through LDS, two rows per level (ping-pong by
-// row parity), so one barrier per input row orders every LDS write after the
-// reads of the previous occupant of its slot.  Level l is valid on columns [l, C - l) and
-// rows [y0 - TB + l, y1 - 1 + TB - l]: a row outside that range (a uniform
-// condition) is skipped but still advances the register window; invalid
-// columns compute values that no valid node reads.  Nodes beyond a wall are
-// never read: the face rule at a boundary node reads the node itself.
-// Offsets within a plane are 32-bit (the host checks plane bytes < 4 GiB).
-// WALLS = false is the instantiation for a fully periodic domain: no face code.
+// keeps them in registers: a ring of three rows (rest, +y, -y), the row a
+// level produced in iteration j in slot j mod 3.  Only the two x-directions
+// cross columns: level 0 (the input) loads its neighbours' values from memory,
+// and levels 1 .. TB-1 pass theirs through LDS, two rows per level in slots
+// chosen by iteration parity, so one barrier per iteration orders every LDS
+// write after the reads of the previous occupant of its slot.  The march is
+// unrolled six times (the period of both), which turns every ring slot, LDS
+// slot and prefetch buffer into a compile-time choice: no register moves to
+// shift windows, no per-row address arithmetic.
+//
+// The first 2 TB iterations (the prologue, fully unrolled) fill the levels:
+// level l has its first row in iteration 2 l, and the output level none.  In
+// the main part every level has a row in every iteration; the output level
+// stores through range-checked buffer stores (lanes outside the output are
+// masked by offset, not by a branch), so every iteration issues the same
+// stores and the wait for the next input row does not also wait for them.
+// Level l is valid on columns [l, C - l); invalid columns compute values that
+// no valid node reads.  Rows beyond a y wall are skipped, and nodes beyond a
+// wall are never read: the face rule at a boundary node reads the node
+// itself.  Offsets within a plane are 32-bit (the host checks plane bytes <
+// 4 GiB).  WALLS = false is the instantiation for a fully periodic domain: no
+// face code.
 // ---------------------------------------------------------------------------
+template <int J>
+using Iter = std::integral_constant<int, J>;
+// f(Iter<0>{}), f(Iter<1>{}), ... in order
+template <typename F, int... Js>
+__device__ __forceinline__ void for_each_iter(F&& f, std::integer_sequence<int, Js...>) {
+  (f(Iter<Js>{}), ...);
+}
+
 template <int M, typename T, int TB, int C, bool WALLS>
 __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
                                              const Consts<T>* __restrict__ cst, int seg_rows, uint32_t tx,
@@ -434,7 +452,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   static_assert(L::axis(2) == 1 && L::sgn(2) > 0 && L::axis(4) == 1 && L::sgn(4) < 0, "y directions");
   constexpr int KXP = 1, KYP = 2, KXM = 3, KYM = 4;
   // x-direction populations of the two most recent rows of levels 1 .. TB-1:
-  // [level - 1][row parity][+x/-x][species][column].  Level 0 (the input rows)
+  // [level - 1][slot][+x/-x][species][column].  Level 0 (the input rows)
   // takes its x-neighbours straight from memory instead.
   __shared__ T xs[TB - 1][2][2][M][C];
 
@@ -455,29 +473,34 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   // a tile that reaches an x wall (uniform): only there do x-pulls need the face rule
   const bool tile_xwall = !px && (x0 - TB <= 0 || x0 - TB + C - 1 >= nx - 1);
   const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
+  const bool out_col = c >= TB && c < C - TB && x_in;
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
   const bool nt_ld = (nontemporal & NT_LOAD_ALIGNED) != 0;
   const int nt_st = nontemporal & NT_STORE;
 
-  // Per level (0 .. TB-1): +y of row r-1; rest/+y/-y of rows r (cur) and r+1 (nxt).
-  T yprev[TB][M], cur[TB][3][M], nxt[TB][3][M];
+  // ring[level][slot][rest/+y/-y][species] (levels 0 .. TB-1)
+  T ring[TB][3][3][M];
+  // level 0, by iteration parity: the left neighbour's +x and the right
+  // neighbour's -x (what level 1 pulls), and the node's own +x/-x (what the
+  // face rule at an x wall reads)
+  T nb[2][2][M], own[2][2][M];
+  // prefetched input rows, by iteration parity
+  T ld[2][P], ldn[2][2][M];
 #pragma unroll
   for (int l = 0; l < TB; ++l)
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      yprev[l][i] = T(0);
+    for (int sl = 0; sl < 3; ++sl)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i] = T(0);
-    }
-  // Level 0 also keeps, for rows r and r+1, the +x population of the left
-  // neighbour and the -x population of the right one (what level 1 pulls), and
-  // its own +x/-x (what the face rule at an x wall reads).
-  T nbc[2][M], nbn[2][M], ownc[2][M], ownn[2][M];
+      for (int j = 0; j < 3; ++j)
 #pragma unroll
-  for (int d = 0; d < 2; ++d)
+        for (int i = 0; i < M; ++i) ring[l][sl][j][i] = T(0);
 #pragma unroll
-    for (int i = 0; i < M; ++i) nbc[d][i] = nbn[d][i] = ownc[d][i] = ownn[d][i] = T(0);
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int i = 0; i < M; ++i) nb[b][d][i] = own[b][d][i] = ldn[b][d][i] = T(0);
 
   // Planes are walked from an opaque scalar base (scalar_base) in steps of the
   // plane stride: every access is that scalar base plus the lane's 32-bit
@@ -486,8 +509,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   const uint64_t pstride = (uint64_t)p.plane * sizeof(T);
   const uint32_t plane_bytes = (uint32_t)pstride;   // < 4 GiB (checked by the host)
 
-  T ld_row[P], ld_nb[2][M];
-  auto load_row = [&](int r) {
+  auto load_row = [&](int r, T (&row_v)[P], T (&nb_v)[2][M]) __attribute__((always_inline)) {
     const bool r_in = r >= 0 && r < ny;
     const int rl = r_in ? r : (((r % ny) + ny) % ny);
     // the scalar base is taken outside the (lane-divergent with walls) branch
@@ -498,38 +520,16 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       const uint32_t offm = (row + xlm) * (uint32_t)sizeof(T), offp = (row + xlp) * (uint32_t)sizeof(T);
 #pragma unroll
       for (int pl = 0; pl < P; ++pl, b += pstride) {
-        ld_row[pl] = gload<T>(b, off, nt_ld);
+        row_v[pl] = gload<T>(b, off, nt_ld);
         // the left neighbour's +x and the right neighbour's -x of the same plane
-        if (pl % Q == KXP) ld_nb[0][pl / Q] = gload<T>(b, offm, nt_ld);
-        if (pl % Q == KXM) ld_nb[1][pl / Q] = gload<T>(b, offp, nt_ld);
+        if (pl % Q == KXP) nb_v[0][pl / Q] = gload<T>(b, offm, nt_ld);
+        if (pl % Q == KXM) nb_v[1][pl / Q] = gload<T>(b, offp, nt_ld);
       }
     } else {
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
+      for (int pl = 0; pl < P; ++pl) row_v[pl] = T(0);
 #pragma unroll
-      for (int i = 0; i < M; ++i) ld_nb[0][i] = ld_nb[1][i] = T(0);
-    }
-  };
-  // Advance level l's window by one row; a computed row r also enters it (and LDS).
-  auto advance = [&](int l) {
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      yprev[l][i] = cur[l][1][i];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) cur[l][j][i] = nxt[l][j][i];
-    }
-  };
-  auto enter = [&](int l, int r, const T (&f)[M][Q]) {
-    const int s = r & 1;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (l > 0) {
-        xs[l - 1][s][0][i][c] = f[i][KXP];
-        xs[l - 1][s][1][i][c] = f[i][KXM];
-      }
-      nxt[l][0][i] = f[i][0];
-      nxt[l][1][i] = f[i][KYP];
-      nxt[l][2][i] = f[i][KYM];
+      for (int i = 0; i < M; ++i) nb_v[0][i] = nb_v[1][i] = T(0);
     }
   };
   // Dirichlet face: 2 w xi_wall minus the node's own opposite population; zero flux: that population.
@@ -537,82 +537,78 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     return (p.bc[fk] == BC_ZERO_FLUX) ? back : T(2.0 * L::w(kb)) * nc.wall[fk][i] - back;
   };
 
-  // The march has a prologue of 2 TB input rows, during which the output
-  // level has no row yet, and a main part in which every output row exists:
-  // there the output level runs unconditionally and stores through
-  // range-checked buffer stores (lanes outside the output are masked by
-  // offset, not by a branch), so that every iteration issues the same stores
-  // and the wait for the next input row does not also wait for them.
   const int r_last = y1 - 1 + TB;
-  auto iteration = [&](int r_in, auto main_c) __attribute__((always_inline)) {
+  // Iteration j of the march (jc: j itself in the prologue, j mod 6 in the
+  // main part, which starts at j = 2 TB).
+  auto iteration = [&](int r_in, auto jc, auto main_c) __attribute__((always_inline)) {
+    constexpr int JJ = decltype(jc)::value;
     constexpr bool MAIN = decltype(main_c)::value;
+    constexpr int J = JJ % 6;
+    constexpr int B = J & 1;   // this row's prefetch buffer and level-0 parity slot
     __syncthreads();
-    {
-      T f[M][Q];
 #pragma unroll
-      for (int i = 0; i < M; ++i)
+    for (int i = 0; i < M; ++i) {
+      ring[0][J % 3][0][i] = ld[B][i * Q];
+      ring[0][J % 3][1][i] = ld[B][i * Q + KYP];
+      ring[0][J % 3][2][i] = ld[B][i * Q + KYM];
+      own[B][0][i] = ld[B][i * Q + KXP];
+      own[B][1][i] = ld[B][i * Q + KXM];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) f[i][k] = ld_row[i * Q + k];
-      advance(0);
-      enter(0, r_in, f);
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          nbc[d][i] = nbn[d][i];
-          nbn[d][i] = ld_nb[d][i];
-          ownc[d][i] = ownn[d][i];
-        }
-        ownn[0][i] = f[i][KXP];
-        ownn[1][i] = f[i][KXM];
-      }
+      for (int d = 0; d < 2; ++d) nb[B][d][i] = ldn[B][d][i];
     }
-    if (r_in < r_last) load_row(r_in + 1);
+    // the next input row (past the last one it is a harmless in-bounds or zero load)
+    load_row(r_in + 1, ld[B ^ 1], ldn[B ^ 1]);
 #pragma unroll
     for (int lvl = 1; lvl <= TB; ++lvl) {
+      // level lvl - 1 produced rows r - 1, r, r + 1 in iterations j - 2, j - 1, j
+      if (!MAIN && (lvl == TB || JJ < 2 * lvl)) continue;   // no row yet (compile time)
       const int r = r_in - lvl;
       const int lp = lvl - 1;
-      const int s = r & 1;
-      // in the main part every level's row is inside the segment's range; rows
-      // beyond a y wall are skipped (never the output level's)
-      const bool row_ok = MAIN ? (lvl == TB || py || (r >= 0 && r < ny))
-                               : (lvl < TB && r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny)));
-      if (lvl < TB) advance(lvl);
-      if (!row_ok) continue;
+      const int sm = (J + 4) % 3, s0 = (J + 2) % 3, sp = J % 3;
+      const int sx = (J - lvl) & 1;   // LDS slot of row r at level lp (and of this level's row)
+      if (lvl < TB && !py && (r < 0 || r >= ny)) continue;   // beyond a y wall
       T f[M][Q];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        f[i][0] = cur[lp][0][i];
-        f[i][KXP] = lp == 0 ? nbc[0][i] : xs[lp > 0 ? lp - 1 : 0][s][0][i][cm];
-        f[i][KXM] = lp == 0 ? nbc[1][i] : xs[lp > 0 ? lp - 1 : 0][s][1][i][cp];
-        f[i][KYP] = yprev[lp][i];
-        f[i][KYM] = nxt[lp][2][i];
+        f[i][0] = ring[lp][s0][0][i];
+        f[i][KXP] = lp == 0 ? nb[B ^ 1][0][i] : xs[lp > 0 ? lp - 1 : 0][sx][0][i][cm];
+        f[i][KXM] = lp == 0 ? nb[B ^ 1][1][i] : xs[lp > 0 ? lp - 1 : 0][sx][1][i][cp];
+        f[i][KYP] = ring[lp][sm][1][i];
+        f[i][KYM] = ring[lp][sp][2][i];
       }
       if constexpr (WALLS) {
         if (tile_xwall) {
 #pragma unroll
           for (int i = 0; i < M; ++i) {
-            const T own_xm = lp == 0 ? ownc[1][i] : xs[lp > 0 ? lp - 1 : 0][s][1][i][c];
-            const T own_xp = lp == 0 ? ownc[0][i] : xs[lp > 0 ? lp - 1 : 0][s][0][i][c];
+            const T own_xm = lp == 0 ? own[B ^ 1][1][i] : xs[lp > 0 ? lp - 1 : 0][sx][1][i][c];
+            const T own_xp = lp == 0 ? own[B ^ 1][0][i] : xs[lp > 0 ? lp - 1 : 0][sx][0][i][c];
             if (wall_xlo) f[i][KXP] = face(0, KXM, i, own_xm);
             if (wall_xhi) f[i][KXM] = face(1, KXP, i, own_xp);
           }
         }
         if (!py && r == 0) {
 #pragma unroll
-          for (int i = 0; i < M; ++i) f[i][KYP] = face(2, KYM, i, cur[lp][2][i]);
+          for (int i = 0; i < M; ++i) f[i][KYP] = face(2, KYM, i, ring[lp][s0][2][i]);
         }
         if (!py && r == ny - 1) {
 #pragma unroll
-          for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, cur[lp][1][i]);
+          for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, ring[lp][s0][1][i]);
         }
       }
       collide_node<2, M, T>(f, nc.cc);
-      if (lvl < TB) enter(lvl, r, f);
+      if (lvl < TB) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          xs[lvl < TB ? lvl - 1 : 0][sx][0][i][c] = f[i][KXP];
+          xs[lvl < TB ? lvl - 1 : 0][sx][1][i][c] = f[i][KXM];
+          ring[lvl < TB ? lvl : 0][sp][0][i] = f[i][0];
+          ring[lvl < TB ? lvl : 0][sp][1][i] = f[i][KYP];
+          ring[lvl < TB ? lvl : 0][sp][2][i] = f[i][KYM];
+        }
+      }
       // The output level (main part only) stores the pass's output; recording
       // (rec_stride > 0, uniform) also stores every intermediate level, level
       // l at dst + (l - 1) rec_stride.
-      const bool out_col = c >= TB && c < C - TB && x_in;
       if (lvl == TB) {
         const uint32_t off = out_col ? ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T) : 0xFFFFFFFFu;
         uint64_t b = scalar_base(dst);
@@ -631,11 +627,25 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       }
     }
   };
-  const int r_main = y0 + TB;
-  load_row(y0 - TB);
-  int r_in = y0 - TB;
-  for (; r_in < r_main; ++r_in) iteration(r_in, std::false_type{});
-  for (; r_in <= r_last; ++r_in) iteration(r_in, std::true_type{});
+  load_row(y0 - TB, ld[0], ldn[0]);
+  for_each_iter([&](auto jc) __attribute__((always_inline)) {
+    iteration(y0 - TB + decltype(jc)::value, jc, std::false_type{});
+  }, std::make_integer_sequence<int, 2 * TB>{});
+  constexpr int P0 = (2 * TB) % 6;
+  for (int r0 = y0 + TB;; r0 += 6) {
+    if (r0 > r_last) break;
+    iteration(r0, Iter<(P0 + 0) % 6>{}, std::true_type{});
+    if (r0 + 1 > r_last) break;
+    iteration(r0 + 1, Iter<(P0 + 1) % 6>{}, std::true_type{});
+    if (r0 + 2 > r_last) break;
+    iteration(r0 + 2, Iter<(P0 + 2) % 6>{}, std::true_type{});
+    if (r0 + 3 > r_last) break;
+    iteration(r0 + 3, Iter<(P0 + 3) % 6>{}, std::true_type{});
+    if (r0 + 4 > r_last) break;
+    iteration(r0 + 4, Iter<(P0 + 4) % 6>{}, std::true_type{});
+    if (r0 + 5 > r_last) break;
+    iteration(r0 + 5, Iter<(P0 + 5) % 6>{}, std::true_type{});
+  }
 }
 
 template <int M, typename T, int TB, int C, bool WALLS>
