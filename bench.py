@@ -400,6 +400,11 @@ def main():
     del sim
     traffic = load_traffic(w.name)
     valu_time = load_valu_time(w.name)
+    try:
+        valu_busy_clock = float(load_profile("valu", w.name)["valu_busy_frac_at_estimated_clock"])
+        clock_ghz = float(load_profile("valu", w.name)["clock_estimate_GHz"])
+    except (KeyError, ValueError):
+        valu_busy_clock = clock_ghz = None
     out = {
         "metric": "MLUPS (node-component updates per second) of the fused collide-and-stream sweep",
         "value": round(mlups, 1),
@@ -431,9 +436,12 @@ def main():
             "traffic_GBps": round(traffic / per_launch / 1e9, 1) if traffic else None,
             "traffic_frac": round(traffic / per_launch / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
             "valu_busy_frac": round(valu_time / per_launch, 4) if valu_time else None,
+            "valu_busy_frac_at_clock_under_load": valu_busy_clock,
+            "clock_under_load_GHz": clock_ghz,
             "note": ("several steps per launch (temporal blocking): achieved counts the bytes of every step "
                      "performed, the kernel moves `traffic` bytes per launch; its limiter is VALU issue "
-                     "(valu_busy_frac at 2.4 GHz) rather than HBM") if rec["steps_per_pass"] > 1 else None,
+                     "(valu_busy_frac at 2.4 GHz; the profile's wave-cycle count gives the clock under load) "
+                     "rather than HBM") if rec["steps_per_pass"] > 1 else None,
         },
         "nonfinite": bad,
     }
