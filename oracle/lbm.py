@@ -45,7 +45,9 @@ class Problem:
     bc      : per axis a pair (low face, high face) of PERIODIC / ZERO_FLUX /
               DIRICHLET; default all periodic
     xi_wall : Dirichlet face values {(axis, 0|1): (N,) mole fractions}
-    relax   : ms.RELAX_PAPER (Eq. (3-16)) or ms.RELAX_SRT (Lambda_2 = Lambda_1)
+    relax   : ms.RELAX_PAPER (Eq. (3-16)), ms.RELAX_SRT (Lambda_2 = Lambda_1) or
+              ms.RELAX_TRT (Lambda_2 from the product rule with parameter `magic`)
+    magic   : TRT parameter (1/lambda_1^ii - 1/2)(1/lambda_2^ii - 1/2) (> 0)
     lambda0 : value of every lambda_0^ij (Sec. 3.1 sets it to 1; it multiplies
               m_0 - m_0^eq, which is identically zero)
     c_t     : total molar concentration in the flux law (Eq. (2-12))
@@ -60,6 +62,7 @@ class Problem:
     bc: tuple = None
     xi_wall: dict = field(default_factory=dict)
     relax: str = _ms.RELAX_PAPER
+    magic: float = _ms.MAGIC_PAPER
     lambda0: float = 1.0
     c_t: float = 1.0
     xi_ref: np.ndarray = None
@@ -140,7 +143,7 @@ def relaxation_matrices(prob: Problem, xi: np.ndarray):
     B = _ms.ms_B(xi_b, prob.D)
     Dt = _ms.fick_matrix(B)
     L1 = _ms.lambda1_from_fick(Dt, prob.lat.cs2, 1.0)
-    L2 = _ms.lambda2_from_lambda1(L1, prob.relax)
+    L2 = _ms.lambda2_from_lambda1(L1, prob.relax, prob.magic)
     return B, Dt, L1, L2
 
 

@@ -87,22 +87,37 @@ def fick_from_lambda1(L1: np.ndarray, cs2: float, dt: float = 1.0) -> np.ndarray
 
 RELAX_PAPER = "paper"   # Eq. (3-16)
 RELAX_SRT = "srt"       # all relaxation parameters equal (Sec. 3.1, after Eq. (3-14))
+RELAX_TRT = "trt"       # odd and even moments with two parameters (Sec. 3.1, after Eq. (3-14))
+
+MAGIC_PAPER = 3.0 / 16.0
 
 
-def lambda2_from_lambda1(L1: np.ndarray, rule: str = RELAX_PAPER) -> np.ndarray:
+def lambda2_from_lambda1(L1: np.ndarray, rule: str = RELAX_PAPER, magic: float = MAGIC_PAPER) -> np.ndarray:
     """Second-order relaxation matrix Lambda_2.
 
     Paper rule, Eq. (3-16): lambda_2^ij = lambda_1^ij for i != j and
     lambda_2^ii = 8 (lambda_1^ii - 2) / (lambda_1^ii - 8), applied entry by entry
     to the coupled matrix Lambda_1.  SRT: Lambda_2 = Lambda_1.
+
+    TRT (the two-relaxation-time case named after Eq. (3-14): odd moments with
+    lambda_o = lambda_1, even ones with lambda_e = lambda_2): the even parameter of
+    each species is fixed by the product (1/lambda_1^ii - 1/2)(1/lambda_2^ii - 1/2)
+    = magic, i.e. lambda_2^ii = 2 (2 - l) / (2 + (4 magic - 1) l) with l = lambda_1^ii;
+    off-diagonal entries as in the paper rule.  Eq. (3-16) is this rule with
+    magic = 3/16.
     """
     L2 = np.array(L1, dtype=np.float64, copy=True)
     if rule == RELAX_SRT:
         return L2
-    if rule != RELAX_PAPER:
+    if rule not in (RELAX_PAPER, RELAX_TRT):
         raise ValueError(f"unknown relaxation rule {rule!r}")
+    if rule == RELAX_TRT and not (np.isfinite(magic) and magic > 0):
+        raise ValueError("the TRT parameter must be positive")
     m = L1.shape[-1]
     for i in range(m):
         l1 = L1[..., i, i]
-        L2[..., i, i] = 8.0 * (l1 - 2.0) / (l1 - 8.0)
+        if rule == RELAX_PAPER:
+            L2[..., i, i] = 8.0 * (l1 - 2.0) / (l1 - 8.0)
+        else:
+            L2[..., i, i] = 2.0 * (2.0 - l1) / (2.0 + (4.0 * magic - 1.0) * l1)
     return L2

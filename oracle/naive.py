@@ -57,6 +57,10 @@ def _node_matrices(prob, xi_all):
     if prob.relax == _ms.RELAX_PAPER:
         for i in range(m):
             L2[i][i] = 8.0 * (L1[i][i] - 2.0) / (L1[i][i] - 8.0)
+    elif prob.relax == _ms.RELAX_TRT:
+        # (1/l1 - 1/2)(1/l2 - 1/2) = magic, solved for l2
+        for i in range(m):
+            L2[i][i] = 1.0 / (0.5 + prob.magic / (1.0 / L1[i][i] - 0.5))
     return B, Dt, L1, L2
 
 

@@ -88,7 +88,11 @@ class Twin:
             L0 = L1
         else:
             diag = torch.diagonal(L1, dim1=-2, dim2=-1)
-            L2 = L1 - torch.diag_embed(diag) + torch.diag_embed(8.0 * (diag - 2.0) / (diag - 8.0))
+            if p.relax == _ms.RELAX_TRT:
+                l2 = 2.0 * (2.0 - diag) / (2.0 + (4.0 * p.magic - 1.0) * diag)
+            else:
+                l2 = 8.0 * (diag - 2.0) / (diag - 8.0)
+            L2 = L1 - torch.diag_embed(diag) + torch.diag_embed(l2)
             L0 = torch.full_like(L1, p.lambda0)
         per = {0: L0, 1: L1, 2: L2}
         feq = self.w.reshape((1, -1) + (1,) * d) * xi_e[:, None]

@@ -165,6 +165,31 @@ def test_lambda2_rule_eq_3_16():
     np.testing.assert_array_equal(ms.lambda2_from_lambda1(L1, ms.RELAX_SRT), L1)
 
 
+@pytest.mark.parametrize("magic", [1 / 12, 3 / 16, 1 / 4, 1 / 2, 2.0])
+def test_trt_rule_product_and_paper_special_case(magic):
+    """TRT (odd moments with lambda_1, even ones with lambda_2, Sec. 3.1 after Eq. (3-14)):
+    the diagonal lambda_2 solves (1/l1 - 1/2)(1/l2 - 1/2) = magic for every l1 in (0, 2),
+    off-diagonals stay lambda_1, and magic = 3/16 is Eq. (3-16) exactly."""
+    rng = np.random.default_rng(8)
+    l1 = rng.uniform(0.05, 1.95, size=(50, 3))
+    L1 = np.zeros((50, 3, 3))
+    for i in range(3):
+        L1[:, i, i] = l1[:, i]
+    L1[:, 0, 1] = rng.uniform(-0.2, 0.2, 50)
+    L2 = ms.lambda2_from_lambda1(L1, ms.RELAX_TRT, magic)
+    np.testing.assert_array_equal(L2[:, 0, 1], L1[:, 0, 1])
+    for i in range(3):
+        np.testing.assert_allclose((1 / L1[:, i, i] - 0.5) * (1 / L2[:, i, i] - 0.5), magic, rtol=1e-12)
+        assert np.all((L2[:, i, i] > 0) & (L2[:, i, i] < 2))       # stable even relaxation
+    if magic == 3 / 16:
+        np.testing.assert_allclose(L2, ms.lambda2_from_lambda1(L1, ms.RELAX_PAPER), rtol=1e-14, atol=1e-15)
+
+
+def test_trt_rejects_non_positive_parameter():
+    with pytest.raises(ValueError):
+        ms.lambda2_from_lambda1(np.eye(2), ms.RELAX_TRT, 0.0)
+
+
 def test_lattice_weights_and_sound_speed():
     """Eqs. (3-5), (3-7), (3-10): weights sum to one, velocity sets are symmetric,
     and sum_k w_k c_k c_k = cs2 I with cs2 = 1/3, 1/3, 1/4."""

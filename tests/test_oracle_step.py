@@ -60,6 +60,24 @@ def test_vectorised_matches_scalar_loops(name, relax):
 
 
 @pytest.mark.parametrize("name", LATS)
+@pytest.mark.parametrize("magic", [0.1, 0.6])
+def test_vectorised_matches_scalar_loops_trt(name, magic):
+    """TRT: the vectorised oracle (closed form of lambda_2) and the scalar loops (lambda_2
+    solved from the defining product) agree."""
+    rng = np.random.default_rng(int(magic * 1000) + len(name))
+    N = 3
+    shape = _shape(name, (5, 4, 3))
+    d = len(shape)
+    kinds = [(lbm.ZERO_FLUX, lbm.DIRICHLET), (lbm.PERIODIC, lbm.PERIODIC), (lbm.DIRICHLET, lbm.ZERO_FLUX)]
+    bc = tuple(kinds[a] for a in range(d))
+    walls = {(a, s): _rand_field(rng, N, ()) for a in range(d) for s in (0, 1) if bc[a][s] == lbm.DIRICHLET}
+    D = _rand_D(rng, N, 0.05, 0.3)
+    p = lbm.Problem(name, D, shape, bc=bc, xi_wall=walls, relax=ms.RELAX_TRT, magic=magic)
+    xi0 = _rand_field(rng, N, p.nodes)
+    np.testing.assert_allclose(lbm.run(p, xi0, 4), naive.run(p, xi0, 4), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", LATS)
 def test_vectorised_matches_scalar_loops_linearised(name):
     rng = np.random.default_rng(7)
     N = 3
@@ -108,7 +126,7 @@ def _trt_collision_matrix(L, L1, L2):
 
 
 @pytest.mark.parametrize("name", LATS)
-@pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT])
+@pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT, ms.RELAX_TRT])
 def test_exact_discrete_fourier_evolution_linear(name, relax):
     """Linearised (constant-B) case: a single Fourier mode evolves exactly by the
     amplification matrix G = S(k) C, S = diag(exp(-i k.c_k)) (Eq. (3-2) with pull
@@ -119,10 +137,11 @@ def test_exact_discrete_fourier_evolution_linear(name, relax):
     D = _rand_D(rng, N, 0.03, 0.3)
     xref = np.array([0.1, 0.2, 0.3, 0.4])
     shape = _shape(name, (12, 8, 6))
-    p = lbm.Problem(name, D, shape, relax=relax, xi_ref=xref)
+    magic = 0.07       # TRT case: a parameter far from Eq. (3-16)'s 3/16
+    p = lbm.Problem(name, D, shape, relax=relax, xi_ref=xref, magic=magic)
     B = ms.ms_B(xref, D)
     L1 = ms.lambda1_from_fick(np.linalg.inv(B), L.cs2)
-    L2 = ms.lambda2_from_lambda1(L1, relax)
+    L2 = ms.lambda2_from_lambda1(L1, relax, magic)
     C = _trt_collision_matrix(L, L1, L2)
     kvec = np.array([2 * np.pi * (a + 1) / shape[a] for a in range(L.d)])
     S = np.kron(np.eye(N - 1), np.diag(np.exp(-1j * (L.c[:, : L.d] @ kvec))))

@@ -30,7 +30,8 @@ def _problem(name, rng, N, relax=ms.RELAX_PAPER, walls=True, lin=False):
     if lin:
         x = rng.uniform(0.2, 1.0, N)
         xref = x / x.sum()
-    return lbm.Problem(name, _rand_D(rng, N), shape, bc=tuple(bc), xi_wall=xi_wall, relax=relax, xi_ref=xref)
+    return lbm.Problem(name, _rand_D(rng, N), shape, bc=tuple(bc), xi_wall=xi_wall, relax=relax, xi_ref=xref,
+                       magic=0.3 if relax == ms.RELAX_TRT else ms.MAGIC_PAPER)
 
 
 def _field(rng, p):
@@ -39,7 +40,7 @@ def _field(rng, p):
 
 
 @pytest.mark.parametrize("name", LATS)
-@pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT])
+@pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT, ms.RELAX_TRT])
 def test_twin_forward_equals_oracle(name, relax):
     rng = np.random.default_rng(31)
     p = _problem(name, rng, 4, relax)
