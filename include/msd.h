@@ -40,7 +40,7 @@ extern "C" {
 #define MSD_API
 #endif
 
-#define MSD_ABI_VERSION 1
+#define MSD_ABI_VERSION 2
 #define MSD_MAX_SPECIES 8
 
 /* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10),
@@ -53,8 +53,12 @@ enum msd_precision { MSD_F32 = 4, MSD_F64 = 8 };
 /* Second-order relaxation: MSD_RELAX_PAPER is Eq. (3-16) (lambda_2^ii =
  * 8(lambda_1^ii - 2)/(lambda_1^ii - 8), off-diagonal lambda_2^ij = lambda_1^ij);
  * MSD_RELAX_SRT sets every relaxation parameter to lambda_1 (the single-
- * relaxation-time special case named after Eq. (3-14)). */
-enum msd_relax { MSD_RELAX_PAPER = 0, MSD_RELAX_SRT = 1 };
+ * relaxation-time special case named after Eq. (3-14)); MSD_RELAX_TRT is the
+ * two-relaxation-time case named there (odd moments with lambda_1, even ones
+ * with lambda_2), lambda_2^ii fixed by (1/lambda_1^ii - 1/2)(1/lambda_2^ii - 1/2)
+ * = msd_problem.trt_magic and off-diagonals as in Eq. (3-16), which is the
+ * trt_magic = 3/16 case. */
+enum msd_relax { MSD_RELAX_PAPER = 0, MSD_RELAX_SRT = 1, MSD_RELAX_TRT = 2 };
 
 /* Face conditions, Sec. 4: half-way bounce-back gives zero flux, half-way
  * anti-bounce-back holds a Dirichlet mole fraction.  Periodic faces come in
@@ -66,7 +70,7 @@ enum msd_status {
   MSD_EINVAL = -1,      /* bad lattice, extents, species count, faces or pointer */
   MSD_EDIFF = -2,       /* D not symmetric or an off-diagonal D_ij <= 0 (Sec. 2, after Eq. (2-7)) */
   MSD_ECOMP = -3,       /* a composition (wall or reference) off the simplex */
-  MSD_ERELAX = -4,      /* unknown relaxation rule */
+  MSD_ERELAX = -4,      /* unknown relaxation rule, or a TRT parameter that is not > 0 */
   MSD_EHIP = -5,        /* a HIP runtime call failed; msd_last_error() has its text */
   MSD_EDIVERGED = -6,   /* diagnostics found non-finite mole fractions */
   MSD_ENOMEM = -7,      /* workspace smaller than msd_workspace_bytes() */
@@ -96,6 +100,7 @@ typedef struct msd_problem {
   int32_t plane_pad;        /* extra values between consecutive distribution planes: a multiple
                                of 64, >= 0 (0 = planes of the node count rounded up to 64) */
   int32_t reserved;         /* must be 0 */
+  double trt_magic;         /* MSD_RELAX_TRT only: the product parameter, finite and > 0 */
 } msd_problem;
 
 typedef struct msd_sim msd_sim;

@@ -11,12 +11,13 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsd.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_SPECIES = 8
 
 D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6 = 1, 2, 3, 4, 5, 6
 F32, F64 = 4, 8
-RELAX_PAPER, RELAX_SRT = 0, 1
+RELAX_PAPER, RELAX_SRT, RELAX_TRT = 0, 1, 2
+MAGIC_PAPER = 3.0 / 16.0
 BC_PERIODIC, BC_ZERO_FLUX, BC_DIRICHLET = 0, 1, 2
 
 OK = 0
@@ -44,6 +45,7 @@ class MsdProblem(C.Structure):
         ("bc", C.c_int32 * 6),
         ("plane_pad", C.c_int32),
         ("reserved", C.c_int32),
+        ("trt_magic", C.c_double),
     ]
 
 

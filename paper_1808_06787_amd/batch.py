@@ -21,7 +21,8 @@ ORDERS = {"instance": F.ORDER_INSTANCE, "interleaved": F.ORDER_INTERLEAVED}
 
 class Batch:
     def __init__(self, specs, lattice: str = "D2Q5", precision: str = "f32", device=None, stream=None):
-        """specs: list of dicts with keys D, shape and optionally bc, xi_wall, relax, c_t, xi_ref."""
+        """specs: list of dicts with keys D, shape and optionally bc, xi_wall, relax, c_t, xi_ref,
+        trt_magic."""
         self.lib = F.lib()
         self.lattice = lattice
         self.precision = precision
@@ -33,7 +34,8 @@ class Batch:
         self.shapes, self.N = [], []
         for i, sp in enumerate(specs):
             p, keep = make_problem(lattice, sp["D"], sp["shape"], precision, sp.get("bc"), sp.get("xi_wall"),
-                                   sp.get("relax", "paper"), sp.get("c_t", 1.0), sp.get("xi_ref"))
+                                   sp.get("relax", "paper"), sp.get("c_t", 1.0), sp.get("xi_ref"),
+                                   trt_magic=sp.get("trt_magic", F.MAGIC_PAPER))
             arr[i] = p
             self._keep.append(keep)
             self.shapes.append(tuple(int(s) for s in sp["shape"]))

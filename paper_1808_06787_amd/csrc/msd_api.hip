@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cstddef>
 #include <new>
 #include <string>
 #include <utility>
@@ -112,7 +113,10 @@ int validate(const msd_problem* p) {
       if (v != p->D[j * N + i]) return fail(MSD_EDIFF, "D is not symmetric at (%d, %d)", i, j);
     }
   if (!(p->c_t > 0.0) || !std::isfinite(p->c_t)) return fail(MSD_EINVAL, "c_t = %g must be positive", p->c_t);
-  if (p->relax != MSD_RELAX_PAPER && p->relax != MSD_RELAX_SRT) return fail(MSD_ERELAX, "unknown relax %d", p->relax);
+  if (p->relax != MSD_RELAX_PAPER && p->relax != MSD_RELAX_SRT && p->relax != MSD_RELAX_TRT)
+    return fail(MSD_ERELAX, "unknown relax %d", p->relax);
+  if (p->relax == MSD_RELAX_TRT && !(p->trt_magic > 0.0 && std::isfinite(p->trt_magic)))
+    return fail(MSD_ERELAX, "trt_magic = %g must be positive", p->trt_magic);
   bool need_wall = false;
   for (int a = 0; a < 3; ++a) {
     const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
@@ -154,6 +158,7 @@ void fill_kernel_problem(const msd_problem* problem, int64_t plane, Problem* out
   kp.ny = (int32_t)problem->ny;
   kp.nz = (int32_t)problem->nz;
   kp.relax = problem->relax;
+  kp.magic = problem->relax == MSD_RELAX_TRT ? problem->trt_magic : 3.0 / 16.0;
   kp.linearized = problem->linearized ? 1 : 0;
   for (int f = 0; f < 6; ++f) kp.bc[f] = problem->bc[f];
   kp.plane = plane;
@@ -247,6 +252,10 @@ struct msd_sim {
   mutable int n_cu = 0;
   mutable int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
 };
+
+static_assert(sizeof(msd_problem) == 120 && offsetof(msd_problem, c_t) == 64 && offsetof(msd_problem, bc) == 80 &&
+                  offsetof(msd_problem, trt_magic) == 112,
+              "msd_problem layout (ABI version 2)");
 
 namespace {
 

@@ -108,7 +108,7 @@ template <> struct Lattice<6> {
 // ---------------------------------------------------------------------------
 struct Problem {
   int32_t nx, ny, nz;
-  int32_t relax;          // 0 paper rule (Eq. (3-16)), 1 SRT
+  int32_t relax;          // 0 paper rule (Eq. (3-16)), 1 SRT, 2 TRT
   int32_t linearized;     // 1: B at xi_ref
   int32_t bc[6];          // x_lo, x_hi, y_lo, y_hi, z_lo, z_hi
   int64_t plane;          // elements between consecutive planes of a buffer
@@ -116,6 +116,7 @@ struct Problem {
   double D[kMaxSpecies][kMaxSpecies];
   double wall[6][kMaxSpecies];
   double xi_ref[kMaxSpecies];
+  double magic;           // TRT: (1/lambda_1 - 1/2)(1/lambda_2 - 1/2) per species
 };
 
 // 1/x.  FP32: the hardware reciprocal, within 1 ulp of the quotient (an IEEE
@@ -234,22 +235,29 @@ __device__ __forceinline__ double mad(double a, double b, double c) { return __b
 // with da_ik = (a/2)(R_ik - R_iN) = -ea_ik, ga_ik = 0, a0_i = 1 + (a/2) R_iN;
 // the linearised mode freezes A at xi_ref (da = ea = 0, a0 and ga hold
 // A(xi_ref)).  rule[] switches the relaxation rule without a branch: with
-// sigma = 1 for Eq. (3-16) and 0 for SRT it holds
-// (4 sigma, sigma/2, -sigma, 1 - sigma/2, sigma - 2) (see collide_node).
+// sigma = 1 for Eq. (3-16) and TRT and 0 for SRT, and the TRT parameter
+// magic (3/16 for Eq. (3-16)), it holds (sigma, sigma/2, -sigma, 1 - sigma/2,
+// sigma - 2, 1 - 4 magic, 8 magic) (SRT: 0 and 1 for the last two; see
+// collide_node).
 template <int M, typename T>
 struct CollideCoef {
   T a0[M];
   T da[M][M];
   T ea[M][M];
   T ga[M][M];
-  T rule[5];
+  T rule[7];
 };
 
 // Collision of one node in place: f[i][k] <- f^+ (Eq. (3-13a) + back-transform).
 //
-// With K2 = 2 A^-1, Lambda_1 = 2 (I - K) = 2I - K2.  Eq. (3-16) in terms of
-// kd = K2_ii (lambda_1 = 2 - kd):  lambda_2 = 8 (2 - lambda_1)/(8 - lambda_1)
-// = 8 kd / (6 + kd), so hd = (lambda_2 - lambda_1)/2 = 4 kd/(6 + kd) + kd/2 - 1.
+// With K2 = 2 A^-1, Lambda_1 = 2 (I - K) = 2I - K2.  The even parameter of
+// species i from the product rule (1/lambda_1 - 1/2)(1/lambda_2 - 1/2) = magic
+// (Eq. (3-16) is magic = 3/16, where lambda_2 = 8 (2 - lambda_1)/(8 - lambda_1)),
+// in terms of kd = K2_ii (lambda_1 = 2 - kd):
+//   lambda_2 / 2 = kd / (8 magic + (1 - 4 magic) kd),
+// so hd = (lambda_2 - lambda_1)/2 = kd / (8 magic + (1 - 4 magic) kd) + kd/2 - 1
+// (for 3/16: 4 kd/(6 + kd) + kd/2 - 1).  The denominator stays positive for
+// kd in (0, 2) and any magic > 0.
 // The relaxation f^+_k = f_k - G neq_k - hd * neq_kbar with G = Lambda_1 +
 // diag(hd) (the pair form of Lambda_1 odd + Lambda_2 even) runs as a chain of
 // FMAs with nG = -G:  nG_ij = K2_ij (i != j), nG_ii = kd - 2 - hd.
@@ -285,7 +293,7 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const C
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     const T kd = nG[i][i];
-    const T r = recip(kd + T(6));
+    const T r = recip(mad(kd, cc.rule[5], cc.rule[6]));
     const T t = kd * cc.rule[0];
     const T hd = mad(t, r, mad(kd, cc.rule[1], cc.rule[2]));
     nG[i][i] = mad(-t, r, mad(kd, cc.rule[3], cc.rule[4]));
@@ -496,11 +504,14 @@ __device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>&
 // [i][j] for i < m, j <= m) into Rbar.  The forward quantities are recomputed
 // exactly as collide_node computes them:
 //   g = f - Lambda_1 neq - diag(delta) even,  Lambda_1 = 2 (I - K),
-//   K = (I + h B)^-1,  delta_i = phi(Lambda_1_ii) - Lambda_1_ii,  phi(l) = 8 (l - 2)/(l - 8).
+//   K = (I + h B)^-1,  delta_i = sigma (phi(Lambda_1_ii) - Lambda_1_ii),
+//   phi(l) = 2 (2 - l) / (2 - g1 l)  (the product rule; g1 = 1 - 4 magic, g0 = 8 magic,
+//   so phi'(l) = -2 g0 / (2 - g1 l)^2; for magic = 3/16 phi(l) = 8 (l - 2)/(l - 8)),
+// with sigma, g1, g0 = rule[0], rule[5], rule[6] of the collision coefficients.
 template <int LAT, int M, typename T>
 __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT>::Q], const T (&u)[M][Lattice<LAT>::Q],
                                                      const T (&R)[M][M + 1], const T (&xref)[M], bool linearized,
-                                                     bool srt, T (&fbar)[M][Lattice<LAT>::Q],
+                                                     const CollideCoef<M, T>& cc, T (&fbar)[M][Lattice<LAT>::Q],
                                                      double (&Rbar)[M][M + 1]) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
@@ -524,9 +535,9 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
 #pragma unroll
     for (int j = 0; j < M; ++j) L1[i][j] = (i == j ? T(2) : T(0)) - T(2) * K[i][j];
     const T l = L1[i][i];
-    const T r8 = recip(l - T(8));
-    delta[i] = srt ? T(0) : (T(8) * (l - T(2)) * r8 - l);
-    dphi[i] = srt ? T(0) : (T(-48) * r8 * r8 - T(1));   // d delta / d lambda
+    const T rd = recip(T(2) - cc.rule[5] * l);
+    delta[i] = cc.rule[0] * (T(2) * (T(2) - l) * rd - l);
+    dphi[i] = cc.rule[0] * (T(-2) * cc.rule[6] * rd * rd - T(1));   // d delta / d lambda
   }
   T neq[M][Q], ev[M][Q];
 #pragma unroll

@@ -74,7 +74,7 @@ __device__ __forceinline__ void load_consts(const Consts<T>* __restrict__ c, Nod
     }
   }
 #pragma unroll
-  for (int j = 0; j < 5; ++j) nc.cc.rule[j] = c->rule[j];
+  for (int j = 0; j < 7; ++j) nc.cc.rule[j] = c->rule[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -120,12 +120,17 @@ __global__ void k_constants(Problem p, int n_species, Consts<T>* out) {
     out->a0[t] = T(a0);
   }
   if (t == 0) {
-    const double sg = p.relax == 0 ? 1.0 : 0.0;   // Eq. (3-16) or SRT
-    out->rule[0] = T(4.0 * sg);
+    // Eq. (3-16) is the product rule with 3/16; SRT has no even correction
+    const bool srt = p.relax == 1;
+    const double sg = srt ? 0.0 : 1.0;
+    const double magic = p.relax == 2 ? p.magic : 3.0 / 16.0;
+    out->rule[0] = T(sg);
     out->rule[1] = T(0.5 * sg);
     out->rule[2] = T(-sg);
     out->rule[3] = T(1.0 - 0.5 * sg);
     out->rule[4] = T(sg - 2.0);
+    out->rule[5] = T(srt ? 0.0 : 1.0 - 4.0 * magic);
+    out->rule[6] = T(srt ? 1.0 : 8.0 * magic);
   }
 }
 
@@ -1048,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __rest
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) pull_dir<LAT, M, T, A32>(p, A, n, k, u, nc.wall, true);
-    collide_node_adjoint<LAT, M, T>(f, u, nc.R, nc.xref, p.linearized != 0, p.relax != 0, fb, Rbar);
+    collide_node_adjoint<LAT, M, T>(f, u, nc.R, nc.xref, p.linearized != 0, nc.cc, fb, Rbar);
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -1130,7 +1135,7 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   const bool wall_xlo = !px && x == 0, wall_xhi = !px && x == nx - 1;
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
-  const bool lin = p.linearized != 0, srt = p.relax != 0;
+  const bool lin = p.linearized != 0;
   double Rbar[M][M + 1];
 #pragma unroll
   for (int i = 0; i < M; ++i)
@@ -1274,10 +1279,10 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
       }
       T g[M][Q];
       if (r >= y0 && r < y1) {
-        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, srt, g, Rbar);
+        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rbar);
       } else {
         double Rhalo[M][M + 1] = {};
-        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, srt, g, Rhalo);
+        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rhalo);
       }
       if (lvl < TB) {
         enter(lvl, r, g);

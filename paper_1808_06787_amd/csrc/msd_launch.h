@@ -29,9 +29,9 @@ struct Consts {
   T da[kMaxSpecies][kMaxSpecies];
   T ea[kMaxSpecies][kMaxSpecies];
   T ga[kMaxSpecies][kMaxSpecies];
-  T rule[5];
+  T rule[7];
 };
-constexpr size_t kConstsBytes = 4096;   // >= sizeof(Consts<double>) = 2632
+constexpr size_t kConstsBytes = 4096;   // >= sizeof(Consts<double>) = 2648
 static_assert(sizeof(Consts<double>) <= kConstsBytes, "constants block too small");
 
 // One mixture of a batch, as the batched sweep sees it (device array, read

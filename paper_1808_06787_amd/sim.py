@@ -18,7 +18,7 @@ from . import _ffi as F
 LATTICES = {"D1Q3": F.D1Q3, "D2Q5": F.D2Q5, "D3Q7": F.D3Q7, "D1Q2": F.D1Q2, "D2Q4": F.D2Q4, "D3Q6": F.D3Q6}
 DIMS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3}
 PRECISIONS = {"f32": F.F32, "f64": F.F64}
-RELAX = {"paper": F.RELAX_PAPER, "srt": F.RELAX_SRT}
+RELAX = {"paper": F.RELAX_PAPER, "srt": F.RELAX_SRT, "trt": F.RELAX_TRT}
 BCS = {"periodic": F.BC_PERIODIC, "zero_flux": F.BC_ZERO_FLUX, "dirichlet": F.BC_DIRICHLET}
 TORCH_DTYPES = {F.F32: torch.float32, F.F64: torch.float64}
 
@@ -28,10 +28,13 @@ def _dptr(t: torch.Tensor) -> int:
 
 
 def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", bc=None, xi_wall=None,
-                 relax: str = "paper", c_t: float = 1.0, xi_ref=None, plane_pad: int = 0):
+                 relax: str = "paper", c_t: float = 1.0, xi_ref=None, plane_pad: int = 0,
+                 trt_magic: float = F.MAGIC_PAPER):
     """Build an msd_problem plus the host arrays it points to (kept alive by the caller).
 
-    bc: per axis (low, high) names from BCS; xi_wall: {(axis, side): (N,) values}.
+    bc: per axis (low, high) names from BCS; xi_wall: {(axis, side): (N,) values};
+    relax: "paper" (Eq. (3-16)), "srt" or "trt" (even parameter from the product
+    rule with trt_magic; "paper" is the trt_magic = 3/16 case).
     """
     d = DIMS[lattice]
     shape = tuple(int(s) for s in shape)
@@ -68,6 +71,7 @@ def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", 
         p.linearized = 1
     p.c_t = float(c_t)
     p.relax = RELAX[relax]
+    p.trt_magic = float(trt_magic)
     p.plane_pad = int(plane_pad)
     return p, keep
 
@@ -77,7 +81,7 @@ class Sim:
 
     def __init__(self, lattice: str, D, shape, precision: str = "f32", bc=None, xi_wall=None,
                  relax: str = "paper", c_t: float = 1.0, xi_ref=None, device=None, stream=None,
-                 plane_pad: int = 0):
+                 plane_pad: int = 0, trt_magic: float = F.MAGIC_PAPER):
         self.lib = F.lib()
         self.lattice = lattice
         self.shape = tuple(int(s) for s in shape)
@@ -85,7 +89,7 @@ class Sim:
         self.precision = precision
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.problem, self._keep = make_problem(lattice, D, shape, precision, bc, xi_wall, relax, c_t, xi_ref,
-                                                plane_pad)
+                                                plane_pad, trt_magic)
         self.N = self.problem.n_species
         self.m = self.N - 1
         status = C.c_int32(0)

@@ -44,9 +44,13 @@ def smooth_field(rng, N, nodes, amp=0.1):
     return out / out.sum(axis=0, keepdims=True)
 
 
-def oracle_problem(lattice, D, shape, bc=None, xi_wall=None, relax="paper", xi_ref=None, c_t=1.0):
-    return lbm.Problem(lattice, D, shape, bc=bc, xi_wall=xi_wall or {},
-                       relax=ms.RELAX_PAPER if relax == "paper" else ms.RELAX_SRT, xi_ref=xi_ref, c_t=c_t)
+RELAX_NAMES = {"paper": ms.RELAX_PAPER, "srt": ms.RELAX_SRT, "trt": ms.RELAX_TRT}
+
+
+def oracle_problem(lattice, D, shape, bc=None, xi_wall=None, relax="paper", xi_ref=None, c_t=1.0,
+                   trt_magic=ms.MAGIC_PAPER):
+    return lbm.Problem(lattice, D, shape, bc=bc, xi_wall=xi_wall or {}, relax=RELAX_NAMES[relax],
+                       magic=trt_magic, xi_ref=xi_ref, c_t=c_t)
 
 
 def oracle_run(prob, xi0, steps):
@@ -55,12 +59,13 @@ def oracle_run(prob, xi0, steps):
 
 
 def gpu_run(lattice, D, shape, precision, xi0, steps, bc=None, xi_wall=None, relax="paper", xi_ref=None,
-            c_t=1.0, launch=None, split=None):
+            c_t=1.0, launch=None, split=None, trt_magic=ms.MAGIC_PAPER):
     import torch
 
     from paper_1808_06787_amd.sim import Sim
 
-    sim = Sim(lattice, D, shape, precision, bc=bc, xi_wall=xi_wall, relax=relax, c_t=c_t, xi_ref=xi_ref)
+    sim = Sim(lattice, D, shape, precision, bc=bc, xi_wall=xi_wall, relax=relax, c_t=c_t, xi_ref=xi_ref,
+              trt_magic=trt_magic)
     if launch:
         sim.set_launch(**launch)
     sim.init(torch.from_numpy(np.ascontiguousarray(xi0)))

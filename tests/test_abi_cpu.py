@@ -39,9 +39,10 @@ def test_binding_declares_every_symbol():
 
 
 def test_struct_layouts():
-    assert C.sizeof(F.MsdProblem) == 112
+    assert C.sizeof(F.MsdProblem) == 120
     assert F.MsdProblem.c_t.offset == 64
     assert F.MsdProblem.bc.offset == 80
+    assert F.MsdProblem.trt_magic.offset == 112
     assert C.sizeof(F.MsdLaunch) == 32
     assert F.lib().msd_abi_version() == F.ABI_VERSION
 
@@ -96,6 +97,20 @@ def test_validation_codes(mutate, code):
     n, st = _ws(p)
     assert n == 0 and st == code
     assert F.lib().msd_last_error()
+
+
+def test_trt_parameter_validation():
+    """MSD_RELAX_TRT needs a finite positive product parameter; the other rules ignore it."""
+    D = np.array([[1, 0.1, 0.2], [0.1, 1, 0.3], [0.2, 0.3, 1.0]])
+    for magic, code in ((0.0, -4), (-0.1, -4), (float("nan"), -4), (float("inf"), -4), (0.25, 0), (3.0, 0)):
+        p, keep = make_problem("D2Q5", D, (16, 8), "f32", relax="trt", trt_magic=magic)
+        n, st = _ws(p)
+        assert st == code and (n > 0) == (code == 0), (magic, n, st)
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32", relax="paper", trt_magic=0.0)
+    assert _ws(p)[1] == 0
+    p, keep = make_problem("D2Q5", D, (16, 8), "f32")
+    p.relax = 3
+    assert _ws(p) == (0, -4)
 
 
 def test_diffusivity_and_composition_validation():

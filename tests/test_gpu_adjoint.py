@@ -50,7 +50,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
-@pytest.mark.parametrize("relax", ["paper", "srt"])
+@pytest.mark.parametrize("relax", ["paper", "srt", "trt"])
 def test_adjoint_matches_autograd_twin_fp64(case, relax):
     lattice, shape, N, bc = CASES[case]
     rng = np.random.default_rng(60 + case)
@@ -63,9 +63,11 @@ def test_adjoint_matches_autograd_twin_fp64(case, relax):
     xi0 = smooth_field(rng, N, shape[::-1], 0.15)
     target = smooth_field(rng, N, shape[::-1], 0.15)
     steps, every = 20, 6
-    p = oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax)
+    magic = 0.35     # TRT: away from Eq. (3-16)'s 3/16 (ignored by the other rules)
+    p = oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax, trt_magic=magic)
     ref = twin.misfit_gradients(p, xi0, target, steps)
-    got = _gpu_grads(lattice, D, shape, "f64", xi0, target, steps, every, bc=bc, xi_wall=walls, relax=relax)
+    got = _gpu_grads(lattice, D, shape, "f64", xi0, target, steps, every, bc=bc, xi_wall=walls, relax=relax,
+                     trt_magic=magic)
     _compare(ref, got, 1e-10, f"{lattice} {relax}")
 
 

@@ -29,7 +29,7 @@ def _specs(lattice, rng):
             bc = (("dirichlet", "zero_flux"),) + (("periodic", "periodic"),) * (d - 1)
             walls = {(0, 0): rand_field(rng, N, ())}
         specs.append(dict(D=rand_D(rng, N), shape=shape, bc=bc, xi_wall=walls,
-                          relax="srt" if b == 3 else "paper"))
+                          relax="srt" if b == 3 else ("trt" if b == 2 else "paper"), trt_magic=0.4))
     fields = [smooth_field(rng, sp["D"].shape[0], sp["shape"][::-1], 0.1) for sp in specs]
     return specs, fields
 
@@ -60,7 +60,8 @@ def test_batch_matches_oracle_per_mixture(lattice, precision):
     b.step(25)
     got = _read_all(b)
     for i, (sp, f) in enumerate(zip(specs, fields)):
-        p = oracle_problem(lattice, sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"])
+        p = oracle_problem(lattice, sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"],
+                           trt_magic=sp["trt_magic"])
         assert_parity(got[i], oracle_run(p, f, 25), precision, f"{lattice} mixture {i}")
     b.close()
 

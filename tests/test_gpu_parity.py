@@ -42,7 +42,7 @@ def test_periodic_and_zero_flux(lattice, N, precision):
 
 @pytest.mark.parametrize("lattice", ALL)
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("relax", ["paper", "srt"])
+@pytest.mark.parametrize("relax", ["paper", "srt", "trt"])
 def test_dirichlet_faces(lattice, precision, relax):
     rng = np.random.default_rng(77)
     N = 3
@@ -55,8 +55,9 @@ def test_dirichlet_faces(lattice, precision, relax):
             if kind == "dirichlet":
                 walls[(a, s)] = rand_field(rng, N, ())
     xi0 = rand_field(rng, N, shape[::-1])
-    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax), xi0, 40)
-    gpu = gpu_run(lattice, D, shape, precision, xi0, 40, bc=bc, xi_wall=walls, relax=relax)
+    magic = 0.11     # TRT: a product parameter away from Eq. (3-16)'s 3/16
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax, trt_magic=magic), xi0, 40)
+    gpu = gpu_run(lattice, D, shape, precision, xi0, 40, bc=bc, xi_wall=walls, relax=relax, trt_magic=magic)
     assert_parity(gpu, orc, precision, f"{lattice} dirichlet {precision} {relax}")
 
 
@@ -268,6 +269,25 @@ def test_temporally_blocked_sweep(case, tb, N, precision):
         gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls,
                       launch=dict(temporal=tb, seg_rows=seg, lds_resident=0), split=[1, 6, 16])
         assert_parity(gpu, orc, precision, f"blocked tb={tb} seg={seg} {shape} N={N} {precision}")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("magic", [0.05, 0.5, 2.0])
+def test_temporally_blocked_sweep_trt(precision, magic):
+    """The TRT rule through the blocked sweep (the collision coefficients carry the
+    product parameter): walls, ragged tiles, 6 steps per pass."""
+    shape, bc = BLOCKED_CASES[2]
+    rng = np.random.default_rng(330)
+    N = 3
+    D = rand_D(rng, N)
+    walls = {(a, s): rand_field(rng, N, ()) for a, (lo, hi) in enumerate(bc) for s, kind in enumerate((lo, hi))
+             if kind == "dirichlet"}
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 19
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls, relax="trt", trt_magic=magic), xi0, steps)
+    gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, relax="trt", trt_magic=magic,
+                  launch=dict(temporal=6, seg_rows=16, lds_resident=0))
+    assert_parity(gpu, orc, precision, f"blocked trt magic={magic} {precision}")
 
 
 def test_blocked_sweep_matches_single_step_sweep():
