@@ -100,15 +100,21 @@ struct LaunchArgs {
 
 // Temporally blocked D2Q5 sweep (k_step_blocked): workgroup width in columns
 // for m evolved species, tb steps per pass and value size `bytes`, or 0 when
-// the per-thread register window (7m values per time level plus one input row
-// of 5m) would take more than 100 VGPRs, so that the kernel keeps four or more
-// waves per SIMD without spilling (m <= 4: beyond that the collision alone
-// leaves too few waves).  The LDS exchange of the x-directions takes
-// (tb - 1) levels * 2 rows * 2 directions * m * cols values.
+// the kernel would not fit.  The sweep runs two waves per SIMD (two
+// workgroups per CU), so each lane may hold up to 256 VGPRs: the per-thread
+// register window (7m values per time level plus the input rows) and the
+// collision's temporaries.  The largest tb that stays within that in every
+// instantiation (periodic and walled, single and batched) was read off the
+// compiled kernels: FP32 m = 1, 2: 6, m = 3: 5, m = 4: 3; FP64 m = 1: 6,
+// m = 2: 3; FP64 m >= 3: none.  The LDS exchange of the x-directions takes
+// (tb - 1) levels * 2 rows * 2 directions * m * cols values (<= 64 KiB here).
 constexpr int kBlockedCols = 256;
 constexpr int kMaxStepsPerPass = 6;
+constexpr int blocked_max_tb(int m, int bytes) {
+  return bytes == 4 ? (m <= 2 ? 6 : m == 3 ? 5 : m == 4 ? 3 : 0) : (m == 1 ? 6 : m == 2 ? 3 : 0);
+}
 constexpr int blocked_cols(int m, int tb, int bytes) {
-  return (m <= 4 && tb >= 2 && tb <= kMaxStepsPerPass && (7 * m * tb + 5 * m) * bytes / 4 <= 100 &&
+  return (tb >= 2 && tb <= kMaxStepsPerPass && tb <= blocked_max_tb(m, bytes) &&
           (tb - 1) * 2 * 2 * m * kBlockedCols * bytes <= 64 * 1024)
              ? kBlockedCols
              : 0;

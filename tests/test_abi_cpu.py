@@ -191,11 +191,11 @@ def test_blocked_plan_limits_without_device():
     cases = [
         ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f32", (32768, 32768), dict(seg_rows=16), 1),
-        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 4),
-        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 2),
+        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 5),
+        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 3),
         ("D2Q5", 6, "f32", (4096, 1024), dict(seg_rows=16), 1),
         ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 6),
-        ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16), 2),
+        ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16), 3),
         ("D2Q5", 4, "f64", (4096, 1024), dict(seg_rows=16), 1),
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=3), 3),
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=0), 1),

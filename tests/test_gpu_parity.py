@@ -314,9 +314,9 @@ def test_steps_per_pass_plan():
         (3, "f32", (4096, 512), {}, 6),
         (3, "f32", (4096, 4096), dict(temporal=4, seg_rows=0), 4),
         (2, "f64", (2048, 512), {}, 6),
-        (4, "f32", (2048, 1024), {}, 4),
-        (5, "f32", (2048, 1024), {}, 2),
-        (3, "f64", (2048, 1024), {}, 2),
+        (4, "f32", (2048, 1024), {}, 5),
+        (5, "f32", (2048, 1024), {}, 3),
+        (3, "f64", (2048, 1024), {}, 3),
         (4, "f64", (2048, 1024), {}, 1),
         (3, "f32", (2048, 1024), dict(temporal=3), 3),
         (3, "f32", (2048, 1024), dict(temporal=0), 1),
