@@ -133,7 +133,8 @@ __device__ __forceinline__ T recip(T x) {
 // ---------------------------------------------------------------------------
 // Small dense inverse of A = I + (a/2) B, times `scale`.  The eigenvalues of B are real and
 // positive for compositions on the simplex, so A is never singular; its
-// off-diagonal entries can exceed the diagonal, hence the pivoting for m >= 4.
+// off-diagonal entries can exceed the diagonal, hence the pivoting for m >= 5
+// (closed forms by cofactors for m <= 4).
 // ---------------------------------------------------------------------------
 template <int M, typename T>
 __device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M], T scale = T(1)) {
@@ -159,6 +160,34 @@ __device__ __forceinline__ void invert_small(T (&A)[M][M], T (&K)[M][M], T scale
     K[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * inv;
     K[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * inv;
     K[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * inv;
+  } else if constexpr (M == 4) {
+    // Cofactors from the 2 x 2 minors of rows 0-1 (s) and rows 2-3 (c): the
+    // Laplace expansion by complementary minors gives det = sum +-s c, and
+    // each adjugate entry is three products of an entry with a minor.
+    const T(&a)[4][4] = A;
+    const T s0 = a[0][0] * a[1][1] - a[1][0] * a[0][1], s1 = a[0][0] * a[1][2] - a[1][0] * a[0][2];
+    const T s2 = a[0][0] * a[1][3] - a[1][0] * a[0][3], s3 = a[0][1] * a[1][2] - a[1][1] * a[0][2];
+    const T s4 = a[0][1] * a[1][3] - a[1][1] * a[0][3], s5 = a[0][2] * a[1][3] - a[1][2] * a[0][3];
+    const T c5 = a[2][2] * a[3][3] - a[3][2] * a[2][3], c4 = a[2][1] * a[3][3] - a[3][1] * a[2][3];
+    const T c3 = a[2][1] * a[3][2] - a[3][1] * a[2][2], c2 = a[2][0] * a[3][3] - a[3][0] * a[2][3];
+    const T c1 = a[2][0] * a[3][2] - a[3][0] * a[2][2], c0 = a[2][0] * a[3][1] - a[3][0] * a[2][1];
+    const T inv = scale * recip(s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0);
+    K[0][0] = (a[1][1] * c5 - a[1][2] * c4 + a[1][3] * c3) * inv;
+    K[0][1] = (a[0][2] * c4 - a[0][1] * c5 - a[0][3] * c3) * inv;
+    K[0][2] = (a[3][1] * s5 - a[3][2] * s4 + a[3][3] * s3) * inv;
+    K[0][3] = (a[2][2] * s4 - a[2][1] * s5 - a[2][3] * s3) * inv;
+    K[1][0] = (a[1][2] * c2 - a[1][0] * c5 - a[1][3] * c1) * inv;
+    K[1][1] = (a[0][0] * c5 - a[0][2] * c2 + a[0][3] * c1) * inv;
+    K[1][2] = (a[3][2] * s2 - a[3][0] * s5 - a[3][3] * s1) * inv;
+    K[1][3] = (a[2][0] * s5 - a[2][2] * s2 + a[2][3] * s1) * inv;
+    K[2][0] = (a[1][0] * c4 - a[1][1] * c2 + a[1][3] * c0) * inv;
+    K[2][1] = (a[0][1] * c2 - a[0][0] * c4 - a[0][3] * c0) * inv;
+    K[2][2] = (a[3][0] * s4 - a[3][1] * s2 + a[3][3] * s0) * inv;
+    K[2][3] = (a[2][1] * s2 - a[2][0] * s4 - a[2][3] * s0) * inv;
+    K[3][0] = (a[1][1] * c1 - a[1][0] * c3 - a[1][2] * c0) * inv;
+    K[3][1] = (a[0][0] * c3 - a[0][1] * c1 + a[0][2] * c0) * inv;
+    K[3][2] = (a[3][1] * s1 - a[3][0] * s3 - a[3][2] * s0) * inv;
+    K[3][3] = (a[2][0] * s3 - a[2][1] * s1 + a[2][2] * s0) * inv;
   } else {
     // Gauss-Jordan on [A | I] with partial pivoting; row swaps are done with
     // selects so that every index stays compile-time (registers only).
