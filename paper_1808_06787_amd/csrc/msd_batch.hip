@@ -580,7 +580,7 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
           }
     if (b->lattice == MSD_D2Q5)
       for (int tb : {2, 3, 4, 5, 6})
-        for (int seg : {8, 16, 32})
+        for (int seg : {8, 16, 32, 64, 128})
           for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED}) {
             msd_schedule c{};
             c.block_x = 64; c.block_y = 4; c.mode = MSD_BATCH_PER_CLASS; c.order = order;
