@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Velocity sets and weights follow Sec. 3.1, Eqs. (3-4) (D1Q2), (3-5) (D1Q3),
-(3-6) (D2Q4), (3-7) (D2Q5), (3-9) (D3Q6) and (3-10) (D3Q7), in the paper's
-direction order.  Velocities are in lattice units
+(3-6) (D2Q4), (3-7) (D2Q5), (3-8) (D2Q9), (3-9) (D3Q6), (3-10) (D3Q7) and
+(3-11) (D3Q15), in the paper's direction order.  Velocities are in lattice units
 (c = dx/dt = 1; the scale invariance M0^-1 Lambda M0 = M^-1 Lambda M after
 Eq. (3-14) makes the C_d factor irrelevant).
 
@@ -29,7 +29,7 @@ class Lattice:
     c: np.ndarray          # (q, 3) integer velocities (unused axes are 0)
     w: np.ndarray          # (q,) weights omega_k
     M0: np.ndarray         # (q, q) moment matrix
-    row_order: tuple       # moment order of each row of M0: 0, 1 or 2
+    row_order: tuple       # moment order of each row of M0: 0 .. 4
 
     @property
     def q(self) -> int:
@@ -170,7 +170,65 @@ D3Q6 = Lattice(
     row_order=(0, 1, 1, 1, 2, 2),
 )
 
-LATTICES = {"D1Q2": D1Q2, "D1Q3": D1Q3, "D2Q4": D2Q4, "D2Q5": D2Q5, "D3Q6": D3Q6, "D3Q7": D3Q7}
+def _poly_rows(c, polys):
+    """Moment matrix rows from polynomials of the velocity components."""
+    return np.array([[float(pfun(*ck)) for ck in c] for pfun in polys])
+
+
+# Eq. (3-8): D2Q9, w = (4/9, 1/9 x4, 1/36 x4); directions (0,0), (1,0), (0,1),
+# (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1).  The paper gives no moment
+# matrix for it: rows are polynomials of definite parity (1; c_x, c_y;
+# c^2, c_x^2 - c_y^2, c_x c_y; c^2 c_x, c^2 c_y; c^4).
+_c2q9 = _vel([(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)])
+D2Q9 = Lattice(
+    name="D2Q9",
+    d=2,
+    c=_c2q9,
+    w=np.array([4.0 / 9.0] + [1.0 / 9.0] * 4 + [1.0 / 36.0] * 4),
+    M0=_poly_rows(_c2q9[:, :2], [
+        lambda x, y: 1,
+        lambda x, y: x, lambda x, y: y,
+        lambda x, y: x * x + y * y, lambda x, y: x * x - y * y, lambda x, y: x * y,
+        lambda x, y: (x * x + y * y) * x, lambda x, y: (x * x + y * y) * y,
+        lambda x, y: (x * x + y * y) ** 2,
+    ]),
+    row_order=(0, 1, 1, 2, 2, 2, 3, 3, 4),
+)
+
+# Eq. (3-11): D3Q15, w = (2/9, 1/9 x6, 1/72 x8), in the paper's direction order.
+# Rows: 1; c_x, c_y, c_z; c^2, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z,
+# c_z c_x; c^2 c_x, c^2 c_y, c^2 c_z, c_x c_y c_z; c^4.
+_c3q15 = _vel([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+               (1, 1, 1), (1, -1, -1), (1, -1, 1), (1, 1, -1), (-1, 1, 1), (-1, -1, -1), (-1, -1, 1), (-1, 1, -1)])
+D3Q15 = Lattice(
+    name="D3Q15",
+    d=3,
+    c=_c3q15,
+    w=np.array([2.0 / 9.0] + [1.0 / 9.0] * 6 + [1.0 / 72.0] * 8),
+    M0=_poly_rows(_c3q15, [
+        lambda x, y, z: 1,
+        lambda x, y, z: x, lambda x, y, z: y, lambda x, y, z: z,
+        lambda x, y, z: x * x + y * y + z * z, lambda x, y, z: 2 * x * x - y * y - z * z,
+        lambda x, y, z: y * y - z * z, lambda x, y, z: x * y, lambda x, y, z: y * z, lambda x, y, z: z * x,
+        lambda x, y, z: (x * x + y * y + z * z) * x, lambda x, y, z: (x * x + y * y + z * z) * y,
+        lambda x, y, z: (x * x + y * y + z * z) * z, lambda x, y, z: x * y * z,
+        lambda x, y, z: (x * x + y * y + z * z) ** 2,
+    ]),
+    row_order=(0, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 4),
+)
+
+LATTICES = {"D1Q2": D1Q2, "D1Q3": D1Q3, "D2Q4": D2Q4, "D2Q5": D2Q5, "D3Q6": D3Q6, "D3Q7": D3Q7,
+            "D2Q9": D2Q9, "D3Q15": D3Q15}
+
+
+def relaxation_family(order: int) -> int:
+    """Which relaxation matrix a moment row of this order takes: 0 the conserved
+    row (its m - m^eq is zero), 1 (Lambda_1) the odd orders, 2 (Lambda_2) the even
+    ones.  Eq. (3-14) assigns Lambda_1 to the first-order and Lambda_2 to the
+    second-order moments of D2Q5; for lattices with higher-order moments the odd
+    ones relax with Lambda_1 and the even ones with Lambda_2, the two-relaxation-
+    time grouping the paper names after Eq. (3-14)."""
+    return 0 if order == 0 else (1 if order % 2 else 2)
 
 
 def get(name: str) -> Lattice:

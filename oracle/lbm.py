@@ -158,7 +158,7 @@ def collide(prob: Problem, f: np.ndarray) -> np.ndarray:
 
     with the diagonal relaxation Lambda^{ij} = diag(lambda_0^ij, lambda_1^ij, ..., lambda_2^ij, ...)
     of Eq. (3-14b): every first-order row of M0 uses Lambda_1, every second-order row
-    Lambda_2.  The zeroth (conserved) moment of f - f^eq is zero exactly, since
+    Lambda_2 (higher orders by parity, lattice.relaxation_family).  The zeroth (conserved) moment of f - f^eq is zero exactly, since
     m_0 = sum_k f_k = xi (Eq. (3-15)) = m_0^eq (Eq. (m0A)); it is set to that exact value
     rather than to its floating-point residual, which would otherwise feed a systematic
     rounding drift of the species totals into every step.
@@ -171,14 +171,14 @@ def collide(prob: Problem, f: np.ndarray) -> np.ndarray:
         L0 = L1
     else:
         L0 = np.full_like(L1, prob.lambda0)
-    per_order = {0: L0, 1: L1, 2: L2}
+    family = (L0, L1, L2)
 
     feq = lat.w[(None, slice(None)) + (None,) * lat.d] * xi_e[:, None]
     dm = np.einsum("rk,ik...->ir...", lat.M0, f - feq)       # m - m^eq (Eq. (3-11))
     dm[:, 0] = 0.0                                           # conserved moment
     relaxed = np.empty_like(dm)
     for r in range(lat.q):
-        relaxed[:, r] = np.einsum("...ij,j...->i...", per_order[lat.row_order[r]], dm[:, r])
+        relaxed[:, r] = np.einsum("...ij,j...->i...", family[_lat.relaxation_family(lat.row_order[r])], dm[:, r])
     return f - np.einsum("kr,ir...->ik...", np.linalg.inv(lat.M0), relaxed)
 
 
@@ -198,28 +198,31 @@ def stream(prob: Problem, fpost: np.ndarray) -> np.ndarray:
     for k in range(lat.q):
         ck = lat.c[k]
         axes = [a for a in range(lat.d) if ck[a] != 0]
-        if not axes:
-            out[:, k] = fpost[:, k]
-            continue
-        (a,) = axes   # every direction of these lattices moves along one axis only
-        ax = 1 + _array_axis(prob, a)   # axis in (m, *nodes) arrays
-        out[:, k] = np.roll(fpost[:, k], shift=int(ck[a]), axis=ax)
-        side = 0 if ck[a] > 0 else 1        # face whose boundary nodes miss their source
-        kind = prob.bc[a][side]
-        if kind == PERIODIC:
-            continue
-        idx = [slice(None)] * out[:, k].ndim
-        idx[ax] = 0 if side == 0 else prob.shape[a] - 1
-        idx = tuple(idx)
-        back = fpost[:, opp[k]][idx]
-        if kind == ZERO_FLUX:
-            out[:, k][idx] = back
-        elif kind == DIRICHLET:
-            xi_b = np.asarray(prob.xi_wall[(a, side)], dtype=np.float64)[: prob.m]
-            shape = (prob.m,) + (1,) * (back.ndim - 1)
-            out[:, k][idx] = -back + 2.0 * lat.w[opp[k]] * xi_b.reshape(shape)
-        else:
-            raise ValueError(f"unknown boundary kind {kind!r}")
+        moved = fpost[:, k]
+        for a in axes:
+            moved = np.roll(moved, shift=int(ck[a]), axis=1 + _array_axis(prob, a))
+        out[:, k] = moved
+        # Boundary nodes whose source x - c_k lies beyond a wall take the face
+        # rule.  A diagonal direction can leave through two or three faces at an
+        # edge or corner; there the face of the lowest axis decides (applied last).
+        for a in reversed(axes):
+            side = 0 if ck[a] > 0 else 1        # face whose boundary nodes miss their source
+            kind = prob.bc[a][side]
+            if kind == PERIODIC:
+                continue
+            ax = 1 + _array_axis(prob, a)       # axis in (m, *nodes) arrays
+            idx = [slice(None)] * out[:, k].ndim
+            idx[ax] = 0 if side == 0 else prob.shape[a] - 1
+            idx = tuple(idx)
+            back = fpost[:, opp[k]][idx]
+            if kind == ZERO_FLUX:
+                out[:, k][idx] = back
+            elif kind == DIRICHLET:
+                xi_b = np.asarray(prob.xi_wall[(a, side)], dtype=np.float64)[: prob.m]
+                shape = (prob.m,) + (1,) * (back.ndim - 1)
+                out[:, k][idx] = -back + 2.0 * lat.w[opp[k]] * xi_b.reshape(shape)
+            else:
+                raise ValueError(f"unknown boundary kind {kind!r}")
     return out
 
 

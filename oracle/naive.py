@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import lattice as _lat
 from . import lbm as _lbm
 from . import ms as _ms
 
@@ -102,12 +103,13 @@ def step(prob, f):
         xi_all = xi + [1.0 - sum(xi)]
         _, _, L1, L2 = _node_matrices(prob, xi_all)
         L0 = L1 if prob.relax == _ms.RELAX_SRT else [[prob.lambda0] * m for _ in range(m)]
-        per = {0: L0, 1: L1, 2: L2}
+        fam = (L0, L1, L2)
         # Eq. (3-2): f+ = f - M0^-1 Lambda M0 (f - f^eq); the conserved moment of
         # f - f^eq is exactly zero (Eq. (3-15)).
         neq = [[fn[i][k] - lat.w[k] * xi[i] for k in range(q)] for i in range(m)]
         dm = [[0.0 if r == 0 else sum(M0[r][k] * neq[i][k] for k in range(q)) for r in range(q)] for i in range(m)]
-        rel = [[sum(per[order[r]][i][j] * dm[j][r] for j in range(m)) for r in range(q)] for i in range(m)]
+        rel = [[sum(fam[_lat.relaxation_family(order[r])][i][j] * dm[j][r] for j in range(m)) for r in range(q)]
+               for i in range(m)]
         fpost[node] = [[fn[i][k] - sum(M0inv[k][r] * rel[i][r] for r in range(q)) for k in range(q)]
                        for i in range(m)]
     opp = lat.opposite

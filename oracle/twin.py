@@ -94,13 +94,13 @@ class Twin:
                 l2 = 8.0 * (diag - 2.0) / (diag - 8.0)
             L2 = L1 - torch.diag_embed(diag) + torch.diag_embed(l2)
             L0 = torch.full_like(L1, p.lambda0)
-        per = {0: L0, 1: L1, 2: L2}
+        fam = (L0, L1, L2)
         feq = self.w.reshape((1, -1) + (1,) * d) * xi_e[:, None]
         dm = torch.einsum("rk,ik...->ir...", self.M0, f - feq)
         mask = torch.ones(self.lat.q, dtype=torch.float64)
         mask[0] = 0.0
         dm = dm * mask.reshape((1, -1) + (1,) * d)                 # conserved moment exactly zero
-        rel = torch.stack([torch.einsum("...ij,j...->i...", per[self.lat.row_order[r]], dm[:, r])
+        rel = torch.stack([torch.einsum("...ij,j...->i...", fam[_lat.relaxation_family(self.lat.row_order[r])], dm[:, r])
                            for r in range(self.lat.q)], dim=1)
         return f - torch.einsum("kr,ir...->ik...", self.M0inv, rel)
 
@@ -115,26 +115,29 @@ class Twin:
             if not axes:
                 outs.append(fpost[:, k])
                 continue
-            (a,) = axes
-            ax = 1 + (lat.d - 1 - a)
-            rolled = torch.roll(fpost[:, k], shifts=int(ck[a]), dims=ax)
-            side = 0 if ck[a] > 0 else 1
-            kind = p.bc[a][side]
-            if kind == _lbm.PERIODIC:
-                outs.append(rolled)
-                continue
-            n = p.shape[a]
-            pos = 0 if side == 0 else n - 1
-            sel = torch.zeros(n, dtype=torch.float64)
-            sel[pos] = 1.0
-            sel = sel.reshape((1,) + tuple(n if i == ax else 1 for i in range(1, rolled.ndim)))
-            back = fpost[:, opp[k]]
-            if kind == _lbm.ZERO_FLUX:
-                face = back
-            else:
-                xb = torch.tensor(np.asarray(p.xi_wall[(a, side)], dtype=np.float64)[: p.m])
-                face = -back + 2.0 * lat.w[opp[k]] * xb.reshape((-1,) + (1,) * (rolled.ndim - 1))
-            outs.append(rolled * (1.0 - sel) + face * sel)
+            out = fpost[:, k]
+            for a in axes:
+                out = torch.roll(out, shifts=int(ck[a]), dims=1 + (lat.d - 1 - a))
+            # face rules, the lowest axis last (it decides at edges and corners)
+            for a in reversed(axes):
+                ax = 1 + (lat.d - 1 - a)
+                side = 0 if ck[a] > 0 else 1
+                kind = p.bc[a][side]
+                if kind == _lbm.PERIODIC:
+                    continue
+                n = p.shape[a]
+                pos = 0 if side == 0 else n - 1
+                sel = torch.zeros(n, dtype=torch.float64)
+                sel[pos] = 1.0
+                sel = sel.reshape((1,) + tuple(n if i == ax else 1 for i in range(1, out.ndim)))
+                back = fpost[:, opp[k]]
+                if kind == _lbm.ZERO_FLUX:
+                    face = back
+                else:
+                    xb = torch.tensor(np.asarray(p.xi_wall[(a, side)], dtype=np.float64)[: p.m])
+                    face = -back + 2.0 * lat.w[opp[k]] * xb.reshape((-1,) + (1,) * (out.ndim - 1))
+                out = out * (1.0 - sel) + face * sel
+            outs.append(out)
         return torch.stack(outs, dim=1)
 
     def run(self, xi0: torch.Tensor, D: torch.Tensor, steps: int) -> torch.Tensor:

@@ -145,7 +145,7 @@ def test_lambda1_roundtrip_eq_3_26():
     """Eq. (3-26) as printed maps the oracle's Lambda_1 back to D~ (self-consistency only;
     the physics of the map is pinned by the continuum-decay tests)."""
     rng = np.random.default_rng(15)
-    for name in ("D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"):
+    for name in ("D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7", "D2Q9", "D3Q15"):
         cs2 = lat.get(name).cs2
         D = _rand_D(rng, 4, 0.02, 0.3)
         Dt = ms.fick_matrix(ms.ms_B(_rand_xi(rng, 4, 30), D))
@@ -240,17 +240,20 @@ def test_d2q5_streaming_operator_in_moment_space():
     np.testing.assert_allclose(cy, expect_y, atol=1e-14)
 
 
-@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7", "D2Q9", "D3Q15"])
 def test_moment_rows_have_definite_parity(name):
-    """Every M0 row is even or odd under k -> kbar, odd rows are exactly the first-order
-    ones, and M0 is invertible (needed for Eq. (3-13b))."""
+    """Every M0 row is even or odd under k -> kbar, odd rows are exactly those of odd
+    order (first order on the lattices of Eq. (3-14)'s kind, also third order on D2Q9
+    and D3Q15), which relax with Lambda_1, and M0 is invertible (needed for Eq. (3-13b))."""
     L = lat.get(name)
     opp = L.opposite
     for r, order in enumerate(L.row_order):
         row = L.M0[r]
-        if order == 1:
+        if order % 2:
             np.testing.assert_array_equal(row[opp], -row)
+            assert lat.relaxation_family(order) == 1
         else:
             np.testing.assert_array_equal(row[opp], row)
+            assert lat.relaxation_family(order) == (0 if order == 0 else 2)
     assert abs(np.linalg.det(L.M0)) > 1e-6
     np.testing.assert_array_equal(L.M0[0], np.ones(L.q))

@@ -201,7 +201,7 @@ def test_loschmidt_tube_extremum_time():
     np.testing.assert_allclose(means[:2], [g["loschmidt_xi1_eq"], g["loschmidt_xi2_eq"]], atol=1e-12)
 
 
-@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7", "D2Q9", "D3Q15"])
 def test_binary_fourier_decay_matches_continuum(name):
     """Eq. (2-13) with constant D (Remark I): a mode cos(k x) decays as exp(-D k^2 t)."""
     L = lat.get(name)
@@ -224,7 +224,7 @@ def test_binary_fourier_decay_matches_continuum(name):
     del L
 
 
-@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"])
+@pytest.mark.parametrize("name", ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7", "D2Q9", "D3Q15"])
 @pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT, ms.RELAX_TRT])
 def test_linearised_multicomponent_decay_matches_eigen_decomposition(name, relax):
     """Linearised Eq. (2-13) (D~ frozen at a reference composition): a mode with

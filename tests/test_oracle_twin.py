@@ -6,7 +6,7 @@ import torch
 
 from oracle import lbm, ms, twin
 
-LATS = ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7"]
+LATS = ["D1Q2", "D1Q3", "D2Q4", "D2Q5", "D3Q6", "D3Q7", "D2Q9", "D3Q15"]
 
 
 def _rand_D(rng, n, lo=0.03, hi=0.3):
