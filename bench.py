@@ -37,7 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-Q = {"D1Q3": 3, "D2Q5": 5, "D3Q7": 7, "D1Q2": 2, "D2Q4": 4, "D3Q6": 6}
+Q = {"D1Q3": 3, "D2Q5": 5, "D3Q7": 7, "D1Q2": 2, "D2Q4": 4, "D3Q6": 6, "D2Q9": 9, "D3Q15": 15}
 KERNEL_SOURCES = ["paper_1808_06787_amd/csrc/msd_device.h", "paper_1808_06787_amd/csrc/msd_kernels.h"]
 
 
@@ -83,8 +83,8 @@ def load_valu_time(workload: str):
         return None
 
 
-def _rest_free(w, lattice: str):
-    """The same inputs on the lattice without a rest direction of equal dimension."""
+def _on_lattice(w, lattice: str):
+    """The same inputs on another lattice of equal dimension."""
     import dataclasses
 
     return dataclasses.replace(w, name=w.name.replace(w.lattice.lower(), lattice.lower()), lattice=lattice)
@@ -460,12 +460,16 @@ def main():
         print(f"# {w3.name}: {m3:.0f} MLUPS, {a3:.0f} GB/s ({100 * a3 / HBM_PEAK_GBS:.1f}%)",
               file=sys.stderr, flush=True)
         del w3
-        # the lattices without a rest direction (Eqs. (3-6), (3-9)), one step per pass
-        for name, make in (("ternary_2d_d2q4_4096^2_f32", lambda: _rest_free(make_workload("ternary_2d"), "D2Q4")),
+        # the lattices without a rest direction (Eqs. (3-6), (3-9)) and with diagonal
+        # directions (Eqs. (3-8), (3-11)), one step per pass
+        for name, make in (("ternary_2d_d2q4_4096^2_f32", lambda: _on_lattice(make_workload("ternary_2d"), "D2Q4")),
                            ("quaternary_3d_d3q6_512^3_f32",
-                            lambda: _rest_free(make_workload("quaternary_3d"), "D3Q6"))):
+                            lambda: _on_lattice(make_workload("quaternary_3d"), "D3Q6")),
+                           ("ternary_2d_d2q9_4096^2_f32", lambda: _on_lattice(make_workload("ternary_2d"), "D2Q9")),
+                           ("quaternary_3d_d3q15_512^3_f32",
+                            lambda: _on_lattice(make_workload("quaternary_3d"), "D3Q15"))):
             wr = make()
-            n_steps = 500 if wr.lattice == "D2Q4" else 100
+            n_steps = 500 if wr.lattice.startswith("D2") else 100
             sr, simr = time_sweep(wr, n_steps, 5)
             rr = sweep_record(wr, sr, n_steps, simr.steps_per_pass())
             simr.close()

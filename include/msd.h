@@ -44,8 +44,15 @@ extern "C" {
 #define MSD_MAX_SPECIES 8
 
 /* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10),
- * and the lattices without a rest direction, Eqs. (3-4), (3-6), (3-9). */
-enum msd_lattice { MSD_D1Q3 = 1, MSD_D2Q5 = 2, MSD_D3Q7 = 3, MSD_D1Q2 = 4, MSD_D2Q4 = 5, MSD_D3Q6 = 6 };
+ * the lattices without a rest direction, Eqs. (3-4), (3-6), (3-9), and the
+ * lattices with diagonal directions, Eqs. (3-8) (D2Q9) and (3-11) (D3Q15).  On
+ * the last two the odd moments relax with lambda_1 and the even ones with
+ * lambda_2; a diagonal direction that leaves the box through an edge or corner
+ * takes the rule of the wall face of the lowest axis it crosses (x, then y,
+ * then z; periodic faces only wrap). */
+enum msd_lattice {
+  MSD_D1Q3 = 1, MSD_D2Q5 = 2, MSD_D3Q7 = 3, MSD_D1Q2 = 4, MSD_D2Q4 = 5, MSD_D3Q6 = 6, MSD_D2Q9 = 7, MSD_D3Q15 = 8
+};
 
 /* Storage and arithmetic precision of the sweep (bytes per value). */
 enum msd_precision { MSD_F32 = 4, MSD_F64 = 8 };

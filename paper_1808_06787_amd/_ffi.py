@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libmsd.so")
 ABI_VERSION = 2
 MAX_SPECIES = 8
 
-D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6 = 1, 2, 3, 4, 5, 6
+D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6, D2Q9, D3Q15 = 1, 2, 3, 4, 5, 6, 7, 8
 F32, F64 = 4, 8
 RELAX_PAPER, RELAX_SRT, RELAX_TRT = 0, 1, 2
 MAGIC_PAPER = 3.0 / 16.0

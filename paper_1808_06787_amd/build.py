@@ -27,6 +27,8 @@ SOURCES = [
     "msd_lat_d1q2.hip",
     "msd_lat_d2q4.hip",
     "msd_lat_d3q6.hip",
+    "msd_lat_d2q9.hip",
+    "msd_lat_d3q15.hip",
 ]
 ARCH = "gfx950"
 

@@ -87,7 +87,7 @@ void cache_store(const char* path, const std::string& key, int k, const int64_t*
 int validate(const msd_problem* p) {
   if (!p) return fail(MSD_EINVAL, "problem is NULL");
   if (p->abi != MSD_ABI_VERSION) return fail(MSD_EABI, "problem.abi = %d, library ABI = %d", p->abi, MSD_ABI_VERSION);
-  if (p->lattice < MSD_D1Q3 || p->lattice > MSD_D3Q6)
+  if (p->lattice < MSD_D1Q3 || p->lattice > MSD_D3Q15)
     return fail(MSD_EINVAL, "unknown lattice %d", p->lattice);
   if (p->n_species < 2 || p->n_species > MSD_MAX_SPECIES)
     return fail(MSD_EINVAL, "n_species = %d outside [2, %d]", p->n_species, MSD_MAX_SPECIES);
@@ -181,6 +181,8 @@ hipError_t dispatch(Op op, const LaunchArgs& a) {
     case MSD_D1Q2: return msd::dispatch<4>(op, a);
     case MSD_D2Q4: return msd::dispatch<5>(op, a);
     case MSD_D3Q6: return msd::dispatch<6>(op, a);
+    case MSD_D2Q9: return msd::dispatch<7>(op, a);
+    case MSD_D3Q15: return msd::dispatch<8>(op, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -222,7 +224,7 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   std::memset(l, 0, sizeof(*l));
   l->block_x = (int)std::min<int64_t>(256, (p->nx + 63) / 64 * 64);
   l->block_y = std::max(1, (int)std::min<int64_t>(256 / l->block_x, p->ny));
-  l->xcd_remap = (p->lattice == MSD_D3Q7 || p->lattice == MSD_D3Q6) ? 1 : 0;
+  l->xcd_remap = lattice_d(p->lattice) == 3 ? 1 : 0;
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
@@ -906,6 +908,7 @@ int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t st
       for (int vec : {0, 1, 4})
         for (int xcd : {0, 1})
           for (int nt : {0, 7}) {
+            if (vec > 0 && lattice_q(s->prob.lattice) > 2 * lattice_d(s->prob.lattice) + 1) continue;  // no vector kernel
             msd_launch l = base;
             l.block_x = b[0]; l.block_y = b[1]; l.vec = vec; l.xcd_remap = xcd; l.nontemporal = nt; l.temporal = 0;
             cand.push_back(l);

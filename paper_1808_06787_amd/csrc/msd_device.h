@@ -32,9 +32,15 @@ constexpr int kMaxSpecies = 8;
 constexpr int BC_PERIODIC = 0, BC_ZERO_FLUX = 1, BC_DIRICHLET = 2;
 
 // ---------------------------------------------------------------------------
-// Lattices (Sec. 3.1).  Direction k moves along axis(k) by sgn(k) (0 for rest).
+// Lattices (Sec. 3.1).  c(k, a) is component a of direction k.  On the
+// lattices without diagonal directions (diag = false) direction k moves along
+// axis(k) by sgn(k) (axis -1 for rest), which the row-marching kernels use.
 // ---------------------------------------------------------------------------
 template <int LAT> struct Lattice;
+
+#define MSD_AXIAL_COMPONENTS                                                                   \
+  static constexpr bool diag = false;                                                           \
+  __host__ __device__ static constexpr int c(int k, int a) { return axis(k) == a ? sgn(k) : 0; }
 
 // Eq. (3-5): c = (0, 1, -1), w = (2/3, 1/6, 1/6).
 template <> struct Lattice<1> {
@@ -44,6 +50,7 @@ template <> struct Lattice<1> {
   __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : 3 - k; }
   __host__ __device__ static constexpr double w(int k) { return k == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
   static constexpr double cs2 = 1.0 / 3.0;
+  MSD_AXIAL_COMPONENTS
 };
 
 // Eq. (3-7): directions (0,0), (1,0), (0,1), (-1,0), (0,-1); w = (1/3, 1/6 x4).
@@ -54,6 +61,7 @@ template <> struct Lattice<2> {
   __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : (k <= 2 ? k + 2 : k - 2); }
   __host__ __device__ static constexpr double w(int k) { return k == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
   static constexpr double cs2 = 1.0 / 3.0;
+  MSD_AXIAL_COMPONENTS
 };
 
 // Eq. (3-10): directions 0, +x, -x, +y, -y, +z, -z; w = (1/4, 1/8 x6).
@@ -66,6 +74,7 @@ template <> struct Lattice<3> {
   __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : ((k & 1) ? k + 1 : k - 1); }
   __host__ __device__ static constexpr double w(int k) { return k == 0 ? 0.25 : 0.125; }
   static constexpr double cs2 = 0.25;
+  MSD_AXIAL_COMPONENTS
 };
 
 // Lattices without a rest direction (q = 2d, equal weights 1/(2d)); their
@@ -79,6 +88,7 @@ template <> struct Lattice<4> {
   __host__ __device__ static constexpr int opp(int k) { return 1 - k; }
   __host__ __device__ static constexpr double w(int) { return 0.5; }
   static constexpr double cs2 = 1.0;
+  MSD_AXIAL_COMPONENTS
 };
 
 // Eq. (3-6): directions (1,0), (0,1), (-1,0), (0,-1); w = 1/4.
@@ -89,6 +99,7 @@ template <> struct Lattice<5> {
   __host__ __device__ static constexpr int opp(int k) { return (k + 2) & 3; }
   __host__ __device__ static constexpr double w(int) { return 0.25; }
   static constexpr double cs2 = 0.5;
+  MSD_AXIAL_COMPONENTS
 };
 
 // Eq. (3-9): directions +x, -x, +y, -y, +z, -z; w = 1/6.
@@ -99,7 +110,85 @@ template <> struct Lattice<6> {
   __host__ __device__ static constexpr int opp(int k) { return k ^ 1; }
   __host__ __device__ static constexpr double w(int) { return 1.0 / 6.0; }
   static constexpr double cs2 = 1.0 / 3.0;
+  MSD_AXIAL_COMPONENTS
 };
+
+#undef MSD_AXIAL_COMPONENTS
+
+// Component of a diagonal direction from a bit mask: bit k set -> +1, else -1.
+__host__ __device__ constexpr int sign_bit(unsigned mask, int k) { return ((mask >> k) & 1u) ? 1 : -1; }
+
+// Eq. (3-8): directions (0,0), (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1),
+// (-1,-1), (1,-1); w = (4/9, 1/9 x4, 1/36 x4); second moment 1/3.
+template <> struct Lattice<7> {
+  static constexpr int D = 2, Q = 9;
+  static constexpr bool diag = true;
+  __host__ __device__ static constexpr int c(int k, int a) {
+    return (k == 0 || a > 1) ? 0
+                             : (k <= 4 ? (((k - 1) & 1) == a ? (k <= 2 ? 1 : -1) : 0)
+                                       : sign_bit(a == 0 ? 0x120u : 0x060u, k));   // +x: 5, 8; +y: 5, 6
+  }
+  __host__ __device__ static constexpr int opp(int k) {
+    return k == 0 ? 0 : (k <= 4 ? (k <= 2 ? k + 2 : k - 2) : ((k - 3) & 3) + 5);
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  static constexpr double cs2 = 1.0 / 3.0;
+};
+
+// Eq. (3-11): directions 0, +x, -x, +y, -y, +z, -z, then (1,1,1), (1,-1,-1),
+// (1,-1,1), (1,1,-1), (-1,1,1), (-1,-1,-1), (-1,-1,1), (-1,1,-1);
+// w = (2/9, 1/9 x6, 1/72 x8); second moment 1/3.
+template <> struct Lattice<8> {
+  static constexpr int D = 3, Q = 15;
+  static constexpr bool diag = true;
+  __host__ __device__ static constexpr int c(int k, int a) {
+    return k == 0 ? 0
+                  : (k <= 6 ? ((k - 1) / 2 == a ? ((k & 1) ? 1 : -1) : 0)
+                            : sign_bit(a == 0 ? 0x0780u : (a == 1 ? 0x4C80u : 0x2A80u), k));
+  }
+  __host__ __device__ static constexpr int opp(int k) {
+    return k == 0 ? 0
+                  : (k <= 6 ? ((k & 1) ? k + 1 : k - 1)
+                            : ((k == 7 || k == 8 || k == 11 || k == 12) ? 19 - k : 23 - k));
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 2.0 / 9.0 : (k <= 6 ? 1.0 / 9.0 : 1.0 / 72.0);
+  }
+  static constexpr double cs2 = 1.0 / 3.0;
+};
+
+// Compile-time checks of every table: opposite directions are negatives with
+// equal weights, the weights sum to 1, first moments vanish, the second moment
+// is isotropic with value cs2 and the mixed second moments vanish.
+template <int LAT>
+constexpr bool lattice_consistent() {
+  using L = Lattice<LAT>;
+  double ws = 0.0;
+  for (int k = 0; k < L::Q; ++k) {
+    ws += L::w(k);
+    if (L::opp(L::opp(k)) != k || L::w(L::opp(k)) != L::w(k)) return false;
+    for (int a = 0; a < 3; ++a)
+      if (L::c(L::opp(k), a) != -L::c(k, a) || (a >= L::D && L::c(k, a) != 0)) return false;
+  }
+  if ((ws - 1.0) * (ws - 1.0) > 1e-28) return false;
+  for (int a = 0; a < L::D; ++a)
+    for (int b = 0; b < L::D; ++b) {
+      double m1 = 0.0, m2 = 0.0;
+      for (int k = 0; k < L::Q; ++k) {
+        m1 += L::w(k) * L::c(k, a);
+        m2 += L::w(k) * L::c(k, a) * L::c(k, b);
+      }
+      const double want = a == b ? L::cs2 : 0.0;
+      if (m1 * m1 > 1e-28 || (m2 - want) * (m2 - want) > 1e-28) return false;
+    }
+  return true;
+}
+static_assert(lattice_consistent<1>() && lattice_consistent<2>() && lattice_consistent<3>() &&
+                  lattice_consistent<4>() && lattice_consistent<5>() && lattice_consistent<6>() &&
+                  lattice_consistent<7>() && lattice_consistent<8>(),
+              "lattice tables");
 
 // ---------------------------------------------------------------------------
 // Kernel parameters (passed by value in the kernel argument segment).
@@ -377,6 +466,32 @@ __device__ __forceinline__ T ld(const T* p, bool nt) {
 // Bits of the non-temporal mask of a sweep launch.
 constexpr int NT_STORE = 1, NT_LOAD_ALIGNED = 2, NT_LOAD_SHIFTED = 4;
 
+// Where direction k of node n reads from on a lattice with diagonal
+// directions: the node x - s c_k (s = 1 for propagation, -1 for its transpose),
+// wrapped across periodic faces; its linear index goes to `off`.  Returns -1
+// for that case, else the wall face (2 axis + side) that decides because
+// x - s c_k lies beyond it: among the wall faces crossed, the one of the
+// lowest axis (a direction leaving through an edge or corner of the box
+// crosses two or three faces).
+template <int LAT>
+__device__ __forceinline__ int diag_source(const Problem& p, const NodePos& n, int k, int s, int64_t& off) {
+  using L = Lattice<LAT>;
+  int face = -1;
+  off = n.idx;
+#pragma unroll
+  for (int a = L::D - 1; a >= 0; --a) {
+    const int c = s * L::c(k, a);
+    if (c == 0) continue;
+    const int32_t ext = extent(p, a);
+    const int64_t st = axis_stride<LAT>(p, a);
+    const bool edge = (c > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
+    const int fa = 2 * a + (c > 0 ? 0 : 1);
+    if (edge && p.bc[fa] != BC_PERIODIC) face = fa;   // lower axes come later and win
+    off += edge ? (int64_t)c * (ext - 1) * st : -(int64_t)c * st;
+  }
+  return face;
+}
+
 // f_k^i(x, t) for all i of one direction k: the post-collision value of the
 // source node x - c_k, or at a wall face
 //   zero flux:  f_kbar^+(x)            (half-way bounce-back)
@@ -387,30 +502,47 @@ __device__ __forceinline__ void pull_direction(const Problem& p, const T* src, c
                                                T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M], int nt) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
-  const int a = L::axis(k);
   const bool nt_al = (nt & NT_LOAD_ALIGNED) != 0;
-  if (a < 0) {
+  if constexpr (L::diag) {
+    int64_t off;
+    const int face = diag_source<LAT>(p, n, k, 1, off);
+    if (face < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + n.idx, nt_al);
-    return;
-  }
-  const bool nt_sh = (a == 0) ? (nt & NT_LOAD_SHIFTED) != 0 : nt_al;
-  const int s = L::sgn(k);
-  const int32_t ext = extent(p, a);
-  const int64_t st = axis_stride<LAT>(p, a);
-  const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
-  const int face = 2 * a + (s > 0 ? 0 : 1);
-  const int kind = edge ? p.bc[face] : BC_PERIODIC;
-  if (kind == BC_PERIODIC) {
-    const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+      for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + off, nt_al);
+    } else {
+      const int kb = L::opp(k);
+      const int kind = p.bc[face];
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + off, nt_sh);
+      for (int i = 0; i < M; ++i) {
+        const T back = ld(src + (int64_t)(i * Q + kb) * p.plane + n.idx, nt_al);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      }
+    }
   } else {
-    const int kb = L::opp(k);
+    const int a = L::axis(k);
+    if (a < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const T back = ld(src + (int64_t)(i * Q + kb) * p.plane + n.idx, nt_al);
-      out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + n.idx, nt_al);
+      return;
+    }
+    const bool nt_sh = (a == 0) ? (nt & NT_LOAD_SHIFTED) != 0 : nt_al;
+    const int s = L::sgn(k);
+    const int32_t ext = extent(p, a);
+    const int64_t st = axis_stride<LAT>(p, a);
+    const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
+    const int face = 2 * a + (s > 0 ? 0 : 1);
+    const int kind = edge ? p.bc[face] : BC_PERIODIC;
+    if (kind == BC_PERIODIC) {
+      const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+#pragma unroll
+      for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + off, nt_sh);
+    } else {
+      const int kb = L::opp(k);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const T back = ld(src + (int64_t)(i * Q + kb) * p.plane + n.idx, nt_al);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      }
     }
   }
 }
@@ -446,29 +578,46 @@ __device__ __forceinline__ void pull_direction_transposed(const Problem& p, cons
                                                           T (&out)[M][Lattice<LAT>::Q]) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
-  const int a = L::axis(k);
-  if (a < 0) {
+  if constexpr (L::diag) {
+    int64_t off;
+    const int face = diag_source<LAT>(p, n, k, -1, off);
+    if (face < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
-    return;
-  }
-  const int s = L::sgn(k);
-  const int32_t ext = extent(p, a);
-  const int64_t st = axis_stride<LAT>(p, a);
-  // the face that direction k leaves the domain through
-  const bool edge = (s > 0) ? (n.c[a] == ext - 1) : (n.c[a] == 0);
-  const int face = 2 * a + (s > 0 ? 1 : 0);
-  const int kind = edge ? p.bc[face] : BC_PERIODIC;
-  if (kind == BC_PERIODIC) {
-    const int64_t off = edge ? n.idx - (int64_t)s * (ext - 1) * st : n.idx + (int64_t)s * st;
+      for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+    } else {
+      const int kb = L::opp(k);
+      const bool zf = p.bc[face] == BC_ZERO_FLUX;
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+      for (int i = 0; i < M; ++i) {
+        const T v = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
+        out[i][k] = zf ? v : -v;
+      }
+    }
   } else {
-    const int kb = L::opp(k);
+    const int a = L::axis(k);
+    if (a < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const T v = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
-      out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+      for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + n.idx];
+      return;
+    }
+    const int s = L::sgn(k);
+    const int32_t ext = extent(p, a);
+    const int64_t st = axis_stride<LAT>(p, a);
+    // the face that direction k leaves the domain through
+    const bool edge = (s > 0) ? (n.c[a] == ext - 1) : (n.c[a] == 0);
+    const int face = 2 * a + (s > 0 ? 1 : 0);
+    const int kind = edge ? p.bc[face] : BC_PERIODIC;
+    if (kind == BC_PERIODIC) {
+      const int64_t off = edge ? n.idx - (int64_t)s * (ext - 1) * st : n.idx + (int64_t)s * st;
+#pragma unroll
+      for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
+    } else {
+      const int kb = L::opp(k);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const T v = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
+        out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+      }
     }
   }
 }
@@ -496,34 +645,58 @@ __device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>&
                                          T (&out)[M][Lattice<LAT>::Q], const T (&wall)[6][M], bool transposed) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
-  const int a = L::axis(k);
-  if (a < 0) {
+  if constexpr (L::diag) {
+    int64_t off;
+    const int face = diag_source<LAT>(p, n, k, transposed ? -1 : 1, off);
+    const int kb = L::opp(k);
+    if (face < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, n.idx);
-    return;
-  }
-  const int s = transposed ? -L::sgn(k) : L::sgn(k);   // read from x - s c
-  const int32_t ext = extent(p, a);
-  const int64_t st = axis_stride<LAT>(p, a);
-  const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
-  const int face = 2 * a + (s > 0 ? 0 : 1);
-  const int kind = edge ? p.bc[face] : BC_PERIODIC;
-  const int kb = L::opp(k);
-  if (kind == BC_PERIODIC) {
-    const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+      for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, off);
+    } else if (!transposed) {
+      const int kind = p.bc[face];
 #pragma unroll
-    for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, off);
-  } else if (!transposed) {
+      for (int i = 0; i < M; ++i) {
+        const T back = src(i * Q + kb, n.idx);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      }
+    } else {
+      const bool zf = p.bc[face] == BC_ZERO_FLUX;
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const T back = src(i * Q + kb, n.idx);
-      out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      for (int i = 0; i < M; ++i) {
+        const T v = src(i * Q + kb, n.idx);
+        out[i][k] = zf ? v : -v;
+      }
     }
   } else {
+    const int a = L::axis(k);
+    if (a < 0) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const T v = src(i * Q + kb, n.idx);
-      out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+      for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, n.idx);
+      return;
+    }
+    const int s = transposed ? -L::sgn(k) : L::sgn(k);   // read from x - s c
+    const int32_t ext = extent(p, a);
+    const int64_t st = axis_stride<LAT>(p, a);
+    const bool edge = (s > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
+    const int face = 2 * a + (s > 0 ? 0 : 1);
+    const int kind = edge ? p.bc[face] : BC_PERIODIC;
+    const int kb = L::opp(k);
+    if (kind == BC_PERIODIC) {
+      const int64_t off = edge ? n.idx + (int64_t)s * (ext - 1) * st : n.idx - (int64_t)s * st;
+#pragma unroll
+      for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, off);
+    } else if (!transposed) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const T back = src(i * Q + kb, n.idx);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const T v = src(i * Q + kb, n.idx);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? v : -v;
+      }
     }
   }
 }

@@ -19,10 +19,12 @@ int validate(const msd_problem* p);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int lattice_d(int lat) {
-  return (lat == MSD_D1Q3 || lat == MSD_D1Q2) ? 1 : ((lat == MSD_D2Q5 || lat == MSD_D2Q4) ? 2 : 3);
+  return (lat == MSD_D1Q3 || lat == MSD_D1Q2) ? 1 : ((lat == MSD_D2Q5 || lat == MSD_D2Q4 || lat == MSD_D2Q9) ? 2 : 3);
 }
-// q = 2d + 1 with a rest direction, 2d without
-inline int lattice_q(int lat) { return 2 * lattice_d(lat) + (lat <= MSD_D3Q7 ? 1 : 0); }
+// q = 2d + 1 with a rest direction, 2d without; 9 and 15 with diagonals
+inline int lattice_q(int lat) {
+  return lat == MSD_D2Q9 ? 9 : (lat == MSD_D3Q15 ? 15 : 2 * lattice_d(lat) + (lat <= MSD_D3Q7 ? 1 : 0));
+}
 
 constexpr int kDiagBlocksMax = 1024;
 

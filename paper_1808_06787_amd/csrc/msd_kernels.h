@@ -773,7 +773,11 @@ __global__ __launch_bounds__(256) void k_read(Problem p, const T* __restrict__ s
     for (int d = 0; d < DD; ++d) m1[i][d] = T(0);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      if (L::axis(k) >= 0) m1[i][L::axis(k) >= 0 ? L::axis(k) : 0] += (L::sgn(k) > 0) ? f[i][k] : -f[i][k];
+#pragma unroll
+      for (int d = 0; d < DD; ++d) {
+        if (L::c(k, d) > 0) m1[i][d] += f[i][k];
+        if (L::c(k, d) < 0) m1[i][d] -= f[i][k];
+      }
   }
 #pragma unroll
   for (int i = 0; i < M; ++i) oxi[(int64_t)i * nodes + n.idx] = TO(xi[i]);
@@ -1547,21 +1551,28 @@ hipError_t run(Op op, const LaunchArgs& a) {
       break;
     }
     case Op::Step: {
-      const int V = vec_width<T>(a);
+      // the vectorised kernel shares x-neighbours between lanes: axis-aligned lattices only
+      const int V = Lattice<LAT>::diag ? 0 : vec_width<T>(a);
       const Tiling tl = make_tiling(a, V > 0 ? V : 1);
       const dim3 grid(tl.tiles), block(a.block_x, a.block_y);
       const T* src = static_cast<const T*>(a.src);
       T* dst = static_cast<T*>(a.dst);
-      if (V == 4)
-        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 4>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
-                           a.nontemporal);
-      else if (V == 2)
-        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 2>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
-                           a.nontemporal);
-      else if (V == 1)
-        hipLaunchKernelGGL((k_step_vec<LAT, M, T, 1>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
-                           a.nontemporal);
-      else
+      bool done = false;
+      if constexpr (!Lattice<LAT>::diag) {
+        done = true;
+        if (V == 4)
+          hipLaunchKernelGGL((k_step_vec<LAT, M, T, 4>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                             a.nontemporal);
+        else if (V == 2)
+          hipLaunchKernelGGL((k_step_vec<LAT, M, T, 2>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                             a.nontemporal);
+        else if (V == 1)
+          hipLaunchKernelGGL((k_step_vec<LAT, M, T, 1>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                             a.nontemporal);
+        else
+          done = false;
+      }
+      if (!done)
         hipLaunchKernelGGL((k_step<LAT, M, T>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
                            a.nontemporal);
       break;

@@ -15,8 +15,9 @@ import torch
 
 from . import _ffi as F
 
-LATTICES = {"D1Q3": F.D1Q3, "D2Q5": F.D2Q5, "D3Q7": F.D3Q7, "D1Q2": F.D1Q2, "D2Q4": F.D2Q4, "D3Q6": F.D3Q6}
-DIMS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3}
+LATTICES = {"D1Q3": F.D1Q3, "D2Q5": F.D2Q5, "D3Q7": F.D3Q7, "D1Q2": F.D1Q2, "D2Q4": F.D2Q4, "D3Q6": F.D3Q6,
+            "D2Q9": F.D2Q9, "D3Q15": F.D3Q15}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3, "D2Q9": 2, "D3Q15": 3}
 PRECISIONS = {"f32": F.F32, "f64": F.F64}
 RELAX = {"paper": F.RELAX_PAPER, "srt": F.RELAX_SRT, "trt": F.RELAX_TRT}
 BCS = {"periodic": F.BC_PERIODIC, "zero_flux": F.BC_ZERO_FLUX, "dirichlet": F.BC_DIRICHLET}

@@ -62,7 +62,9 @@ def test_workspace_size_model():
     # two halves of m*q planes plus < 1 MiB of constants and reduction scratch
     assert 2 * 2 * 5 * plane * 4 <= n < 2 * 2 * 5 * plane * 4 + (1 << 20)
     # lattices without a rest direction: q = 2d
-    for lattice, shape, q in (("D1Q2", (300,), 2), ("D2Q4", (100, 37), 4), ("D3Q6", (20, 9, 7), 6)):
+    # and with diagonal directions: q = 9, 15
+    for lattice, shape, q in (("D1Q2", (300,), 2), ("D2Q4", (100, 37), 4), ("D3Q6", (20, 9, 7), 6),
+                              ("D2Q9", (100, 37), 9), ("D3Q15", (20, 9, 7), 15)):
         p, keep = make_problem(lattice, D, shape, "f64")
         n, st = _ws(p)
         assert st == 0
@@ -74,7 +76,7 @@ def test_workspace_size_model():
     "mutate,code",
     [
         (lambda p: setattr(p, "abi", 99), -8),
-        (lambda p: setattr(p, "lattice", 7), -1),
+        (lambda p: setattr(p, "lattice", 9), -1),
         (lambda p: setattr(p, "n_species", 1), -1),
         (lambda p: setattr(p, "n_species", 9), -1),
         (lambda p: setattr(p, "precision", 2), -1),

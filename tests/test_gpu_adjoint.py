@@ -46,6 +46,9 @@ CASES = [
     ("D1Q2", (19,), 3, (("dirichlet", "zero_flux"),)),
     ("D2Q4", (11, 8), 4, (("zero_flux", "dirichlet"), ("periodic", "periodic"))),
     ("D3Q6", (5, 6, 4), 3, (("periodic", "periodic"), ("zero_flux", "dirichlet"), ("zero_flux", "zero_flux"))),
+    ("D2Q9", (12, 9), 3, (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"))),
+    ("D2Q9", (10, 11), 4, (("periodic", "periodic"), ("dirichlet", "zero_flux"))),
+    ("D3Q15", (6, 5, 4), 3, (("zero_flux", "dirichlet"), ("periodic", "periodic"), ("dirichlet", "zero_flux"))),
 ]
 
 

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _specs(lattice, rng):
-    if lattice in ("D2Q5", "D2Q4"):
+    if lattice in ("D2Q5", "D2Q4", "D2Q9"):
         shapes = [(64, 64), (97, 45), (128, 33), (65, 70), (1, 1), (130, 7)]
         Ns = [2, 3, 4, 5, 3, 6]
     else:
@@ -51,7 +51,7 @@ def _read_all(b):
     return out
 
 
-@pytest.mark.parametrize("lattice", ["D2Q5", "D3Q7", "D2Q4", "D3Q6"])
+@pytest.mark.parametrize("lattice", ["D2Q5", "D3Q7", "D2Q4", "D3Q6", "D2Q9", "D3Q15"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_batch_matches_oracle_per_mixture(lattice, precision):
     rng = np.random.default_rng(70)

@@ -14,9 +14,11 @@ from gpu_cases import (assert_parity, gpu_run, oracle_problem, oracle_run, rand_
 pytestmark = pytest.mark.gpu
 
 SHAPES = {"D1Q3": (301,), "D2Q5": (97, 45), "D3Q7": (37, 19, 11),
-          "D1Q2": (301,), "D2Q4": (97, 45), "D3Q6": (37, 19, 11)}
-WALLS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3}
-ALL = ["D1Q3", "D2Q5", "D3Q7", "D1Q2", "D2Q4", "D3Q6"]
+          "D1Q2": (301,), "D2Q4": (97, 45), "D3Q6": (37, 19, 11),
+          "D2Q9": (97, 45), "D3Q15": (37, 19, 11)}
+WALLS = {"D1Q3": 1, "D2Q5": 2, "D3Q7": 3, "D1Q2": 1, "D2Q4": 2, "D3Q6": 3, "D2Q9": 2, "D3Q15": 3}
+ALL = ["D1Q3", "D2Q5", "D3Q7", "D1Q2", "D2Q4", "D3Q6", "D2Q9", "D3Q15"]
+DIAG = ["D2Q9", "D3Q15"]
 
 
 def _bc(lattice, kinds):
@@ -160,6 +162,50 @@ def test_degenerate_extents(shape, rest):
         assert_parity(gpu, orc, "f64", f"{shape} {launch}")
 
 
+@pytest.mark.parametrize("lattice", DIAG)
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("faces", range(3))
+def test_diagonal_lattices_walls_on_every_face(lattice, precision, faces):
+    """Walls on every face, of both kinds, so that diagonal directions leave through
+    edges and corners where two or three wall faces meet (the wall of the lowest
+    axis decides), and mixed with periodic axes."""
+    kinds = [
+        (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"), ("dirichlet", "zero_flux")),
+        (("zero_flux", "zero_flux"), ("dirichlet", "dirichlet"), ("zero_flux", "dirichlet")),
+        (("periodic", "periodic"), ("dirichlet", "zero_flux"), ("periodic", "periodic")),
+    ][faces]
+    rng = np.random.default_rng(1300 + faces)
+    N = 3
+    D = rand_D(rng, N)
+    shape = {"D2Q9": (71, 38), "D3Q15": (29, 17, 10)}[lattice]
+    bc = kinds[: len(shape)]
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for side, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, side)] = rand_field(rng, N, ())
+    xi0 = rand_field(rng, N, shape[::-1])
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls), xi0, 35)
+    gpu = gpu_run(lattice, D, shape, precision, xi0, 35, bc=bc, xi_wall=walls)
+    assert_parity(gpu, orc, precision, f"{lattice} faces {faces} {precision}")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 6), (5, 1), (13, 8), (1, 1, 1), (3, 1, 2), (9, 7, 5)])
+def test_diagonal_lattices_small_and_degenerate(shape):
+    """Extents of one node (every diagonal wraps onto its own row or column) and
+    small grids, through the LDS-resident kernel and the global one."""
+    lattice = {2: "D2Q9", 3: "D3Q15"}[len(shape)]
+    rng = np.random.default_rng(1400 + len(shape))
+    D = rand_D(rng, 3)
+    xi0 = rand_field(rng, 3, shape[::-1])
+    bc = tuple(("zero_flux", "dirichlet") if n > 2 else ("periodic", "periodic") for n in shape)
+    walls = {(a, 1): rand_field(rng, 3, ()) for a, n in enumerate(shape) if n > 2}
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls), xi0, 11)
+    for launch in (dict(lds_resident=1), dict(lds_resident=0)):
+        gpu = gpu_run(lattice, D, shape, "f64", xi0, 11, bc=bc, xi_wall=walls, launch=launch)
+        assert_parity(gpu, orc, "f64", f"{lattice} {shape} {launch}")
+
+
 def test_zero_steps_reads_initial_state():
     rng = np.random.default_rng(9)
     D = rand_D(rng, 4)
@@ -171,7 +217,8 @@ def test_zero_steps_reads_initial_state():
 
 
 VEC_SHAPES = {"D1Q3": (1028,), "D2Q5": (1028, 13), "D3Q7": (68, 9, 5),
-              "D1Q2": (1028,), "D2Q4": (1028, 13), "D3Q6": (68, 9, 5)}
+              "D1Q2": (1028,), "D2Q4": (1028, 13), "D3Q6": (68, 9, 5),
+              "D2Q9": (1028, 13), "D3Q15": (68, 9, 5)}     # diagonal lattices ignore the vector width
 
 
 @pytest.mark.parametrize("lattice", ALL)
