@@ -472,11 +472,16 @@ constexpr int NT_STORE = 1, NT_LOAD_ALIGNED = 2, NT_LOAD_SHIFTED = 4;
 // for that case, else the wall face (2 axis + side) that decides because
 // x - s c_k lies beyond it: among the wall faces crossed, the one of the
 // lowest axis (a direction leaving through an edge or corner of the box
-// crosses two or three faces).
+// crosses two or three faces).  `kind` receives that face's boundary kind.
+// Face numbers are compile-time constants inside the unrolled loop; callers
+// select per-face values with wall_value so that no array is indexed at run
+// time (which would move the constants to scratch memory).
 template <int LAT>
-__device__ __forceinline__ int diag_source(const Problem& p, const NodePos& n, int k, int s, int64_t& off) {
+__device__ __forceinline__ int diag_source(const Problem& p, const NodePos& n, int k, int s, int64_t& off,
+                                           int& kind) {
   using L = Lattice<LAT>;
   int face = -1;
+  kind = BC_PERIODIC;
   off = n.idx;
 #pragma unroll
   for (int a = L::D - 1; a >= 0; --a) {
@@ -486,10 +491,30 @@ __device__ __forceinline__ int diag_source(const Problem& p, const NodePos& n, i
     const int64_t st = axis_stride<LAT>(p, a);
     const bool edge = (c > 0) ? (n.c[a] == 0) : (n.c[a] == ext - 1);
     const int fa = 2 * a + (c > 0 ? 0 : 1);
-    if (edge && p.bc[fa] != BC_PERIODIC) face = fa;   // lower axes come later and win
+    if (edge && p.bc[fa] != BC_PERIODIC) {   // lower axes come later and win
+      face = fa;
+      kind = p.bc[fa];
+    }
     off += edge ? (int64_t)c * (ext - 1) * st : -(int64_t)c * st;
   }
   return face;
+}
+
+// wall[face][i] for a face number known only at run time, by a chain of
+// selects between registers.  The empty asm statements pin each candidate in a
+// register; without them the compiler turns the chain back into one indexed
+// load, which puts the whole constant block in scratch memory.
+template <int LAT, int M, typename T>
+__device__ __forceinline__ T wall_value(const T (&wall)[6][M], int face, int i) {
+  T v = wall[0][i];
+  asm volatile("" : "+v"(v));
+#pragma unroll
+  for (int f = 1; f < 2 * Lattice<LAT>::D; ++f) {
+    T c = wall[f][i];
+    asm volatile("" : "+v"(c));
+    v = (face == f) ? c : v;
+  }
+  return v;
 }
 
 // f_k^i(x, t) for all i of one direction k: the post-collision value of the
@@ -505,17 +530,18 @@ __device__ __forceinline__ void pull_direction(const Problem& p, const T* src, c
   const bool nt_al = (nt & NT_LOAD_ALIGNED) != 0;
   if constexpr (L::diag) {
     int64_t off;
-    const int face = diag_source<LAT>(p, n, k, 1, off);
+    int kind;
+    const int face = diag_source<LAT>(p, n, k, 1, off, kind);
     if (face < 0) {
 #pragma unroll
       for (int i = 0; i < M; ++i) out[i][k] = ld(src + (int64_t)(i * Q + k) * p.plane + off, nt_al);
     } else {
       const int kb = L::opp(k);
-      const int kind = p.bc[face];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         const T back = ld(src + (int64_t)(i * Q + kb) * p.plane + n.idx, nt_al);
-        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back
+                                           : (T(2.0 * L::w(kb)) * wall_value<LAT, M, T>(wall, face, i) - back);
       }
     }
   } else {
@@ -580,13 +606,14 @@ __device__ __forceinline__ void pull_direction_transposed(const Problem& p, cons
   constexpr int Q = L::Q;
   if constexpr (L::diag) {
     int64_t off;
-    const int face = diag_source<LAT>(p, n, k, -1, off);
+    int kind;
+    const int face = diag_source<LAT>(p, n, k, -1, off, kind);
     if (face < 0) {
 #pragma unroll
       for (int i = 0; i < M; ++i) out[i][k] = src[(int64_t)(i * Q + k) * p.plane + off];
     } else {
       const int kb = L::opp(k);
-      const bool zf = p.bc[face] == BC_ZERO_FLUX;
+      const bool zf = kind == BC_ZERO_FLUX;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         const T v = src[(int64_t)(i * Q + kb) * p.plane + n.idx];
@@ -647,20 +674,21 @@ __device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>&
   constexpr int Q = L::Q;
   if constexpr (L::diag) {
     int64_t off;
-    const int face = diag_source<LAT>(p, n, k, transposed ? -1 : 1, off);
+    int kind;
+    const int face = diag_source<LAT>(p, n, k, transposed ? -1 : 1, off, kind);
     const int kb = L::opp(k);
     if (face < 0) {
 #pragma unroll
       for (int i = 0; i < M; ++i) out[i][k] = src(i * Q + k, off);
     } else if (!transposed) {
-      const int kind = p.bc[face];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         const T back = src(i * Q + kb, n.idx);
-        out[i][k] = (kind == BC_ZERO_FLUX) ? back : (T(2.0 * L::w(kb)) * wall[face][i] - back);
+        out[i][k] = (kind == BC_ZERO_FLUX) ? back
+                                           : (T(2.0 * L::w(kb)) * wall_value<LAT, M, T>(wall, face, i) - back);
       }
     } else {
-      const bool zf = p.bc[face] == BC_ZERO_FLUX;
+      const bool zf = kind == BC_ZERO_FLUX;
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         const T v = src(i * Q + kb, n.idx);
