@@ -54,6 +54,8 @@ class Problem:
     xi_ref  : if given, B is evaluated at these fixed mole fractions instead of
               the local ones (the linearised theory with constant effective
               diffusivities, Sec. 1)
+    dilute  : if true, B is the dilute-species approximation of Remark III
+              (diagonal, Eqs. (2-16), (2-17)) instead of Eq. (2-10)
     """
 
     lattice: str
@@ -66,6 +68,7 @@ class Problem:
     lambda0: float = 1.0
     c_t: float = 1.0
     xi_ref: np.ndarray = None
+    dilute: bool = False
 
     def __post_init__(self):
         self.D = np.asarray(self.D, dtype=np.float64)
@@ -133,14 +136,15 @@ def first_moments(prob: Problem, f: np.ndarray) -> np.ndarray:
 def relaxation_matrices(prob: Problem, xi: np.ndarray):
     """B, D~, Lambda_1, Lambda_2 at every node from the mole fractions xi (N, *nodes).
 
-    B by Eq. (2-10), D~ = B^-1 by Eq. (2-11), Lambda_1 by inverting Eq. (3-26),
-    Lambda_2 by Eq. (3-16) (or = Lambda_1 in SRT mode).  All (*nodes, m, m).
+    B by Eq. (2-10) (by Eqs. (2-16), (2-17) in dilute mode), D~ = B^-1 by
+    Eq. (2-11), Lambda_1 by inverting Eq. (3-26), Lambda_2 by Eq. (3-16) (or =
+    Lambda_1 in SRT mode).  All (*nodes, m, m).
     """
     if prob.xi_ref is not None:
         xi_b = np.broadcast_to(prob.xi_ref, prob.nodes + (prob.N,))
     else:
         xi_b = np.moveaxis(xi, 0, -1)
-    B = _ms.ms_B(xi_b, prob.D)
+    B = (_ms.ms_B_dilute if prob.dilute else _ms.ms_B)(xi_b, prob.D)
     Dt = _ms.fick_matrix(B)
     L1 = _ms.lambda1_from_fick(Dt, prob.lat.cs2, 1.0)
     L2 = _ms.lambda2_from_lambda1(L1, prob.relax, prob.magic)

@@ -51,6 +51,29 @@ def ms_B(xi: np.ndarray, D: np.ndarray) -> np.ndarray:
     return B
 
 
+def ms_B_dilute(xi: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """The dilute-species approximation of B (Remark III, Eqs. (2-16), (2-17)),
+    applied to every evolved species: B is diagonal with
+
+        B_ii = 1 / D_eff,i = sum_{k != i, k = 1..N} xi_k / D_ik,
+
+    so each species follows Fick's law with its own composition-dependent
+    effective diffusivity.  xi: (..., N); returns (..., N-1, N-1).
+    """
+    xi = np.asarray(xi, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    n = D.shape[0]
+    m = n - 1
+    B = np.zeros(xi.shape[:-1] + (m, m), dtype=np.float64)
+    for i in range(m):
+        s = np.zeros(xi.shape[:-1])
+        for k in range(n):
+            if k != i:
+                s = s + xi[..., k] / D[i, k]
+        B[..., i, i] = s
+    return B
+
+
 def fick_matrix(B: np.ndarray) -> np.ndarray:
     """Generalised Fick diffusivity D~ = B^-1 (Eq. (2-11)); B is invertible (Sec. 2)."""
     return np.linalg.inv(B)

@@ -34,7 +34,8 @@ def _inverse(a):
 
 
 def _node_matrices(prob, xi_all):
-    """B (Eq. (2-10)), D~ = B^-1, Lambda_1 (Eq. (3-26)), Lambda_2 (Eq. (3-16)) at one node."""
+    """B (Eq. (2-10), or Eqs. (2-16), (2-17) in dilute mode), D~ = B^-1, Lambda_1
+    (Eq. (3-26)), Lambda_2 (Eq. (3-16)) at one node."""
     n = prob.N
     m = n - 1
     D = prob.D
@@ -43,9 +44,9 @@ def _node_matrices(prob, xi_all):
     for i in range(m):
         for j in range(m):
             if i != j:
-                B[i][j] = x[i] * (1.0 / D[i][n - 1] - 1.0 / D[i][j])
+                B[i][j] = 0.0 if prob.dilute else x[i] * (1.0 / D[i][n - 1] - 1.0 / D[i][j])
             else:
-                s = x[i] / D[i][n - 1]
+                s = 0.0 if prob.dilute else x[i] / D[i][n - 1]
                 for k in range(n):
                     if k != i:
                         s += x[k] / D[i][k]
