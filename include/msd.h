@@ -40,7 +40,7 @@ extern "C" {
 #define MSD_API
 #endif
 
-#define MSD_ABI_VERSION 2
+#define MSD_ABI_VERSION 3
 #define MSD_MAX_SPECIES 8
 
 /* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10),
@@ -106,7 +106,12 @@ typedef struct msd_problem {
   int32_t bc[6];            /* enum msd_bc for faces x_lo, x_hi, y_lo, y_hi, z_lo, z_hi */
   int32_t plane_pad;        /* extra values between consecutive distribution planes: a multiple
                                of 64, >= 0 (0 = planes of the node count rounded up to 64) */
-  int32_t reserved;         /* must be 0 */
+  int32_t dilute;           /* 0: B of Eq. (2-10); 1: the dilute-species approximation of Remark III,
+                               Eqs. (2-16), (2-17), for every evolved species: B diagonal with
+                               B_ii = sum_{k != i} xi_k / D_ik (each species follows Fick's law with
+                               its own composition-dependent D_eff).  With linearized = 1 the
+                               diagonal is frozen at xi_ref.  Runs one step per pass; the adjoint
+                               entry points and the batch reject it (MSD_EINVAL) */
   double trt_magic;         /* MSD_RELAX_TRT only: the product parameter, finite and > 0 */
 } msd_problem;
 

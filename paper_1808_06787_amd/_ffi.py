@@ -11,7 +11,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsd.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_SPECIES = 8
 
 D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6, D2Q9, D3Q15 = 1, 2, 3, 4, 5, 6, 7, 8
@@ -44,7 +44,7 @@ class MsdProblem(C.Structure):
         ("linearized", C.c_int32),
         ("bc", C.c_int32 * 6),
         ("plane_pad", C.c_int32),
-        ("reserved", C.c_int32),
+        ("dilute", C.c_int32),
         ("trt_magic", C.c_double),
     ]
 

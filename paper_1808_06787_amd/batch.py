@@ -35,7 +35,7 @@ class Batch:
         for i, sp in enumerate(specs):
             p, keep = make_problem(lattice, sp["D"], sp["shape"], precision, sp.get("bc"), sp.get("xi_wall"),
                                    sp.get("relax", "paper"), sp.get("c_t", 1.0), sp.get("xi_ref"),
-                                   trt_magic=sp.get("trt_magic", F.MAGIC_PAPER))
+                                   trt_magic=sp.get("trt_magic", F.MAGIC_PAPER), dilute=sp.get("dilute", False))
             arr[i] = p
             self._keep.append(keep)
             self.shapes.append(tuple(int(s) for s in sp["shape"]))

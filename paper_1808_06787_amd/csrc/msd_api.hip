@@ -100,7 +100,7 @@ int validate(const msd_problem* p) {
     if (ext[a] > (int64_t)1 << 30) return fail(MSD_EINVAL, "extent %d too large", a);
   }
   if (p->nx * p->ny * p->nz >= ((int64_t)1 << 31)) return fail(MSD_EINVAL, "more than 2^31 - 1 nodes");
-  if (p->reserved) return fail(MSD_EINVAL, "reserved field must be 0");
+  if (p->dilute != 0 && p->dilute != 1) return fail(MSD_EINVAL, "dilute = %d must be 0 or 1", p->dilute);
   if (p->plane_pad < 0 || p->plane_pad % 64 || p->plane_pad > (1 << 24))
     return fail(MSD_EINVAL, "plane_pad = %d must be a multiple of 64 in [0, 2^24]", p->plane_pad);
   if (!p->D) return fail(MSD_EINVAL, "D is NULL");
@@ -160,6 +160,7 @@ void fill_kernel_problem(const msd_problem* problem, int64_t plane, Problem* out
   kp.relax = problem->relax;
   kp.magic = problem->relax == MSD_RELAX_TRT ? problem->trt_magic : 3.0 / 16.0;
   kp.linearized = problem->linearized ? 1 : 0;
+  kp.dilute = problem->dilute ? 1 : 0;
   for (int f = 0; f < 6; ++f) kp.bc[f] = problem->bc[f];
   kp.plane = plane;
   kp.c_t = problem->c_t;
@@ -256,8 +257,8 @@ struct msd_sim {
 };
 
 static_assert(sizeof(msd_problem) == 120 && offsetof(msd_problem, c_t) == 64 && offsetof(msd_problem, bc) == 80 &&
-                  offsetof(msd_problem, trt_magic) == 112,
-              "msd_problem layout (ABI version 2)");
+                  offsetof(msd_problem, dilute) == 108 && offsetof(msd_problem, trt_magic) == 112,
+              "msd_problem layout (ABI version 3)");
 
 namespace {
 
@@ -303,7 +304,7 @@ struct BlockedPlan {
 
 BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   BlockedPlan pl;
-  if (s->prob.lattice != MSD_D2Q5) return pl;
+  if (s->prob.lattice != MSD_D2Q5 || s->prob.dilute) return pl;   // blocked kernels: full model only
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)
@@ -667,8 +668,15 @@ size_t msd_adjoint_accum_bytes(const msd_sim* s) {
   return sizeof(double) * (size_t)adjoint_slots(s) * s->m * (s->m + 1);
 }
 
+// The hand-written adjoint differentiates the collision of Eq. (2-10) only.
+static int adjoint_supported(const msd_sim* s) {
+  if (s->prob.dilute) return fail(MSD_EINVAL, "the adjoint covers B of Eq. (2-10) only (dilute = 1)");
+  return MSD_OK;
+}
+
 int msd_adjoint_begin(msd_sim* s, void* d_accum) {
   if (!s || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   msd::LaunchArgs a = base_args(s);
   a.partials = static_cast<double*>(d_accum);
   a.fill_count = (int64_t)(msd_adjoint_accum_bytes(s) / sizeof(double));
@@ -679,6 +687,7 @@ int msd_adjoint_begin(msd_sim* s, void* d_accum) {
 
 int msd_adjoint_seed(msd_sim* s, const double* d_dL_dxi, void* d_adj_out) {
   if (!s || !d_dL_dxi || !d_adj_out) return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
   msd::LaunchArgs a = base_args(s);
   a.xi0 = d_dL_dxi;
@@ -692,6 +701,7 @@ int msd_adjoint_seed(msd_sim* s, const double* d_dL_dxi, void* d_adj_out) {
 int msd_adjoint_step(msd_sim* s, int64_t t, const void* d_state_prev, const void* d_adj_in, void* d_adj_out,
                      void* d_accum) {
   if (!s || !d_state_prev || !d_adj_in || !d_adj_out || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
   if (t < 1) return fail(MSD_EINVAL, "adjoint step t = %lld < 1", (long long)t);
   if (d_adj_in == d_adj_out) return fail(MSD_EINVAL, "adjoint input and output must differ");
@@ -710,6 +720,7 @@ int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_stat
                       void* d_adj_a, void* d_adj_b, void* d_accum, int32_t* h_result_in_b) {
   if (!s || !d_state_lo || !d_adj_a || !d_adj_b || !d_accum || !h_result_in_b)
     return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (t_lo < 0 || t_hi < t_lo) return fail(MSD_EINVAL, "steps (%lld, %lld]", (long long)t_lo, (long long)t_hi);
   if (t_hi - t_lo > 1 && !d_stack) return fail(MSD_EINVAL, "stack is NULL");
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
@@ -754,6 +765,7 @@ int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_stat
 
 int msd_adjoint_finish(msd_sim* s, const void* d_adj0, const void* d_accum, double* d_dL_dxi0, double* h_dL_dD) {
   if (!s || !d_adj0 || !d_accum) return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   msd::LaunchArgs a = base_args(s);
   a.adj_in = d_adj0;
   hipError_t e;
@@ -824,6 +836,7 @@ int msd_forward_checkpointed(msd_sim* s, int64_t nsteps, int64_t every, void* d_
 int msd_adjoint(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
                 double* d_dL_dxi0, double* h_dL_dD, void* d_scratch, size_t scratch_bytes) {
   if (!s || !d_dL_dxi || !d_scratch) return fail(MSD_EINVAL, "NULL argument");
+  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (nsteps < 0 || every < 1) return fail(MSD_EINVAL, "nsteps = %lld, every = %lld", (long long)nsteps,
                                            (long long)every);
   if (nsteps > 0 && !d_ckpts) return fail(MSD_EINVAL, "checkpoint buffer is NULL");

@@ -56,6 +56,8 @@ int validate_batch(const msd_problem* probs, int32_t count) {
     if (st != MSD_OK) return st;
     if (probs[b].lattice != probs[0].lattice || probs[b].precision != probs[0].precision)
       return fail(MSD_EINVAL, "mixture %d: all mixtures of a batch share lattice and precision", b);
+    if (probs[b].dilute)
+      return fail(MSD_EINVAL, "mixture %d: the batched sweep covers B of Eq. (2-10) only (dilute = 1)", b);
   }
   return MSD_OK;
 }

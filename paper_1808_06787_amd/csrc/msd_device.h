@@ -199,6 +199,7 @@ struct Problem {
   int32_t nx, ny, nz;
   int32_t relax;          // 0 paper rule (Eq. (3-16)), 1 SRT, 2 TRT
   int32_t linearized;     // 1: B at xi_ref
+  int32_t dilute;         // 1: B of the dilute-species approximation (diagonal)
   int32_t bc[6];          // x_lo, x_hi, y_lo, y_hi, z_lo, z_hi
   int64_t plane;          // elements between consecutive planes of a buffer
   double c_t;
@@ -342,6 +343,26 @@ __device__ __forceinline__ void ms_inverse(const T (&xb)[M], const T (&R)[M][M +
   invert_small<M, T>(A, K);
 }
 
+// K = A^-1 of the dilute-species approximation: diagonal, A_ii = 1 + (a/2)
+// (sum_{k != i, k < N} xb_k R_ik + xb_N R_iN) with xb_N = 1 - sum_k xb_k.
+template <int M, typename T>
+__device__ __forceinline__ void ms_inverse_dilute(const T (&xb)[M], const T (&R)[M][M + 1], T half_a,
+                                                  T (&K)[M][M]) {
+  T xN = T(1);
+#pragma unroll
+  for (int k = 0; k < M; ++k) xN -= xb[k];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T b = xN * R[i][M];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (k != i) b += xb[k] * R[i][k];
+#pragma unroll
+    for (int j = 0; j < M; ++j) K[i][j] = T(0);
+    K[i][i] = T(1) / (T(1) + half_a * b);
+  }
+}
+
 // Fused multiply-add in the sweep's precision.
 __device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -352,7 +373,10 @@ __device__ __forceinline__ double mad(double a, double b, double c) { return __b
 //   A_ii = a0_i + sum_{k != i} xi_k da_ik,   A_ik = xi_i ea_ik + ga_ik   (k != i)
 // with da_ik = (a/2)(R_ik - R_iN) = -ea_ik, ga_ik = 0, a0_i = 1 + (a/2) R_iN;
 // the linearised mode freezes A at xi_ref (da = ea = 0, a0 and ga hold
-// A(xi_ref)).  rule[] switches the relaxation rule without a branch: with
+// A(xi_ref)).  The dilute-species approximation (Eqs. (2-16), (2-17)) makes A
+// diagonal, A_ii = 1 + (a/2) sum_{k != i, k <= N} xi_k R_ik; with xi_N
+// eliminated that is a0_i + sum_{k != i} xi_k da_ik + xi_i ds_i, ds_i =
+// -(a/2) R_iN (collide_node with DIL = true).  rule[] switches the relaxation rule without a branch: with
 // sigma = 1 for Eq. (3-16) and TRT and 0 for SRT, and the TRT parameter
 // magic (3/16 for Eq. (3-16)), it holds (sigma, sigma/2, -sigma, 1 - sigma/2,
 // sigma - 2, 1 - 4 magic, 8 magic) (SRT: 0 and 1 for the last two; see
@@ -360,6 +384,7 @@ __device__ __forceinline__ double mad(double a, double b, double c) { return __b
 template <int M, typename T>
 struct CollideCoef {
   T a0[M];
+  T ds[M];          // dilute mode only: coefficient of xi_i in A_ii
   T da[M][M];
   T ea[M][M];
   T ga[M][M];
@@ -382,7 +407,10 @@ struct CollideCoef {
 // Direction 0 takes what the others leave of xi: sum_k f^+_k = xi exactly in
 // real arithmetic (sum_k neq_k = 0 because sum_k w_k = 1), so the species
 // totals change only by unbiased rounding, never by the rounded weights.
-template <int LAT, int M, typename T>
+//
+// DIL = true is the dilute-species approximation: A is diagonal, so K2 = 2 A^-1
+// needs one reciprocal per species and the relaxation couples no species.
+template <int LAT, int M, typename T, bool DIL = false>
 __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const CollideCoef<M, T>& cc) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
@@ -394,20 +422,34 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const C
     for (int k = 1; k < Q; ++k) s += f[i][k];
     xi[i] = s;
   }
-  T A[M][M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    T d = cc.a0[i];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      if (k == i) continue;
-      d = mad(xi[k], cc.da[i][k], d);
-      A[i][k] = mad(xi[i], cc.ea[i][k], cc.ga[i][k]);
-    }
-    A[i][i] = d;
-  }
   T nG[M][M], nhd[M];
-  invert_small<M, T>(A, nG, T(2));
+  if constexpr (DIL) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T d = mad(xi[i], cc.ds[i], cc.a0[i]);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        if (k == i) continue;
+        d = mad(xi[k], cc.da[i][k], d);
+        nG[i][k] = T(0);
+      }
+      nG[i][i] = T(2) * recip(d);
+    }
+  } else {
+    T A[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T d = cc.a0[i];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        if (k == i) continue;
+        d = mad(xi[k], cc.da[i][k], d);
+        A[i][k] = mad(xi[i], cc.ea[i][k], cc.ga[i][k]);
+      }
+      A[i][i] = d;
+    }
+    invert_small<M, T>(A, nG, T(2));
+  }
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     const T kd = nG[i][i];
@@ -431,7 +473,8 @@ __device__ __forceinline__ void collide_node(T (&f)[M][Lattice<LAT>::Q], const C
     for (int k = 1; k < Q; ++k) {
       T acc = f[i][k];
 #pragma unroll
-      for (int j = 0; j < M; ++j) acc = mad(nG[i][j], neq[j][k], acc);
+      for (int j = 0; j < M; ++j)
+        if (!DIL || j == i) acc = mad(nG[i][j], neq[j][k], acc);
       acc = mad(nhd[i], neq[i][L::opp(k)], acc);
       f[i][k] = acc;
       rest -= acc;

@@ -65,6 +65,7 @@ __device__ __forceinline__ void load_consts(const Consts<T>* __restrict__ c, Nod
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     nc.cc.a0[i] = c->a0[i];
+    nc.cc.ds[i] = c->ds[i];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       if (k == i) continue;
@@ -94,10 +95,10 @@ __global__ void k_constants(Problem p, int n_species, Consts<T>* out) {
       const double h = 0.5 * Lattice<LAT>::cs2;
       const double S = 1.0 / p.D[i][j] - 1.0 / p.D[i][M];
       if (p.linearized) {
-        ga = -h * p.xi_ref[i] * S;
+        ga = p.dilute ? 0.0 : -h * p.xi_ref[i] * S;
       } else {
         da = h * S;
-        ea = -h * S;
+        ea = p.dilute ? 0.0 : -h * S;
       }
     }
     out->da[i][j] = T(da);
@@ -107,17 +108,22 @@ __global__ void k_constants(Problem p, int n_species, Consts<T>* out) {
   if (t < 6 * kMaxSpecies) out->wall[t / kMaxSpecies][t % kMaxSpecies] = T(p.wall[t / kMaxSpecies][t % kMaxSpecies]);
   if (t < kMaxSpecies) {
     out->xref[t] = T(p.xi_ref[t]);
-    double a0 = 1.0;
+    double a0 = 1.0, ds = 0.0;
     if (t < M) {
       const double h = 0.5 * Lattice<LAT>::cs2;
       const double rN = 1.0 / p.D[t][M];
       double d = rN;
-      if (p.linearized)
+      if (p.linearized) {
         for (int k = 0; k < M; ++k)
           if (k != t) d += p.xi_ref[k] * (1.0 / p.D[t][k] - rN);
+        if (p.dilute) d -= p.xi_ref[t] * rN;   // xi_N R_iN carries -xi_i R_iN
+      } else if (p.dilute) {
+        ds = -h * rN;
+      }
       a0 = 1.0 + h * d;
     }
     out->a0[t] = T(a0);
+    out->ds[t] = T(ds);
   }
   if (t == 0) {
     // Eq. (3-16) is the product rule with 3/16; SRT has no even correction
@@ -179,7 +185,10 @@ __global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ s
   load_consts<M, T>(cst, nc);
   T f[M][Q];
   gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
-  collide_node<LAT, M, T>(f, nc.cc);
+  if (p.dilute)
+    collide_node<LAT, M, T, true>(f, nc.cc);
+  else
+    collide_node<LAT, M, T>(f, nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -726,7 +735,10 @@ __global__ __launch_bounds__(256) void k_step_lds(Problem p, const T* __restrict
       n.c[2] = (int32_t)(r / p.ny);
       T f[M][Q];
       gather_node<LAT, M, T>(lp, (const T*)A, n, pull, f, nc.wall);
-      collide_node<LAT, M, T>(f, nc.cc);
+      if (p.dilute)
+        collide_node<LAT, M, T, true>(f, nc.cc);
+      else
+        collide_node<LAT, M, T>(f, nc.cc);
 #pragma unroll
       for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -787,7 +799,10 @@ __global__ __launch_bounds__(256) void k_read(Problem p, const T* __restrict__ s
 #pragma unroll
   for (int i = 0; i < M; ++i) xb[i] = p.linearized ? nc.xref[i] : xi[i];
   T K[M][M];
-  ms_inverse<M, T>(xb, nc.R, T(0.5 * L::cs2), K);
+  if (p.dilute)
+    ms_inverse_dilute<M, T>(xb, nc.R, T(0.5 * L::cs2), K);
+  else
+    ms_inverse<M, T>(xb, nc.R, T(0.5 * L::cs2), K);
 #pragma unroll
   for (int i = 0; i < M; ++i) {
 #pragma unroll
@@ -1552,7 +1567,8 @@ hipError_t run(Op op, const LaunchArgs& a) {
     }
     case Op::Step: {
       // the vectorised kernel shares x-neighbours between lanes: axis-aligned lattices only
-      const int V = Lattice<LAT>::diag ? 0 : vec_width<T>(a);
+      // (and the full Maxwell-Stefan collision only)
+      const int V = (Lattice<LAT>::diag || a.p.dilute) ? 0 : vec_width<T>(a);
       const Tiling tl = make_tiling(a, V > 0 ? V : 1);
       const dim3 grid(tl.tiles), block(a.block_x, a.block_y);
       const T* src = static_cast<const T*>(a.src);

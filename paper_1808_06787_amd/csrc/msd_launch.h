@@ -26,12 +26,13 @@ struct Consts {
   // collision coefficients (CollideCoef): A = I + (a/2) B as an affine map of
   // the composition, and the relaxation-rule factors
   T a0[kMaxSpecies];
+  T ds[kMaxSpecies];
   T da[kMaxSpecies][kMaxSpecies];
   T ea[kMaxSpecies][kMaxSpecies];
   T ga[kMaxSpecies][kMaxSpecies];
   T rule[7];
 };
-constexpr size_t kConstsBytes = 4096;   // >= sizeof(Consts<double>) = 2648
+constexpr size_t kConstsBytes = 4096;   // >= sizeof(Consts<double>) = 2712
 static_assert(sizeof(Consts<double>) <= kConstsBytes, "constants block too small");
 
 // One mixture of a batch, as the batched sweep sees it (device array, read

@@ -30,12 +30,13 @@ def _dptr(t: torch.Tensor) -> int:
 
 def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", bc=None, xi_wall=None,
                  relax: str = "paper", c_t: float = 1.0, xi_ref=None, plane_pad: int = 0,
-                 trt_magic: float = F.MAGIC_PAPER):
+                 trt_magic: float = F.MAGIC_PAPER, dilute: bool = False):
     """Build an msd_problem plus the host arrays it points to (kept alive by the caller).
 
     bc: per axis (low, high) names from BCS; xi_wall: {(axis, side): (N,) values};
     relax: "paper" (Eq. (3-16)), "srt" or "trt" (even parameter from the product
-    rule with trt_magic; "paper" is the trt_magic = 3/16 case).
+    rule with trt_magic; "paper" is the trt_magic = 3/16 case); dilute: B of the
+    dilute-species approximation (Remark III) instead of Eq. (2-10).
     """
     d = DIMS[lattice]
     shape = tuple(int(s) for s in shape)
@@ -74,6 +75,7 @@ def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", 
     p.relax = RELAX[relax]
     p.trt_magic = float(trt_magic)
     p.plane_pad = int(plane_pad)
+    p.dilute = 1 if dilute else 0
     return p, keep
 
 
@@ -82,7 +84,7 @@ class Sim:
 
     def __init__(self, lattice: str, D, shape, precision: str = "f32", bc=None, xi_wall=None,
                  relax: str = "paper", c_t: float = 1.0, xi_ref=None, device=None, stream=None,
-                 plane_pad: int = 0, trt_magic: float = F.MAGIC_PAPER):
+                 plane_pad: int = 0, trt_magic: float = F.MAGIC_PAPER, dilute: bool = False):
         self.lib = F.lib()
         self.lattice = lattice
         self.shape = tuple(int(s) for s in shape)
@@ -90,7 +92,7 @@ class Sim:
         self.precision = precision
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.problem, self._keep = make_problem(lattice, D, shape, precision, bc, xi_wall, relax, c_t, xi_ref,
-                                                plane_pad, trt_magic)
+                                                plane_pad, trt_magic, dilute)
         self.N = self.problem.n_species
         self.m = self.N - 1
         status = C.c_int32(0)

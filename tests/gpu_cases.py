@@ -48,9 +48,9 @@ RELAX_NAMES = {"paper": ms.RELAX_PAPER, "srt": ms.RELAX_SRT, "trt": ms.RELAX_TRT
 
 
 def oracle_problem(lattice, D, shape, bc=None, xi_wall=None, relax="paper", xi_ref=None, c_t=1.0,
-                   trt_magic=ms.MAGIC_PAPER):
+                   trt_magic=ms.MAGIC_PAPER, dilute=False):
     return lbm.Problem(lattice, D, shape, bc=bc, xi_wall=xi_wall or {}, relax=RELAX_NAMES[relax],
-                       magic=trt_magic, xi_ref=xi_ref, c_t=c_t)
+                       magic=trt_magic, xi_ref=xi_ref, c_t=c_t, dilute=dilute)
 
 
 def oracle_run(prob, xi0, steps):
@@ -59,13 +59,13 @@ def oracle_run(prob, xi0, steps):
 
 
 def gpu_run(lattice, D, shape, precision, xi0, steps, bc=None, xi_wall=None, relax="paper", xi_ref=None,
-            c_t=1.0, launch=None, split=None, trt_magic=ms.MAGIC_PAPER):
+            c_t=1.0, launch=None, split=None, trt_magic=ms.MAGIC_PAPER, dilute=False):
     import torch
 
     from paper_1808_06787_amd.sim import Sim
 
     sim = Sim(lattice, D, shape, precision, bc=bc, xi_wall=xi_wall, relax=relax, c_t=c_t, xi_ref=xi_ref,
-              trt_magic=trt_magic)
+              trt_magic=trt_magic, dilute=dilute)
     if launch:
         sim.set_launch(**launch)
     sim.init(torch.from_numpy(np.ascontiguousarray(xi0)))

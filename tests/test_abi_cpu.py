@@ -42,6 +42,7 @@ def test_struct_layouts():
     assert C.sizeof(F.MsdProblem) == 120
     assert F.MsdProblem.c_t.offset == 64
     assert F.MsdProblem.bc.offset == 80
+    assert F.MsdProblem.dilute.offset == 108
     assert F.MsdProblem.trt_magic.offset == 112
     assert C.sizeof(F.MsdLaunch) == 32
     assert F.lib().msd_abi_version() == F.ABI_VERSION
@@ -89,7 +90,7 @@ def test_workspace_size_model():
         (lambda p: p.bc.__setitem__(0, 9), -1),
         (lambda p: setattr(p, "plane_pad", 32), -1),
         (lambda p: setattr(p, "plane_pad", -64), -1),
-        (lambda p: setattr(p, "reserved", 1), -1),
+        (lambda p: setattr(p, "dilute", 2), -1),
     ],
 )
 def test_validation_codes(mutate, code):

@@ -206,6 +206,60 @@ def test_diagonal_lattices_small_and_degenerate(shape):
         assert_parity(gpu, orc, "f64", f"{lattice} {shape} {launch}")
 
 
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7", "D2Q4", "D2Q9", "D3Q15"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("linearised", [False, True])
+def test_dilute_species_mode(lattice, precision, linearised):
+    """Remark III's diagonal B (Eqs. (2-16), (2-17)) with Dirichlet and zero-flux
+    walls, TRT relaxation, four species; the vector width is a hint the mode
+    ignores, and on D2Q5 it runs one step per pass."""
+    rng = np.random.default_rng(1500 + len(lattice))
+    N = 4
+    D = rand_D(rng, N)
+    shape = SHAPES[lattice]
+    bc = _bc(lattice, [("dirichlet", "zero_flux"), ("periodic", "periodic"), ("zero_flux", "dirichlet")])
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for side, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, side)] = rand_field(rng, N, ())
+    xref = rand_field(rng, N, ()) if linearised else None
+    xi0 = rand_field(rng, N, shape[::-1])
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax="trt", trt_magic=0.3,
+                                    xi_ref=xref, dilute=True), xi0, 30)
+    gpu = gpu_run(lattice, D, shape, precision, xi0, 30, bc=bc, xi_wall=walls, relax="trt", trt_magic=0.3,
+                  xi_ref=xref, dilute=True, launch=dict(vec=4, lds_resident=0))
+    assert_parity(gpu, orc, precision, f"{lattice} dilute {precision} lin={linearised}")
+
+
+def test_dilute_species_mode_lds_resident_and_rules():
+    """Small grid through the LDS-resident kernel; one step per pass on D2Q5; the
+    batch and the adjoint refuse the mode."""
+    import torch
+
+    from paper_1808_06787_amd import adjoint
+    from paper_1808_06787_amd._ffi import MsdError
+    from paper_1808_06787_amd.batch import Batch
+    from paper_1808_06787_amd.sim import Sim
+
+    rng = np.random.default_rng(1550)
+    D = rand_D(rng, 3)
+    shape = (21, 13)
+    xi0 = rand_field(rng, 3, shape[::-1])
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, dilute=True), xi0, 25)
+    gpu = gpu_run("D2Q5", D, shape, "f64", xi0, 25, dilute=True, launch=dict(lds_resident=1))
+    assert_parity(gpu, orc, "f64", "dilute lds")
+    sim = Sim("D2Q5", D, (512, 512), "f32", dilute=True)
+    assert sim.steps_per_pass() == 1
+    sim.init(torch.from_numpy(rand_field(rng, 3, (512, 512))))
+    ckpts = adjoint.forward_with_checkpoints(sim, 4, 2)
+    with pytest.raises(MsdError, match="dilute"):
+        adjoint.gradients(sim, ckpts, 4, torch.zeros((3, 512, 512), dtype=torch.float64, device="cuda"), 2)
+    sim.close()
+    with pytest.raises(MsdError, match="dilute"):
+        Batch([dict(D=D, shape=shape, dilute=True)], "D2Q5", "f32")
+
+
 def test_zero_steps_reads_initial_state():
     rng = np.random.default_rng(9)
     D = rand_D(rng, 4)
