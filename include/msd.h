@@ -110,8 +110,9 @@ typedef struct msd_problem {
                                Eqs. (2-16), (2-17), for every evolved species: B diagonal with
                                B_ii = sum_{k != i} xi_k / D_ik (each species follows Fick's law with
                                its own composition-dependent D_eff).  With linearized = 1 the
-                               diagonal is frozen at xi_ref.  Runs one step per pass; the adjoint
-                               entry points and the batch reject it (MSD_EINVAL) */
+                               diagonal is frozen at xi_ref.  Runs in the single-step and the
+                               temporally blocked sweeps; the adjoint entry points and the
+                               batch reject it (MSD_EINVAL) */
   double trt_magic;         /* MSD_RELAX_TRT only: the product parameter, finite and > 0 */
 } msd_problem;
 
@@ -280,15 +281,17 @@ typedef struct msd_launch {
                                with the intermediate time levels of a few rows on chip); 0 or
                                1: one step per pass.  The library takes the largest count up
                                to this one whose on-chip window fits the species count and
-                               precision (FP32: m <= 2 up to 6, m = 3 up to 4, m = 4 up to 2;
-                               FP64: m = 1 up to 6, m = 2 up to 2; else one step per pass).
+                               precision (FP32: m <= 2 up to 6, m = 3 up to 5, m = 4 up to 3;
+                               FP64: m = 1 up to 6, m = 2 up to 3; else one step per pass).
                                Default 6 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
-                               automatic, segments sized so that the launch holds about 1.35
-                               times the workgroups the device runs at once, at least 8 rows,
-                               and one step per pass when 8-row segments give fewer than 512
-                               workgroups (small domains run faster unblocked); negative or
-                               above 2^20 is MSD_EINVAL */
+                               automatic.  Forward: about k * 2 workgroups per CU in all,
+                               with k doubling (up to 64) while segments stay at least 128
+                               rows tall; the adjoint's blocked passes: about 1.35 times the
+                               workgroups the device runs at once.  Segments are at least 8
+                               rows, and one step per pass is used when 8-row segments give
+                               fewer than 512 workgroups (small domains run faster
+                               unblocked); negative or above 2^20 is MSD_EINVAL */
 } msd_launch;
 
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);

@@ -304,7 +304,7 @@ struct BlockedPlan {
 
 BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   BlockedPlan pl;
-  if (s->prob.lattice != MSD_D2Q5 || s->prob.dilute) return pl;   // blocked kernels: full model only
+  if (s->prob.lattice != MSD_D2Q5) return pl;
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)

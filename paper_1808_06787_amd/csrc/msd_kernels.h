@@ -455,7 +455,7 @@ __device__ __forceinline__ void for_each_iter(F&& f, std::integer_sequence<int, 
   (f(Iter<Js>{}), ...);
 }
 
-template <int M, typename T, int TB, int C, bool WALLS>
+template <int M, typename T, int TB, int C, bool WALLS, bool DIL = false>
 __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
                                              const Consts<T>* __restrict__ cst, int seg_rows, uint32_t tx,
                                              uint32_t seg, int nontemporal, int64_t rec_stride = 0) {
@@ -609,7 +609,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
           for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, ring[lp][s0][1][i]);
         }
       }
-      collide_node<2, M, T>(f, nc.cc);
+      collide_node<2, M, T, DIL>(f, nc.cc);
       if (lvl < TB) {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -668,6 +668,18 @@ __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restri
                                                     uint32_t tiles_x, int nontemporal, int64_t rec_stride) {
   blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
                                    nontemporal, rec_stride);
+}
+
+// The same sweep with the dilute-species collision (diagonal A).  Its register
+// needs differ from the full model's, so it asks the compiler for the two
+// waves per SIMD the host plan assumes.
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C, 2) void k_step_blocked_dilute(Problem p, const T* __restrict__ src,
+                                                              T* __restrict__ dst, const Consts<T>* __restrict__ cst,
+                                                              int seg_rows, uint32_t tiles_x, int nontemporal,
+                                                              int64_t rec_stride) {
+  blocked_tile<M, T, TB, C, WALLS, true>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
+                                         nontemporal, rec_stride);
 }
 
 // The blocked sweep over the mixtures of one batch class (equal m): workgroup
@@ -1488,12 +1500,22 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     T* dst = static_cast<T*>(a.dst);
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
     const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
-    if (walls)
-      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
-                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
-    else
-      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
-                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    const dim3 grid(tiles_x * segs);
+    if (a.p.dilute) {
+      if (walls)
+        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.p, src, dst,
+                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+      else
+        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.p, src, dst,
+                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    } else {
+      if (walls)
+        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
+                           a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+      else
+        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
+                           a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    }
     return hipSuccess;
   }
 }

@@ -211,8 +211,8 @@ def test_diagonal_lattices_small_and_degenerate(shape):
 @pytest.mark.parametrize("linearised", [False, True])
 def test_dilute_species_mode(lattice, precision, linearised):
     """Remark III's diagonal B (Eqs. (2-16), (2-17)) with Dirichlet and zero-flux
-    walls, TRT relaxation, four species; the vector width is a hint the mode
-    ignores, and on D2Q5 it runs one step per pass."""
+    walls, TRT relaxation, four species, one step per pass (the vector width is a
+    hint the mode ignores)."""
     rng = np.random.default_rng(1500 + len(lattice))
     N = 4
     D = rand_D(rng, N)
@@ -228,13 +228,13 @@ def test_dilute_species_mode(lattice, precision, linearised):
     orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax="trt", trt_magic=0.3,
                                     xi_ref=xref, dilute=True), xi0, 30)
     gpu = gpu_run(lattice, D, shape, precision, xi0, 30, bc=bc, xi_wall=walls, relax="trt", trt_magic=0.3,
-                  xi_ref=xref, dilute=True, launch=dict(vec=4, lds_resident=0))
+                  xi_ref=xref, dilute=True, launch=dict(vec=4, lds_resident=0, temporal=0))
     assert_parity(gpu, orc, precision, f"{lattice} dilute {precision} lin={linearised}")
 
 
 def test_dilute_species_mode_lds_resident_and_rules():
-    """Small grid through the LDS-resident kernel; one step per pass on D2Q5; the
-    batch and the adjoint refuse the mode."""
+    """Small grid through the LDS-resident kernel; on D2Q5 the same steps per pass
+    as the full model; the batch and the adjoint refuse the mode."""
     import torch
 
     from paper_1808_06787_amd import adjoint
@@ -249,12 +249,15 @@ def test_dilute_species_mode_lds_resident_and_rules():
     orc = oracle_run(oracle_problem("D2Q5", D, shape, dilute=True), xi0, 25)
     gpu = gpu_run("D2Q5", D, shape, "f64", xi0, 25, dilute=True, launch=dict(lds_resident=1))
     assert_parity(gpu, orc, "f64", "dilute lds")
-    sim = Sim("D2Q5", D, (512, 512), "f32", dilute=True)
-    assert sim.steps_per_pass() == 1
-    sim.init(torch.from_numpy(rand_field(rng, 3, (512, 512))))
+    n = 2048     # large enough for the blocked sweep (smaller domains run one step per pass)
+    full = Sim("D2Q5", D, (n, n), "f32")
+    sim = Sim("D2Q5", D, (n, n), "f32", dilute=True)
+    assert sim.steps_per_pass() == full.steps_per_pass() > 1
+    full.close()
+    sim.init(torch.from_numpy(rand_field(rng, 3, (n, n))))
     ckpts = adjoint.forward_with_checkpoints(sim, 4, 2)
     with pytest.raises(MsdError, match="dilute"):
-        adjoint.gradients(sim, ckpts, 4, torch.zeros((3, 512, 512), dtype=torch.float64, device="cuda"), 2)
+        adjoint.gradients(sim, ckpts, 4, torch.zeros((3, n, n), dtype=torch.float64, device="cuda"), 2)
     sim.close()
     with pytest.raises(MsdError, match="dilute"):
         Batch([dict(D=D, shape=shape, dilute=True)], "D2Q5", "f32")
@@ -370,6 +373,30 @@ def test_temporally_blocked_sweep(case, tb, N, precision):
         gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls,
                       launch=dict(temporal=tb, seg_rows=seg, lds_resident=0), split=[1, 6, 16])
         assert_parity(gpu, orc, precision, f"blocked tb={tb} seg={seg} {shape} N={N} {precision}")
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
+@pytest.mark.parametrize("tb", [2, 3, 5, 6])
+@pytest.mark.parametrize("N", [2, 3, 5])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_temporally_blocked_sweep_dilute(case, tb, N, precision):
+    """The dilute-species collision (Remark III) inside the blocked sweep, with
+    the linearised theory on every other case."""
+    shape, bc = BLOCKED_CASES[case]
+    rng = np.random.default_rng(700 + 10 * case + N)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xref = rand_field(rng, N, ()) if case % 2 else None
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 23
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls, xi_ref=xref, dilute=True), xi0, steps)
+    gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, xi_ref=xref, dilute=True,
+                  launch=dict(temporal=tb, seg_rows=7, lds_resident=0), split=[1, 6, 16])
+    assert_parity(gpu, orc, precision, f"blocked dilute tb={tb} {shape} N={N} {precision}")
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
