@@ -205,9 +205,16 @@ def test_blocked_plan_limits_without_device():
         ("D2Q5", 3, "f32", (5, 3), dict(seg_rows=16), 6),
         ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
         ("D1Q3", 3, "f64", (256,), dict(seg_rows=16), 1),
+        ("D2Q9", 3, "f32", (4096, 1024), dict(seg_rows=16), 1),
+        ("D3Q15", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
+        # the dilute-species mode has its own blocked kernel with the same limits
+        ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, dilute=True), 6),
+        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16, dilute=True), 3),
+        ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16, dilute=True), 3),
     ]
     for lattice, N, prec, shape, launch, want in cases:
-        p, keep = make_problem(lattice, D(N), shape, prec)
+        launch = dict(launch)
+        p, keep = make_problem(lattice, D(N), shape, prec, dilute=launch.pop("dilute", False))
         n, st = _ws(p)
         assert st == 0
         h = C.c_void_p()
