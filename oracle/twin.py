@@ -51,17 +51,22 @@ class Twin:
         self.M0inv = torch.linalg.inv(self.M0)
 
     def _B(self, xi_b: torch.Tensor, D: torch.Tensor) -> torch.Tensor:
-        """Eq. (2-10); xi_b: (*nodes, N)."""
+        """Eq. (2-10), or in dilute mode the diagonal B of Eqs. (2-16), (2-17);
+        xi_b: (*nodes, N)."""
         N = D.shape[0]
         m = N - 1
+        dilute = self.prob.dilute
         rows = []
         for i in range(m):
             cols = []
             for j in range(m):
                 if i != j:
-                    cols.append(xi_b[..., i] * (1.0 / D[i, N - 1] - 1.0 / D[i, j]))
+                    if dilute:
+                        cols.append(torch.zeros_like(xi_b[..., i]))
+                    else:
+                        cols.append(xi_b[..., i] * (1.0 / D[i, N - 1] - 1.0 / D[i, j]))
                 else:
-                    s = xi_b[..., i] / D[i, N - 1]
+                    s = torch.zeros_like(xi_b[..., i]) if dilute else xi_b[..., i] / D[i, N - 1]
                     for k in range(N):
                         if k != i:
                             s = s + xi_b[..., k] / D[i, k]

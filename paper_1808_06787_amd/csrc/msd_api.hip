@@ -305,6 +305,7 @@ struct BlockedPlan {
 BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   BlockedPlan pl;
   if (s->prob.lattice != MSD_D2Q5) return pl;
+  if (adjoint && s->prob.dilute) return pl;   // the blocked adjoint pass: B of Eq. (2-10) only
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)
@@ -668,15 +669,8 @@ size_t msd_adjoint_accum_bytes(const msd_sim* s) {
   return sizeof(double) * (size_t)adjoint_slots(s) * s->m * (s->m + 1);
 }
 
-// The hand-written adjoint differentiates the collision of Eq. (2-10) only.
-static int adjoint_supported(const msd_sim* s) {
-  if (s->prob.dilute) return fail(MSD_EINVAL, "the adjoint covers B of Eq. (2-10) only (dilute = 1)");
-  return MSD_OK;
-}
-
 int msd_adjoint_begin(msd_sim* s, void* d_accum) {
   if (!s || !d_accum) return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   msd::LaunchArgs a = base_args(s);
   a.partials = static_cast<double*>(d_accum);
   a.fill_count = (int64_t)(msd_adjoint_accum_bytes(s) / sizeof(double));
@@ -687,7 +681,6 @@ int msd_adjoint_begin(msd_sim* s, void* d_accum) {
 
 int msd_adjoint_seed(msd_sim* s, const double* d_dL_dxi, void* d_adj_out) {
   if (!s || !d_dL_dxi || !d_adj_out) return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
   msd::LaunchArgs a = base_args(s);
   a.xi0 = d_dL_dxi;
@@ -701,7 +694,6 @@ int msd_adjoint_seed(msd_sim* s, const double* d_dL_dxi, void* d_adj_out) {
 int msd_adjoint_step(msd_sim* s, int64_t t, const void* d_state_prev, const void* d_adj_in, void* d_adj_out,
                      void* d_accum) {
   if (!s || !d_state_prev || !d_adj_in || !d_adj_out || !d_accum) return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
   if (t < 1) return fail(MSD_EINVAL, "adjoint step t = %lld < 1", (long long)t);
   if (d_adj_in == d_adj_out) return fail(MSD_EINVAL, "adjoint input and output must differ");
@@ -720,7 +712,6 @@ int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_stat
                       void* d_adj_a, void* d_adj_b, void* d_accum, int32_t* h_result_in_b) {
   if (!s || !d_state_lo || !d_adj_a || !d_adj_b || !d_accum || !h_result_in_b)
     return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (t_lo < 0 || t_hi < t_lo) return fail(MSD_EINVAL, "steps (%lld, %lld]", (long long)t_lo, (long long)t_hi);
   if (t_hi - t_lo > 1 && !d_stack) return fail(MSD_EINVAL, "stack is NULL");
   if (!s->initialised) return fail(MSD_ESTATE, "adjoint before msd_init");
@@ -765,7 +756,6 @@ int msd_adjoint_steps(msd_sim* s, int64_t t_hi, int64_t t_lo, const void* d_stat
 
 int msd_adjoint_finish(msd_sim* s, const void* d_adj0, const void* d_accum, double* d_dL_dxi0, double* h_dL_dD) {
   if (!s || !d_adj0 || !d_accum) return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   msd::LaunchArgs a = base_args(s);
   a.adj_in = d_adj0;
   hipError_t e;
@@ -836,7 +826,6 @@ int msd_forward_checkpointed(msd_sim* s, int64_t nsteps, int64_t every, void* d_
 int msd_adjoint(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
                 double* d_dL_dxi0, double* h_dL_dD, void* d_scratch, size_t scratch_bytes) {
   if (!s || !d_dL_dxi || !d_scratch) return fail(MSD_EINVAL, "NULL argument");
-  if (adjoint_supported(s) != MSD_OK) return MSD_EINVAL;
   if (nsteps < 0 || every < 1) return fail(MSD_EINVAL, "nsteps = %lld, every = %lld", (long long)nsteps,
                                            (long long)every);
   if (nsteps > 0 && !d_ckpts) return fail(MSD_EINVAL, "checkpoint buffer is NULL");

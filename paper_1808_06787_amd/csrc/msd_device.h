@@ -781,7 +781,8 @@ __device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>&
 //   phi(l) = 2 (2 - l) / (2 - g1 l)  (the product rule; g1 = 1 - 4 magic, g0 = 8 magic,
 //   so phi'(l) = -2 g0 / (2 - g1 l)^2; for magic = 3/16 phi(l) = 8 (l - 2)/(l - 8)),
 // with sigma, g1, g0 = rule[0], rule[5], rule[6] of the collision coefficients.
-template <int LAT, int M, typename T>
+// DIL = true differentiates the dilute-species collision (diagonal B).
+template <int LAT, int M, typename T, bool DIL = false>
 __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT>::Q], const T (&u)[M][Lattice<LAT>::Q],
                                                      const T (&R)[M][M + 1], const T (&xref)[M], bool linearized,
                                                      const CollideCoef<M, T>& cc, T (&fbar)[M][Lattice<LAT>::Q],
@@ -801,7 +802,10 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
 #pragma unroll
   for (int i = 0; i < M; ++i) xb[i] = linearized ? xref[i] : xi[i];
   T K[M][M];
-  ms_inverse<M, T>(xb, R, h, K);
+  if constexpr (DIL)
+    ms_inverse_dilute<M, T>(xb, R, h, K);
+  else
+    ms_inverse<M, T>(xb, R, h, K);
   T L1[M][M], delta[M], dphi[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
@@ -911,6 +915,31 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
       Bbar[i][j] = -h * acc;
     }
 
+  if constexpr (DIL) {
+    // B_ij = 0 (i != j), B_ii = sum_{k != i, k < N} xb_k R_ik + xb_N R_iN with
+    // xb_N = 1 - sum_k xb_k: dB_ii/dxb_k = S_ik (k != i), dB_ii/dxb_i = -R_iN,
+    // dB_ii/dR_ik = xb_k, dB_ii/dR_iN = xb_N
+    T xN = T(1);
+#pragma unroll
+    for (int k = 0; k < M; ++k) xN -= xb[k];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const T bb = Bbar[i][i];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (j == i) continue;
+        if (!linearized) xibar[j] += bb * (R[i][j] - R[i][M]);
+        Rbar[i][j] += (double)(bb * xb[j]);
+      }
+      if (!linearized) xibar[i] -= bb * R[i][M];
+      Rbar[i][M] += (double)(bb * xN);
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fbar[i][k] += xibar[i];
+    return;
+  }
   // B_ij = -xb_i S_ij (i != j), B_ii = R_iN + sum_{k != i} xb_k S_ik,  S_ik = R_ik - R_iN
 #pragma unroll
   for (int i = 0; i < M; ++i) {

@@ -1046,7 +1046,8 @@ __global__ __launch_bounds__(256) void k_adjoint_seed(Problem p, const double* _
 // The adjoint sweep gives each thread kAdjointNodesPerThread nodes (from
 // consecutive block_x-wide strips along x), so that one workgroup reduction of
 // dL/dR covers 4 * 256 nodes.
-template <int LAT, int M, typename T, bool A32>
+// DIL: the dilute-species collision (a separate instantiation, chosen at launch).
+template <int LAT, int M, typename T, bool A32, bool DIL = false>
 __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __restrict__ state_prev,
                                                       const T* __restrict__ adj_in, T* __restrict__ adj_out,
                                                       const Consts<T>* __restrict__ cst, int pull, Tiling tl,
@@ -1084,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __rest
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) pull_dir<LAT, M, T, A32>(p, A, n, k, u, nc.wall, true);
-    collide_node_adjoint<LAT, M, T>(f, u, nc.R, nc.xref, p.linearized != 0, nc.cc, fb, Rbar);
+    collide_node_adjoint<LAT, M, T, DIL>(f, u, nc.R, nc.xref, p.linearized != 0, nc.cc, fb, Rbar);
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -1651,14 +1652,25 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::AdjointStep: {
       const Tiling tl = make_tiling(a, kAdjointNodesPerThread);
       const bool a32 = (uint64_t)a.p.plane * sizeof(T) < (1ull << 32);
-      if (a32)
-        hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, true>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0,
-                           a.stream, a.p, static_cast<const T*>(a.src), static_cast<const T*>(a.adj_in),
-                           static_cast<T*>(a.dst), cst, a.pull, tl, a.partials);
-      else
-        hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, false>), dim3(tl.tiles), dim3(a.block_x, a.block_y), 0,
-                           a.stream, a.p, static_cast<const T*>(a.src), static_cast<const T*>(a.adj_in),
-                           static_cast<T*>(a.dst), cst, a.pull, tl, a.partials);
+      const dim3 grid(tl.tiles), block(a.block_x, a.block_y);
+      const T* sp = static_cast<const T*>(a.src);
+      const T* ain = static_cast<const T*>(a.adj_in);
+      T* aout = static_cast<T*>(a.dst);
+      if (a.p.dilute) {
+        if (a32)
+          hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, true, true>), grid, block, 0, a.stream, a.p, sp, ain, aout,
+                             cst, a.pull, tl, a.partials);
+        else
+          hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, false, true>), grid, block, 0, a.stream, a.p, sp, ain, aout,
+                             cst, a.pull, tl, a.partials);
+      } else {
+        if (a32)
+          hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, true>), grid, block, 0, a.stream, a.p, sp, ain, aout, cst,
+                             a.pull, tl, a.partials);
+        else
+          hipLaunchKernelGGL((k_adjoint_step<LAT, M, T, false>), grid, block, 0, a.stream, a.p, sp, ain, aout, cst,
+                             a.pull, tl, a.partials);
+      }
       break;
     }
     case Op::AdjointXi0: {

@@ -226,3 +226,41 @@ def test_blocked_adjoint_fp32_ternary(case, tb):
     got = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=dict(temporal=tb, seg_rows=4),
                      bc=bc, xi_wall=walls)
     _compare(ref, got, 2e-4, f"fp32 blocked tb={tb} case {case}")
+
+
+DILUTE_CASES = [
+    ("D2Q5", (13, 9), (("dirichlet", "zero_flux"), ("periodic", "periodic")), None),
+    ("D1Q3", (23,), (("zero_flux", "dirichlet"),), None),
+    ("D3Q7", (6, 5, 4), (("zero_flux", "zero_flux"), ("periodic", "periodic"), ("dirichlet", "dirichlet")), None),
+    ("D2Q9", (12, 9), (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet")), None),
+    ("D2Q5", (11, 10), (("periodic", "periodic"), ("zero_flux", "dirichlet")), "linearised"),
+    # wide enough for blocked forward recomputation (the adjoint passes stay single steps)
+    ("D2Q5", (300, 11), (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet")), "blocked"),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DILUTE_CASES)))
+@pytest.mark.parametrize("relax", ["paper", "trt"])
+def test_adjoint_dilute_mode_matches_autograd_twin_fp64(case, relax):
+    """Remark III's diagonal B through the hand-written adjoint: loss, dL/dD and
+    dL/dxi(0) against the autograd twin of the oracle."""
+    lattice, shape, bc, extra = DILUTE_CASES[case]
+    N = 3 if extra == "blocked" else 4     # FP64 blocks up to m = 2
+    rng = np.random.default_rng(90 + case)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xref = rand_field(rng, N, ()) if extra == "linearised" else None
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    target = smooth_field(rng, N, shape[::-1], 0.15)
+    steps, every = 17, 5
+    p = oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls, relax=relax, trt_magic=0.35, xi_ref=xref,
+                       dilute=True)
+    ref = twin.misfit_gradients(p, xi0, target, steps)
+    launch = dict(temporal=3, seg_rows=4) if extra == "blocked" else None
+    got = _gpu_grads(lattice, D, shape, "f64", xi0, target, steps, every, launch=launch, bc=bc, xi_wall=walls,
+                     relax=relax, trt_magic=0.35, xi_ref=xref, dilute=True)
+    _compare(ref, got, 1e-10, f"{lattice} dilute {relax} {extra}")

@@ -17,7 +17,7 @@ def _rand_D(rng, n, lo=0.03, hi=0.3):
     return D
 
 
-def _problem(name, rng, N, relax=ms.RELAX_PAPER, walls=True, lin=False):
+def _problem(name, rng, N, relax=ms.RELAX_PAPER, walls=True, lin=False, dilute=False):
     shape = {1: (7,), 2: (6, 5), 3: (4, 3, 3)}[int(name[1])]
     d = len(shape)
     bc = [("periodic", "periodic")] * d
@@ -31,7 +31,7 @@ def _problem(name, rng, N, relax=ms.RELAX_PAPER, walls=True, lin=False):
         x = rng.uniform(0.2, 1.0, N)
         xref = x / x.sum()
     return lbm.Problem(name, _rand_D(rng, N), shape, bc=tuple(bc), xi_wall=xi_wall, relax=relax, xi_ref=xref,
-                       magic=0.3 if relax == ms.RELAX_TRT else ms.MAGIC_PAPER)
+                       magic=0.3 if relax == ms.RELAX_TRT else ms.MAGIC_PAPER, dilute=dilute)
 
 
 def _field(rng, p):
@@ -41,9 +41,10 @@ def _field(rng, p):
 
 @pytest.mark.parametrize("name", LATS)
 @pytest.mark.parametrize("relax", [ms.RELAX_PAPER, ms.RELAX_SRT, ms.RELAX_TRT])
-def test_twin_forward_equals_oracle(name, relax):
+@pytest.mark.parametrize("dilute", [False, True])
+def test_twin_forward_equals_oracle(name, relax, dilute):
     rng = np.random.default_rng(31)
-    p = _problem(name, rng, 4, relax)
+    p = _problem(name, rng, 4, relax, dilute=dilute)
     xi0 = _field(rng, p)
     f_np = lbm.run(p, xi0, 6)
     tw = twin.Twin(p)
@@ -58,9 +59,10 @@ def _loss_np(p, xi0, target, steps):
 
 @pytest.mark.parametrize("name", LATS)
 @pytest.mark.parametrize("lin", [False, True])
-def test_twin_gradients_equal_finite_differences(name, lin):
+@pytest.mark.parametrize("dilute", [False, True])
+def test_twin_gradients_equal_finite_differences(name, lin, dilute):
     rng = np.random.default_rng(32)
-    p = _problem(name, rng, 3, lin=lin)
+    p = _problem(name, rng, 3, lin=lin, dilute=dilute)
     xi0 = _field(rng, p)
     target = _field(rng, p)
     steps = 5
@@ -73,8 +75,10 @@ def test_twin_gradients_equal_finite_differences(name, lin):
             Dp, Dm = p.D.copy(), p.D.copy()
             Dp[i, j] = Dp[j, i] = p.D[i, j] + h
             Dm[i, j] = Dm[j, i] = p.D[i, j] - h
-            pp = lbm.Problem(p.lattice, Dp, p.shape, bc=p.bc, xi_wall=p.xi_wall, relax=p.relax, xi_ref=p.xi_ref)
-            pm = lbm.Problem(p.lattice, Dm, p.shape, bc=p.bc, xi_wall=p.xi_wall, relax=p.relax, xi_ref=p.xi_ref)
+            pp = lbm.Problem(p.lattice, Dp, p.shape, bc=p.bc, xi_wall=p.xi_wall, relax=p.relax, xi_ref=p.xi_ref,
+                             dilute=p.dilute)
+            pm = lbm.Problem(p.lattice, Dm, p.shape, bc=p.bc, xi_wall=p.xi_wall, relax=p.relax, xi_ref=p.xi_ref,
+                             dilute=p.dilute)
             fd = (_loss_np(pp, xi0, target, steps) - _loss_np(pm, xi0, target, steps)) / (2 * h)
             assert abs(fd - gD[i, j]) <= 1e-6 * max(abs(fd), 1e-3), (i, j, fd, gD[i, j])
     v = rng.standard_normal(size=xi0.shape)
