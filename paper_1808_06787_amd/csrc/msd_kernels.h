@@ -174,7 +174,8 @@ __device__ __forceinline__ bool tile_node(const Problem& p, const Tiling& tl, No
 // ---------------------------------------------------------------------------
 // One fused time step: pull-propagate (with face rules), collide, store.
 // ---------------------------------------------------------------------------
-template <int LAT, int M, typename T>
+// DIL: the dilute-species collision (a separate instantiation, chosen at launch).
+template <int LAT, int M, typename T, bool DIL = false>
 __global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ src, T* __restrict__ dst,
                                                const Consts<T>* __restrict__ cst, int pull, Tiling tl,
                                                int nontemporal) {
@@ -185,10 +186,7 @@ __global__ __launch_bounds__(256) void k_step(Problem p, const T* __restrict__ s
   load_consts<M, T>(cst, nc);
   T f[M][Q];
   gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
-  if (p.dilute)
-    collide_node<LAT, M, T, true>(f, nc.cc);
-  else
-    collide_node<LAT, M, T>(f, nc.cc);
+  collide_node<LAT, M, T, DIL>(f, nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -1611,7 +1609,10 @@ hipError_t run(Op op, const LaunchArgs& a) {
         else
           done = false;
       }
-      if (!done)
+      if (!done && a.p.dilute)
+        hipLaunchKernelGGL((k_step<LAT, M, T, true>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
+                           a.nontemporal);
+      else if (!done)
         hipLaunchKernelGGL((k_step<LAT, M, T>), grid, block, 0, a.stream, a.p, src, dst, cst, a.pull, tl,
                            a.nontemporal);
       break;
