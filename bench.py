@@ -358,7 +358,7 @@ def main():
                     help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sweep would shard by slabs with halo exchange; not implemented)", file=sys.stderr)
         raise SystemExit(2)
     import torch
