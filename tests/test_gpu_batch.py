@@ -191,7 +191,8 @@ def test_batch_state_rules():
 
 def test_batched_workload_sampled():
     """The 256-mixture workload (N in {3,4,5}, sides 64..1024) after 9 steps of the
-    default schedule (blocked passes of 4, 3 and 2 steps by class): sampled nodes
+    default schedule (blocked passes by class, as many steps per pass as each
+    class's species count allows, with remainders): sampled nodes
     of several mixtures against the oracle on their light cones."""
     import workloads
     from paper_1808_06787_amd.batch import Batch
