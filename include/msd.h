@@ -111,8 +111,9 @@ typedef struct msd_problem {
                                B_ii = sum_{k != i} xi_k / D_ik (each species follows Fick's law with
                                its own composition-dependent D_eff).  With linearized = 1 the
                                diagonal is frozen at xi_ref.  Runs in the single-step and the
-                               temporally blocked sweeps and in the adjoint (single adjoint
-                               steps); the batch rejects it (MSD_EINVAL) */
+                               temporally blocked sweeps, in batches (dilute mixtures in
+                               launches of their own) and in the adjoint (single adjoint
+                               steps) */
   double trt_magic;         /* MSD_RELAX_TRT only: the product parameter, finite and > 0 */
 } msd_problem;
 

@@ -37,6 +37,7 @@ struct Range {
   int mmax = 0;
   uint32_t begin = 0, count = 0;
   int tb = 0, seg = 0, walls = 0;
+  int dilute = 0;            // all members use the dilute-species collision
   uint32_t bbegin = 0, bcount = 0;
   std::vector<int> members;
 };
@@ -56,8 +57,6 @@ int validate_batch(const msd_problem* probs, int32_t count) {
     if (st != MSD_OK) return st;
     if (probs[b].lattice != probs[0].lattice || probs[b].precision != probs[0].precision)
       return fail(MSD_EINVAL, "mixture %d: all mixtures of a batch share lattice and precision", b);
-    if (probs[b].dilute)
-      return fail(MSD_EINVAL, "mixture %d: the batched sweep covers B of Eq. (2-10) only (dilute = 1)", b);
   }
   return MSD_OK;
 }
@@ -167,23 +166,39 @@ int build_tiles(msd_batch* b) {
   }
   std::vector<int> idx(b->count);
   for (int i = 0; i < b->count; ++i) idx[i] = i;
+  // Mixtures with the full and with the dilute-species collision run in
+  // separate launches (different kernel instantiations).
   std::vector<std::vector<int>> groups;
+  std::vector<int> group_dilute;
   const bool by_class = sc.mode == MSD_BATCH_PER_CLASS || (b->lattice == MSD_D2Q5 && sc.temporal >= 2);
-  if (by_class) {
-    for (int m = 1; m < MSD_MAX_SPECIES; ++m) {
+  for (int dil = 0; dil <= 1; ++dil) {
+    if (by_class) {
+      for (int m = 1; m < MSD_MAX_SPECIES; ++m) {
+        std::vector<int> g;
+        for (int i : idx)
+          if (b->mem[i].m == m && (b->mem[i].prob.dilute != 0) == (dil != 0)) g.push_back(i);
+        if (!g.empty()) {
+          groups.push_back(g);
+          group_dilute.push_back(dil);
+        }
+      }
+    } else {
       std::vector<int> g;
       for (int i : idx)
-        if (b->mem[i].m == m) g.push_back(i);
-      if (!g.empty()) groups.push_back(g);
+        if ((b->mem[i].prob.dilute != 0) == (dil != 0)) g.push_back(i);
+      if (!g.empty()) {
+        groups.push_back(g);
+        group_dilute.push_back(dil);
+      }
     }
-  } else {
-    groups.push_back(idx);
   }
   b->h_tiles.clear();
   b->ranges.clear();
-  for (const auto& g : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& g = groups[gi];
     Range r;
     r.members = g;
+    r.dilute = group_dilute[gi];
     r.begin = (uint32_t)b->h_tiles.size();
     std::vector<uint32_t> nt(g.size());
     for (size_t j = 0; j < g.size(); ++j) {
@@ -389,6 +404,7 @@ int msd_batch_step(msd_batch* b, int64_t nsteps) {
   for (const Range& r : b->ranges) {
     int cur = b->mem[r.members[0]].cur;
     a.m = r.mmax;
+    a.dilute = r.dilute;
     int64_t n = 0;
     while (n < nsteps) {
       const int64_t t = b->t + n;

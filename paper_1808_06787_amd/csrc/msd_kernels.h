@@ -683,11 +683,10 @@ __global__ __launch_bounds__(C, 2) void k_step_blocked_dilute(Problem p, const T
 // The blocked sweep over the mixtures of one batch class (equal m): workgroup
 // g takes tile table entry tile_begin + g, i.e. (mixture, column tile + segment
 // * column tiles of that mixture); cur selects each mixture's source buffer.
-template <int M, typename T, int TB, int C, bool WALLS>
-__global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __restrict__ insts,
-                                                          const BatchTile* __restrict__ tiles, uint32_t tile_begin,
-                                                          char* __restrict__ ws, int cur, int seg_rows,
-                                                          int nontemporal) {
+template <int M, typename T, int TB, int C, bool WALLS, bool DIL>
+__device__ __forceinline__ void batch_blocked_body(const BatchInst* __restrict__ insts,
+                                                   const BatchTile* __restrict__ tiles, uint32_t tile_begin,
+                                                   char* __restrict__ ws, int cur, int seg_rows, int nontemporal) {
   constexpr int W = C - 2 * TB;
   // The table entries are uniform but read by vector loads: move the fields the
   // tile uses to scalar registers (the tile addresses planes from scalar bases).
@@ -709,7 +708,26 @@ __global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __res
   const T* src = reinterpret_cast<const T*>(ws + u64(I->half_off[cur]));
   T* dst = reinterpret_cast<T*>(ws + u64(I->half_off[1 - cur]));
   const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + u64(I->consts_off));
-  blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, bt.tile % tiles_x, bt.tile / tiles_x, nontemporal);
+  blocked_tile<M, T, TB, C, WALLS, DIL>(p, src, dst, cst, seg_rows, bt.tile % tiles_x, bt.tile / tiles_x,
+                                        nontemporal);
+}
+
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __restrict__ insts,
+                                                          const BatchTile* __restrict__ tiles, uint32_t tile_begin,
+                                                          char* __restrict__ ws, int cur, int seg_rows,
+                                                          int nontemporal) {
+  batch_blocked_body<M, T, TB, C, WALLS, false>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal);
+}
+
+// A class of dilute-species mixtures (diagonal A); two waves per SIMD as for
+// k_step_blocked_dilute.
+template <int M, typename T, int TB, int C, bool WALLS>
+__global__ __launch_bounds__(C, 2) void k_batch_step_blocked_dilute(const BatchInst* __restrict__ insts,
+                                                                    const BatchTile* __restrict__ tiles,
+                                                                    uint32_t tile_begin, char* __restrict__ ws, int cur,
+                                                                    int seg_rows, int nontemporal) {
+  batch_blocked_body<M, T, TB, C, WALLS, true>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal);
 }
 
 // ---------------------------------------------------------------------------
@@ -952,7 +970,7 @@ __global__ void k_diag_final(const double* __restrict__ partials, int blocks, in
 // and constants; the number of evolved species (uniform per workgroup) selects
 // the template instance, up to MMAX.
 // ---------------------------------------------------------------------------
-template <int LAT, int M, typename T>
+template <int LAT, int M, typename T, bool DIL>
 __device__ __forceinline__ void batch_tile_body(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
                                                 const Consts<T>* __restrict__ cst, uint32_t tile, int pull,
                                                 int nontemporal) {
@@ -973,7 +991,7 @@ __device__ __forceinline__ void batch_tile_body(const Problem& p, const T* __res
   load_consts<M, T>(cst, nc);
   T f[M][Q];
   gather_node<LAT, M, T>(p, src, n, pull != 0, f, nc.wall, nontemporal);
-  collide_node<LAT, M, T>(f, nc.cc);
+  collide_node<LAT, M, T, DIL>(f, nc.cc);
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -981,7 +999,8 @@ __device__ __forceinline__ void batch_tile_body(const Problem& p, const T* __res
       store_value(dst + (int64_t)(i * Q + k) * p.plane + n.idx, f[i][k], nontemporal & NT_STORE);
 }
 
-template <int LAT, int MMAX, typename T>
+// DIL: a range of dilute-species mixtures (a separate instantiation).
+template <int LAT, int MMAX, typename T, bool DIL = false>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchInst* __restrict__ insts,
                                                     const BatchTile* __restrict__ tiles, uint32_t tile_begin,
                                                     uint32_t ntiles, char* __restrict__ ws, int cur, int pull,
@@ -999,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchInst* __restrict_
   const Problem& p = I->p;
 #define MSD_BATCH_CASE(MM)                                                              \
   case MM:                                                                              \
-    if constexpr (MM <= MMAX) batch_tile_body<LAT, MM, T>(p, src, dst, cst, bt.tile, pull, nontemporal); \
+    if constexpr (MM <= MMAX) batch_tile_body<LAT, MM, T, DIL>(p, src, dst, cst, bt.tile, pull, nontemporal); \
     break;
   switch (m) {
     MSD_BATCH_CASE(1)
@@ -1526,12 +1545,23 @@ hipError_t launch_batch_blocked_tb(const LaunchArgs& a) {
     return hipErrorInvalidValue;
   } else {
     if (a.ntiles == 0) return hipSuccess;
-    if (a.walls)
-      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), dim3(a.ntiles), dim3(C), (blocked_lds_pad<M, T, TB, C>(a)), a.stream, a.insts,
-                         a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
-    else
-      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), dim3(a.ntiles), dim3(C), (blocked_lds_pad<M, T, TB, C>(a)), a.stream, a.insts,
-                         a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+    const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
+    const dim3 grid(a.ntiles);
+    if (a.dilute) {
+      if (a.walls)
+        hipLaunchKernelGGL((k_batch_step_blocked_dilute<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.insts,
+                           a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+      else
+        hipLaunchKernelGGL((k_batch_step_blocked_dilute<M, T, TB, C, false>), grid, dim3(C), pad, a.stream,
+                           a.insts, a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+    } else {
+      if (a.walls)
+        hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.insts, a.tiles,
+                           a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+      else
+        hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.insts, a.tiles,
+                           a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+    }
     return hipSuccess;
   }
 }
@@ -1729,9 +1759,14 @@ hipError_t run(Op op, const LaunchArgs& a) {
     case Op::BatchStep:
       // here M is the largest number of evolved species in the launch
       if (a.ntiles == 0) break;
-      hipLaunchKernelGGL((k_batch_step<LAT, M, T>), dim3(a.ntiles), dim3(a.block_x, a.block_y), 0, a.stream,
-                         a.insts, a.tiles, a.tile_begin, a.ntiles, a.ws, a.cur, a.pull, a.xcd_remap,
-                         a.nontemporal);
+      if (a.dilute)
+        hipLaunchKernelGGL((k_batch_step<LAT, M, T, true>), dim3(a.ntiles), dim3(a.block_x, a.block_y), 0, a.stream,
+                           a.insts, a.tiles, a.tile_begin, a.ntiles, a.ws, a.cur, a.pull, a.xcd_remap,
+                           a.nontemporal);
+      else
+        hipLaunchKernelGGL((k_batch_step<LAT, M, T>), dim3(a.ntiles), dim3(a.block_x, a.block_y), 0, a.stream,
+                           a.insts, a.tiles, a.tile_begin, a.ntiles, a.ws, a.cur, a.pull, a.xcd_remap,
+                           a.nontemporal);
       break;
   }
   return hipGetLastError();

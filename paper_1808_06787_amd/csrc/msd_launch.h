@@ -68,6 +68,7 @@ struct LaunchArgs {
   int tb = 0;                // steps per pass of the temporally blocked sweep
   int seg_rows = 32;         // rows per workgroup segment of the blocked sweep
   int walls = 0;             // blocked batch launch: some mixture has a non-periodic face
+  int dilute = 0;            // batch launches: the range holds dilute-species mixtures
   int64_t rec_stride = 0;    // blocked sweep: elements between recorded states (0: no recording)
   const void* states[4] = {nullptr, nullptr, nullptr, nullptr};   // blocked adjoint: s_{t-1}, ..., s_{t-TB}
   int64_t accum_slots = 0;   // adjoint: workgroup slots of the dL/dR accumulator

@@ -66,6 +66,29 @@ def test_batch_matches_oracle_per_mixture(lattice, precision):
     b.close()
 
 
+@pytest.mark.parametrize("lattice", ["D2Q5", "D3Q7", "D2Q9"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("sched", [None, dict(temporal=0, mode="fused"), dict(temporal=3, seg_rows=8)])
+def test_batch_with_dilute_species_mixtures(lattice, precision, sched):
+    """Mixtures with the dilute-species collision (Remark III) next to full ones:
+    they run in launches of their own (fused, per class, blocked), each against
+    the oracle (blocked passes apply to D2Q5; the other lattices take single steps)."""
+    rng = np.random.default_rng(75)
+    specs, fields = _specs(lattice, rng)
+    for i, sp in enumerate(specs):
+        sp["dilute"] = i % 2 == 1
+    b = _batch(lattice, precision, specs, fields)
+    if sched:
+        b.set_schedule(**sched)
+    b.step(19)
+    got = _read_all(b)
+    for i, (sp, f) in enumerate(zip(specs, fields)):
+        p = oracle_problem(lattice, sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"],
+                           trt_magic=sp["trt_magic"], dilute=sp["dilute"])
+        assert_parity(got[i], oracle_run(p, f, 19), precision, f"{lattice} mixture {i} dilute={sp['dilute']}")
+    b.close()
+
+
 def test_schedules_are_bitwise_identical_and_match_reference_schedule():
     """One-step schedules move only the mapping of nodes to workgroups (bitwise
     identical fields); blocked passes run the same per-node arithmetic in another

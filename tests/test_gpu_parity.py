@@ -232,11 +232,9 @@ def test_dilute_species_mode(lattice, precision, linearised):
     assert_parity(gpu, orc, precision, f"{lattice} dilute {precision} lin={linearised}")
 
 
-def test_dilute_species_mode_lds_resident_and_rules():
+def test_dilute_species_mode_lds_resident_and_steps_per_pass():
     """Small grid through the LDS-resident kernel; on D2Q5 the same steps per pass
-    as the full model; the batch refuses the mode."""
-    from paper_1808_06787_amd._ffi import MsdError
-    from paper_1808_06787_amd.batch import Batch
+    as the full model."""
     from paper_1808_06787_amd.sim import Sim
 
     rng = np.random.default_rng(1550)
@@ -252,8 +250,6 @@ def test_dilute_species_mode_lds_resident_and_rules():
     assert sim.steps_per_pass() == full.steps_per_pass() > 1
     full.close()
     sim.close()
-    with pytest.raises(MsdError, match="dilute"):
-        Batch([dict(D=D, shape=shape, dilute=True)], "D2Q5", "f32")
 
 
 def test_zero_steps_reads_initial_state():
