@@ -162,6 +162,30 @@ def test_table_I_on_the_gpu():
         s.close()
 
 
+@pytest.mark.parametrize("lattice,shape", [("D2Q9", (200, 90)), ("D3Q15", (40, 30, 20))])
+def test_sim_autotuner_on_diagonal_lattices(tmp_path, lattice, shape):
+    """The library's candidate list on lattices with diagonal directions has no
+    vector widths (that kernel is axial only); the tuned run continues as if untuned."""
+    from paper_1808_06787_amd import autotune
+
+    rng = np.random.default_rng(77)
+    D = rand_D(rng, 3)
+    xi0 = smooth_field(rng, 3, shape[::-1], 0.1)
+    ref = _sim(lattice, D, shape, "f64", xi0)
+    ref.step(9)
+    want = ref.read()[0].cpu().numpy()
+    ref.close()
+    s = _sim(lattice, D, shape, "f64", xi0)
+    s.step(4)
+    res = autotune.tune_sim(s, cache_path=str(tmp_path / "tune.txt"), steps=2)
+    # 5 tile shapes x XCD remapping on/off x streaming hints on/off, no vector widths
+    assert len(res["trials"]) == 20 and res["best"]["vec"] == 0
+    assert s.time == 4 and s.get_launch() == res["best"]
+    s.step(5)
+    np.testing.assert_allclose(s.read()[0].cpu().numpy(), want, rtol=0, atol=1e-14)
+    s.close()
+
+
 def test_sim_autotuner_keeps_state_and_caches(tmp_path):
     """msd_tune times candidate launches from a saved state and restores it: the
     run continues as if untuned (to FP32 rounding: the chosen launch may take
