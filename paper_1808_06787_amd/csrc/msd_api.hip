@@ -300,6 +300,7 @@ msd::LaunchArgs base_args(const msd_sim* s) {
 struct BlockedPlan {
   int tb = 0;
   int seg = 0;
+  int cols = msd::kBlockedCols;   // tile width of full passes (remainders use kBlockedCols)
 };
 
 BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
@@ -315,7 +316,10 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
       break;
     }
   if (tb == 0) return pl;
-  const int64_t W = msd::kBlockedCols - 2 * tb;
+  if (!adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
+      s->prob.nx >= msd::kWideMinNx)
+    pl.cols = msd::kBlockedColsWide;
+  const int64_t W = pl.cols - 2 * tb;
   const int64_t tiles_x = (s->prob.nx + W - 1) / W;
   auto groups = [&](int64_t seg) { return tiles_x * ((s->prob.ny + seg - 1) / seg); };
   int seg = s->launch.seg_rows;
@@ -325,6 +329,7 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
     if (cached == 0) {
       msd::LaunchArgs a = base_args(s);
       a.tb = tb;
+      a.cols = pl.cols;
       a.adjoint = adjoint ? 1 : 0;
       int res[2] = {0, 0};
       a.out_int = res;
@@ -522,6 +527,7 @@ int msd_step(msd_sim* s, int64_t nsteps) {
       // the first step after msd_init reads pre-collision values and is always
       // a single step
       a.tb = pass;
+      a.cols = pass == tb ? plan.cols : 0;
       a.seg_rows = plan.seg;
       e = dispatch(msd::Op::StepBlocked, a);
       done = pass;
@@ -633,6 +639,7 @@ int msd_record(msd_sim* s, int64_t nsteps, void* d_stack) {
     if (plan.tb >= 2 && s->t + n > 0 && pass >= 2) {
       // one pass writes the states after each of its steps into consecutive slots
       a.tb = pass;
+      a.cols = pass == plan.tb ? plan.cols : 0;
       a.seg_rows = plan.seg;
       a.rec_stride = (int64_t)(sb / (size_t)s->prob.precision);
       e = dispatch(msd::Op::StepBlocked, a);

@@ -1478,6 +1478,15 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
       e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint_blocked<M, T, TB, CA, true>, CA, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint_blocked<M, T, TB, CA, false>, CA, 0);
     }
+  } else if (a.cols == kBlockedColsWide) {
+    if constexpr (blocked_wide_ok(M, TB, (int)sizeof(T))) {
+      constexpr int CW = kBlockedColsWide;
+      const size_t pad = blocked_lds_pad<M, T, TB, CW>(a);
+      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, true>, CW, pad)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, false>, CW, pad);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
     if constexpr (C > 0) {
       const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
@@ -1504,9 +1513,35 @@ hipError_t launch_adjoint_blocked(const LaunchArgs& a) {
   return hipErrorInvalidValue;
 }
 
+// The wide (512-column) tile for the full model, where the host plan chose it.
+template <int M, typename T, int TB>
+hipError_t launch_blocked_wide(const LaunchArgs& a) {
+  if constexpr (!blocked_wide_ok(M, TB, (int)sizeof(T))) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int C = kBlockedColsWide, W = C - 2 * TB;
+    if (a.p.dilute) return hipErrorInvalidValue;
+    const uint32_t tiles_x = (uint32_t)((a.p.nx + W - 1) / W);
+    const uint32_t segs = (uint32_t)((a.p.ny + a.seg_rows - 1) / a.seg_rows);
+    const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
+    const T* src = static_cast<const T*>(a.src);
+    T* dst = static_cast<T*>(a.dst);
+    const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
+    const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
+    if (walls)
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    else
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p,
+                         src, dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    return hipSuccess;
+  }
+}
+
 template <int M, typename T, int TB>
 hipError_t launch_blocked_tb(const LaunchArgs& a) {
   constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
+  if (a.cols == kBlockedColsWide) return launch_blocked_wide<M, T, TB>(a);
   if constexpr (C == 0) {
     return hipErrorInvalidValue;
   } else {

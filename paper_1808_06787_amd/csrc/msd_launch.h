@@ -68,6 +68,7 @@ struct LaunchArgs {
   int tb = 0;                // steps per pass of the temporally blocked sweep
   int seg_rows = 32;         // rows per workgroup segment of the blocked sweep
   int walls = 0;             // blocked batch launch: some mixture has a non-periodic face
+  int cols = 0;              // blocked sweep of one mixture: tile width (0: kBlockedCols)
   int dilute = 0;            // batch launches: the range holds dilute-species mixtures
   int64_t rec_stride = 0;    // blocked sweep: elements between recorded states (0: no recording)
   const void* states[4] = {nullptr, nullptr, nullptr, nullptr};   // blocked adjoint: s_{t-1}, ..., s_{t-TB}
@@ -122,6 +123,16 @@ constexpr int blocked_cols(int m, int tb, int bytes) {
              : 0;
 }
 
+// Wide tiles for wide domains: 512 columns halve the share of the 2 tb halo
+// columns per tile.  Measured on ternary FP32 at six steps per pass: 8192^2
+// 8 % faster, 4096^2 within run-to-run spread, 2048^2 and the batch slower; so
+// the host plan takes them from kWideMinNx columns on, for m <= 2 in FP32 at
+// tb = 6 (80 KiB of LDS exchange per workgroup; 142 VGPRs, one workgroup per
+// CU, two waves per SIMD as with 256 columns).
+constexpr int kBlockedColsWide = 512;
+constexpr int kWideMinNx = 6144;
+constexpr bool blocked_wide_ok(int m, int tb, int bytes) { return bytes == 4 && m <= 2 && tb == 6; }
+
 // Temporally blocked adjoint sweep (k_adjoint_blocked): workgroup width for m
 // evolved species, tb adjoint steps per pass and value size, or 0 when its
 // register window (7m values per level) next to the pulled state, the incoming
@@ -133,7 +144,7 @@ constexpr int adjoint_blocked_cols(int m, int tb, int bytes) {
              : 0;
 }
 
-// Nodes per thread of the adjoint sweep// Nodes per thread of the adjoint sweep (see k_adjoint_step).
+// Nodes per thread of the adjoint sweep (see k_adjoint_step).
 constexpr int kAdjointNodesPerThread = 4;
 
 // Largest domain (nodes) the single-workgroup LDS-resident sweep accepts for a

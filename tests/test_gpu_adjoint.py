@@ -264,3 +264,19 @@ def test_adjoint_dilute_mode_matches_autograd_twin_fp64(case, relax):
     got = _gpu_grads(lattice, D, shape, "f64", xi0, target, steps, every, launch=launch, bc=bc, xi_wall=walls,
                      relax=relax, trt_magic=0.35, xi_ref=xref, dilute=True)
     _compare(ref, got, 1e-10, f"{lattice} dilute {relax} {extra}")
+
+
+def test_adjoint_with_wide_tile_recomputation_fp32():
+    """A domain of 6144 columns or more: the forward recomputation of the adjoint
+    takes 512-column blocked passes; the gradients equal those of a run whose
+    passes stay on 256-column tiles (five steps per pass), to FP32 rounding."""
+    N = 3
+    rng = np.random.default_rng(95)
+    D = rand_D(rng, N)
+    shape = (6200, 20)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    steps, every = 26, 13
+    wide = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every)
+    narrow = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=dict(temporal=5))
+    _compare(narrow, wide, 2e-5, "wide vs 256-column recomputation")

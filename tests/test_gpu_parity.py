@@ -364,6 +364,29 @@ def test_temporally_blocked_sweep(case, tb, N, precision):
         assert_parity(gpu, orc, precision, f"blocked tb={tb} seg={seg} {shape} N={N} {precision}")
 
 
+@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("faces", [(("periodic", "periodic"), ("periodic", "periodic")),
+                                   (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"))])
+def test_blocked_sweep_wide_tiles(N, faces):
+    """Domains of 6144 columns or more take 512-column tiles for full passes of six
+    steps (FP32, up to two evolved species); shorter passes use 256 columns.  20
+    steps in calls of 1, 6, 6, 4 and 3: a single step from the initial state, two
+    wide passes, then passes of 4 and 3 steps on 256-column tiles."""
+    shape = (6250, 23)
+    rng = np.random.default_rng(1600 + N)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(faces):
+        for side, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, side)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=faces, xi_wall=walls), xi0, 20)
+    gpu = gpu_run("D2Q5", D, shape, "f32", xi0, 20, bc=faces, xi_wall=walls, launch=dict(lds_resident=0),
+                  split=[1, 6, 6, 4, 3])
+    assert_parity(gpu, orc, "f32", f"wide tiles N={N} {faces}")
+
+
 @pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
 @pytest.mark.parametrize("tb", [2, 3, 5, 6])
 @pytest.mark.parametrize("N", [2, 3, 5])
