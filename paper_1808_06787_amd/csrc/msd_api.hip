@@ -316,8 +316,9 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
       break;
     }
   if (tb == 0) return pl;
+  const bool xy_walls = s->prob.bc[0] != MSD_BC_PERIODIC || s->prob.bc[2] != MSD_BC_PERIODIC;
   if (!adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
-      s->prob.nx >= msd::kWideMinNx)
+      (!xy_walls || msd::blocked_wide_walls_ok(s->m)) && s->prob.nx >= msd::kWideMinNx)
     pl.cols = msd::kBlockedColsWide;
   const int64_t W = pl.cols - 2 * tb;
   const int64_t tiles_x = (s->prob.nx + W - 1) / W;

@@ -1482,8 +1482,14 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
     if constexpr (blocked_wide_ok(M, TB, (int)sizeof(T))) {
       constexpr int CW = kBlockedColsWide;
       const size_t pad = blocked_lds_pad<M, T, TB, CW>(a);
-      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, true>, CW, pad)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, false>, CW, pad);
+      if (walls) {
+        if constexpr (blocked_wide_walls_ok(M))
+          e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, true>, CW, pad);
+        else
+          return hipErrorInvalidValue;
+      } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, CW, false>, CW, pad);
+      }
     } else {
       return hipErrorInvalidValue;
     }
@@ -1528,12 +1534,16 @@ hipError_t launch_blocked_wide(const LaunchArgs& a) {
     T* dst = static_cast<T*>(a.dst);
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
     const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
-    if (walls)
-      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p, src,
-                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
-    else
+    if (walls) {
+      if constexpr (blocked_wide_walls_ok(M))
+        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p,
+                           src, dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+      else
+        return hipErrorInvalidValue;
+    } else {
       hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), dim3(tiles_x * segs), dim3(C), pad, a.stream, a.p,
                          src, dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    }
     return hipSuccess;
   }
 }

@@ -124,14 +124,19 @@ constexpr int blocked_cols(int m, int tb, int bytes) {
 }
 
 // Wide tiles for wide domains: 512 columns halve the share of the 2 tb halo
-// columns per tile.  Measured on ternary FP32 at six steps per pass: 8192^2
-// 8 % faster, 4096^2 within run-to-run spread, 2048^2 and the batch slower; so
-// the host plan takes them from kWideMinNx columns on, for m <= 2 in FP32 at
-// tb = 6 (80 KiB of LDS exchange per workgroup; 142 VGPRs, one workgroup per
-// CU, two waves per SIMD as with 256 columns).
+// columns per tile.  Measured in FP32: ternary (tb = 6) 8192^2 8 % faster,
+// quaternary (tb = 5, periodic in x and y) 8192^2 and 12288^2 10-12 % faster,
+// 4096^2 unchanged, 2048^2 and the batch slower; so the host plan takes them
+// from kWideMinNx columns on.  LDS exchange per workgroup 80 KiB (m = 2) and
+// 96 KiB (m = 3); one workgroup per CU, two waves per SIMD as with 256
+// columns.  The quaternary walled instantiation would spill registers, so
+// quaternary problems with x or y walls keep 256 columns.
 constexpr int kBlockedColsWide = 512;
 constexpr int kWideMinNx = 6144;
-constexpr bool blocked_wide_ok(int m, int tb, int bytes) { return bytes == 4 && m <= 2 && tb == 6; }
+constexpr bool blocked_wide_ok(int m, int tb, int bytes) {
+  return bytes == 4 && ((m <= 2 && tb == 6) || (m == 3 && tb == 5));
+}
+constexpr bool blocked_wide_walls_ok(int m) { return m <= 2; }
 
 // Temporally blocked adjoint sweep (k_adjoint_blocked): workgroup width for m
 // evolved species, tb adjoint steps per pass and value size, or 0 when its

@@ -364,7 +364,7 @@ def test_temporally_blocked_sweep(case, tb, N, precision):
         assert_parity(gpu, orc, precision, f"blocked tb={tb} seg={seg} {shape} N={N} {precision}")
 
 
-@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("N", [2, 3, 4])
 @pytest.mark.parametrize("faces", [(("periodic", "periodic"), ("periodic", "periodic")),
                                    (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"))])
 def test_blocked_sweep_wide_tiles(N, faces):
