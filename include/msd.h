@@ -284,8 +284,9 @@ typedef struct msd_launch {
                                to this one whose on-chip window fits the species count and
                                precision (FP32: m <= 2 up to 6, m = 3 up to 5, m = 4 up to 3;
                                FP64: m = 1 up to 6, m = 2 up to 3; else one step per pass).
-                               Six-step passes of FP32 problems with m <= 2 and nx >= 6144
-                               use 512-column tiles, all other passes 256-column tiles.
+                               FP32 problems with nx >= 6144 use 512-column tiles for full
+                               passes (m <= 2 at six steps; m = 3 at five steps when x and y
+                               are periodic), all other passes 256-column tiles.
                                Default 6 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
                                automatic.  Forward: about k * 2 workgroups per CU in all,
