@@ -1,26 +1,27 @@
 """Benchmark of the fused Maxwell-Stefan lattice Boltzmann sweep on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload ternary_2d|quaternary_3d|ternary_1d]
+    python bench.py [--steps K] [--warmup W] [--workload quaternary_3d|ternary_2d|ternary_1d]
                     [--no-cpu-baseline] [--no-extras]
 
-Default workload: 2D ternary mixture on a 4096^2 D2Q5 lattice in FP32
-(periodic, smooth random field, random D_ij), K = 2000 steps timed after W
-warm-up steps.  One step is one fused collide-and-stream update of every node
-(propagation with face rules, moments, the local Maxwell-Stefan solve,
-relaxation, store); the 2D sweep performs several steps per launch (temporal
-blocking: intermediate time levels stay on chip).  Prints one JSON line:
+Default workload: 3D quaternary mixture on a 512^3 D3Q7 lattice in FP32
+(zero-flux x walls, periodic y and z, two slabs with 1 % noise, random D_ij),
+K = 500 steps timed after W warm-up steps.  One step is one fused
+collide-and-stream update of every node (propagation with face rules, moments,
+the local Maxwell-Stefan solve, relaxation, store).  Prints one JSON line:
 
   value        MLUPS = nodes * (N - 1) * K / seconds / 1e6 (node-component updates)
   roofline     HBM roofline of the sweep kernel: algorithmic bytes per launch
-               (2 q (N-1) bytes-per-value per node and step: every distribution
-               read once and written once, times the steps one launch performs)
-               over the average launch duration measured with HIP events on the
-               sweep's stream (over whole passes right after the timed region
-               when a launch performs several steps).  With several steps per
-               launch the kernel moves about 1/steps of these bytes, so frac can
-               exceed 1; `traffic` is the measured HBM bytes per launch
+               (2 q (N-1) bytes-per-value per node: every distribution read once
+               and written once per pass over the state) over the average launch
+               duration measured with HIP events on the sweep's stream; `traffic`
+               is the HBM bytes per launch from rocprofv3 counters (FETCH_SIZE +
+               WRITE_SIZE, calibrated on a copy kernel), when a summary taken on
+               the current kernel sources is committed under profiles/
   cpu_baseline the FP64 numpy oracle on a bounded sample of the same workload
-  extras       the 3D quaternary workload and the other kernels, timed the same way
+  extras       the 2D ternary workload (temporally blocked: several steps per
+               launch, bound by VALU issue, so reported against the FP32 vector
+               peak), the other lattices, the 1D workload, the 256-mixture batch
+               and the gradient workload, timed the same way
 """
 from __future__ import annotations
 
@@ -139,23 +140,119 @@ def time_steps(sim, n: int) -> float:
 
 
 def sweep_record(w, seconds, steps, steps_per_pass=1):
-    """MLUPS and the HBM roofline figures of a timed run of `steps` steps from t > 0.
+    """MLUPS of a timed run of `steps` steps from t > 0, and the launch count.
 
-    A launch of the blocked sweep advances `steps_per_pass` steps; its algorithmic
-    bytes are those of the steps it performs (2 q (N-1) value sizes per node and
-    step), so `achieved` is comparable with the one-step-per-pass sweep."""
+    A launch of the blocked sweep advances `steps_per_pass` steps (the host plan
+    splits a run into passes of near-equal length, so `launches` is the number
+    of passes of at most that length)."""
     m = w.N - 1
-    q = Q[w.lattice]
-    s = 4 if w.precision == "f32" else 8
     nodes = w.nodes
-    mlups = nodes * m * steps / seconds / 1e6
     spp = max(1, int(steps_per_pass))
-    launches = steps // spp + (1 if steps % spp else 0)     # a remainder runs as one shorter pass
-    bytes_per_launch = nodes * m * 2 * q * s * spp
-    per_launch = seconds / launches
-    achieved = bytes_per_launch / per_launch / 1e9 if steps % spp == 0 else nodes * m * 2 * q * s * steps / seconds / 1e9
-    return dict(mlups=mlups, per_step=seconds / steps, launches=launches, per_launch=per_launch,
-                bytes_per_launch=bytes_per_launch, achieved=achieved, steps_per_pass=spp)
+    launches = -(-steps // spp)
+    return dict(mlups=nodes * m * steps / seconds / 1e6, per_step=seconds / steps, launches=launches,
+                per_launch=seconds / launches, steps_per_pass=spp)
+
+
+def pass_bytes(w) -> int:
+    """Algorithmic bytes of one pass over the state: every distribution of the
+    N - 1 evolved species read once and written once (2 q (N-1) value sizes per node)."""
+    s = 4 if w.precision == "f32" else 8
+    return w.nodes * (w.N - 1) * 2 * Q[w.lattice] * s
+
+
+# FP32 vector issue without packed instructions: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops per FMA x 2.4 GHz (the packed-FP32 figure, 157.3 TFLOP/s, needs
+# instructions this build does not emit)
+ALU_PEAK_F32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_PEAK_F64_TFLOPS = ALU_PEAK_F32_TFLOPS
+
+
+def collision_flops(m: int, q: int) -> int:
+    """Floating-point operations of one node update (FMA = 2), counted from the
+    collision's algebra: species sums m (q-1); A = I + (a/2) B, 2 m (m-1) FMAs;
+    the scaled small inverse (cofactors for m <= 4); the relaxation rule, 12 per
+    species; the non-equilibrium parts, m (q-1) FMAs; the relaxation, (m+1) FMAs per
+    species and moving direction; the rest closure, m (q-1)."""
+    inv = {1: 2, 2: 9, 3: 43, 4: 145}.get(m, 2 * m ** 3)
+    return m * (q - 1) * (4 + 2 * (m + 1)) + 4 * m * (m - 1) + inv + 12 * m
+
+
+def measure(w, steps, warmup, launch=None):
+    """Time `steps` steps after `warmup`; returns the record, the launch used and
+    the sim (open).  With several steps per launch the dominant kernel's launch
+    duration is measured again, live, over whole passes right after the timed
+    region (HIP events on the sweep's stream)."""
+    seconds, sim = time_sweep(w, steps, warmup, launch)
+    rec = sweep_record(w, seconds, steps, sim.steps_per_pass())
+    if rec["steps_per_pass"] > 1:
+        passes = max(1, min(rec["launches"], 100))
+        rec["per_launch"] = time_steps(sim, passes * rec["steps_per_pass"]) / passes
+        rec["per_launch_over"] = f"{passes} whole passes after the timed region"
+    else:
+        rec["per_launch_over"] = "the timed region"
+    used = sim.get_launch()
+    used["steps_per_pass"] = rec["steps_per_pass"]
+    rec["launch"] = used
+    return rec, sim
+
+
+def hbm_roofline(w, rec):
+    """HBM roofline of a one-step-per-launch sweep: algorithmic bytes per launch
+    over the measured launch duration, and the counted traffic when a profile of
+    the current kernel sources is committed."""
+    bpl = pass_bytes(w)
+    achieved = bpl / rec["per_launch"] / 1e9
+    traffic = load_traffic(w.name)
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": bpl,
+        "steps_per_launch": rec["steps_per_pass"],
+        "launches_timed": rec["launches"],
+        "ms_per_launch": round(rec["per_launch"] * 1e3, 5),
+        "ms_per_launch_measured_over": rec["per_launch_over"],
+        "traffic_over_algorithmic": round(traffic / bpl, 4) if traffic else None,
+    }
+
+
+def alu_roofline(w, rec):
+    """ALU roofline of a temporally blocked sweep (several steps per launch, the
+    intermediate levels kept on chip): algorithmic flops per launch (collision_flops
+    per node and step) over the measured launch duration, against the FP32 (FP64)
+    vector peak without packed instructions; the launch's HBM traffic and the
+    measured VALU issue fraction come from committed counter profiles."""
+    m, q = w.N - 1, Q[w.lattice]
+    flops = collision_flops(m, q) * w.nodes * rec["steps_per_pass"]
+    achieved = flops / rec["per_launch"] / 1e12
+    peak = ALU_PEAK_F32_TFLOPS if w.precision == "f32" else ALU_PEAK_F64_TFLOPS
+    traffic = load_traffic(w.name)
+    valu_time = load_valu_time(w.name)
+    try:
+        valu_busy_clock = float(load_profile("valu", w.name)["valu_busy_frac_at_estimated_clock"])
+        clock_ghz = float(load_profile("valu", w.name)["clock_estimate_GHz"])
+    except (KeyError, ValueError):
+        valu_busy_clock = clock_ghz = None
+    return {
+        "bound": "alu",
+        "achieved": round(achieved, 2),
+        "peak": round(peak, 2),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": traffic,
+        "flops_per_node_update": collision_flops(m, q),
+        "steps_per_launch": rec["steps_per_pass"],
+        "ms_per_launch": round(rec["per_launch"] * 1e3, 5),
+        "ms_per_launch_measured_over": rec["per_launch_over"],
+        "traffic_GBps": round(traffic / rec["per_launch"] / 1e9, 1) if traffic else None,
+        "traffic_frac_of_hbm_peak": round(traffic / rec["per_launch"] / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+        "valu_busy_frac_at_2.4GHz": round(valu_time / rec["per_launch"], 4) if valu_time else None,
+        "valu_busy_frac_at_clock_under_load": valu_busy_clock,
+        "clock_under_load_GHz": clock_ghz,
+    }
 
 
 def batched_extra(steps: int = 1000, warmup: int = 5):
@@ -300,6 +397,24 @@ def adjoint_extra():
     return res
 
 
+def host_cpu_info() -> dict:
+    """Logical CPUs of this host and their model name (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"logical_cpus": os.cpu_count(), "usable_cpus": usable, "model": model}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle (unchanged) on a bounded sub-grid of the workload, single thread."""
     try:
@@ -335,7 +450,27 @@ def cpu_baseline(w, budget_s=15.0):
         "cores": 1,
         "kind": "oracle",
         "sample": f"{'x'.join(map(str, sub))} sub-grid of the same field, {n} steps, FP64 numpy, 1 thread",
+        "host": host_cpu_info(),
     }
+
+
+def lattice_extras(extras):
+    """The lattices without a rest direction (Eqs. (3-6), (3-9)) and with diagonal
+    directions (Eqs. (3-8), (3-11)) on the 2D and 3D inputs, one step per pass."""
+    for name, base, lattice in (("ternary_2d_d2q4_4096^2_f32", "ternary_2d", "D2Q4"),
+                                ("quaternary_3d_d3q6_512^3_f32", "quaternary_3d", "D3Q6"),
+                                ("ternary_2d_d2q9_4096^2_f32", "ternary_2d", "D2Q9"),
+                                ("quaternary_3d_d3q15_512^3_f32", "quaternary_3d", "D3Q15")):
+        wr = _on_lattice(make_workload(base), lattice)
+        n_steps = 500 if wr.lattice.startswith("D2") else 100
+        rr, simr = measure(wr, n_steps, 5)
+        simr.close()
+        a = pass_bytes(wr) / rr["per_launch"] / 1e9
+        extras[name] = {"MLUPS": round(rr["mlups"], 1), "ms_per_step": round(rr["per_step"] * 1e3, 4),
+                        "steps": n_steps, "GB_per_s": round(a, 1), "hbm_frac": round(a / HBM_PEAK_GBS, 4)}
+        print(f"# {name}: {rr['mlups']:.0f} MLUPS, {a:.0f} GB/s ({100 * a / HBM_PEAK_GBS:.1f}%)",
+              file=sys.stderr, flush=True)
+        del wr
 
 
 def main():
@@ -343,7 +478,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ternary_2d")
+    ap.add_argument("--workload", default="quaternary_3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--block-x", type=int, default=0)
@@ -352,7 +487,7 @@ def main():
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--vec", type=int, default=0)
     ap.add_argument("--temporal", type=int, default=None,
-                    help="steps per pass of the blocked D2Q5 sweep (0: one step per pass; default: library's)")
+                    help="steps per pass of the blocked sweep (0: one step per pass; default: library's)")
     ap.add_argument("--seg-rows", type=int, default=None)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
@@ -382,32 +517,14 @@ def main():
                   nontemporal=args.nontemporal, vec=args.vec, temporal=args.temporal, seg_rows=args.seg_rows)
     print(f"# workload {w.name}: {w.lattice} N={w.N} shape={w.shape} {w.precision}; "
           f"warmup {args.warmup}, timing {steps} steps", file=sys.stderr, flush=True)
-    seconds, sim = time_sweep(w, steps, args.warmup, launch)
-    rec = sweep_record(w, seconds, steps, sim.steps_per_pass())
-    mlups, bpl = rec["mlups"], rec["bytes_per_launch"]
-    if rec["steps_per_pass"] > 1:
-        # the dominant kernel's launch duration, live: whole passes right after the
-        # timed region, HIP events on the sweep's stream
-        passes = max(1, min(rec["launches"], 100))
-        per_launch = time_steps(sim, passes * rec["steps_per_pass"]) / passes
-    else:
-        per_launch = rec["per_launch"]
-    achieved = bpl / per_launch / 1e9
+    rec, sim = measure(w, steps, args.warmup, launch)
     _, _, _, bad = sim.diagnostics(raise_on_diverged=False)
-    used_launch = sim.get_launch()
-    used_launch["steps_per_pass"] = rec["steps_per_pass"]
     sim.close()
     del sim
-    traffic = load_traffic(w.name)
-    valu_time = load_valu_time(w.name)
-    try:
-        valu_busy_clock = float(load_profile("valu", w.name)["valu_busy_frac_at_estimated_clock"])
-        clock_ghz = float(load_profile("valu", w.name)["clock_estimate_GHz"])
-    except (KeyError, ValueError):
-        valu_busy_clock = clock_ghz = None
+    roof = hbm_roofline(w, rec) if rec["steps_per_pass"] == 1 else alu_roofline(w, rec)
     out = {
         "metric": "MLUPS (node-component updates per second) of the fused collide-and-stream sweep",
-        "value": round(mlups, 1),
+        "value": round(rec["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": steps,
@@ -419,66 +536,27 @@ def main():
         "dtype": "f32" if w.precision == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": w.lattice, "n_species": w.N, "extents": list(w.shape),
-                   "faces": [list(b) for b in w.bc], "precision": w.precision, "launch": used_launch},
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bpl,
-            "steps_per_launch": rec["steps_per_pass"],
-            "launches_timed": rec["launches"],
-            "ms_per_launch": round(per_launch * 1e3, 5),
-            "ms_per_launch_measured_over": ("whole passes after the timed region" if rec["steps_per_pass"] > 1
-                                            else "the timed region"),
-            "traffic_GBps": round(traffic / per_launch / 1e9, 1) if traffic else None,
-            "traffic_frac": round(traffic / per_launch / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
-            "valu_busy_frac": round(valu_time / per_launch, 4) if valu_time else None,
-            "valu_busy_frac_at_clock_under_load": valu_busy_clock,
-            "clock_under_load_GHz": clock_ghz,
-            "note": ("several steps per launch (temporal blocking): achieved counts the bytes of every step "
-                     "performed, the kernel moves `traffic` bytes per launch; its limiter is VALU issue "
-                     "(valu_busy_frac at 2.4 GHz; the profile's wave-cycle count gives the clock under load) "
-                     "rather than HBM") if rec["steps_per_pass"] > 1 else None,
-        },
+                   "faces": [list(b) for b in w.bc], "precision": w.precision, "launch": rec["launch"]},
+        "roofline": roof,
         "nonfinite": bad,
     }
-    print(f"# {w.name}: {mlups:.0f} MLUPS, {rec['per_step'] * 1e3:.4f} ms/step, {achieved:.0f} GB/s "
-          f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)", file=sys.stderr, flush=True)
+    print(f"# {w.name}: {rec['mlups']:.0f} MLUPS, {rec['per_step'] * 1e3:.4f} ms/step; roofline "
+          f"{roof['bound']} {roof['achieved']} {roof['unit']} = {100 * roof['frac']:.1f}% of peak",
+          file=sys.stderr, flush=True)
     extras = {}
-    if not args.no_extras and args.workload == "ternary_2d":
-        w3 = make_workload("quaternary_3d")
-        s3, sim3 = time_sweep(w3, w3.steps, 5)
-        r3 = sweep_record(w3, s3, w3.steps, sim3.steps_per_pass())
-        sim3.close()
-        m3, p3, a3 = r3["mlups"], r3["per_step"], r3["achieved"]
-        extras["quaternary_3d_d3q7_512^3_f32"] = {
-            "MLUPS": round(m3, 1), "ms_per_step": round(p3 * 1e3, 4), "steps": w3.steps,
-            "GB_per_s": round(a3, 1), "hbm_frac": round(a3 / HBM_PEAK_GBS, 4)}
-        print(f"# {w3.name}: {m3:.0f} MLUPS, {a3:.0f} GB/s ({100 * a3 / HBM_PEAK_GBS:.1f}%)",
+    if not args.no_extras and args.workload == "quaternary_3d":
+        w2 = make_workload("ternary_2d")
+        r2, sim2 = measure(w2, w2.steps, 5)
+        sim2.close()
+        roof2 = alu_roofline(w2, r2) if r2["steps_per_pass"] > 1 else hbm_roofline(w2, r2)
+        extras["ternary_2d_d2q5_4096^2_f32"] = {
+            "MLUPS": round(r2["mlups"], 1), "ms_per_step": round(r2["per_step"] * 1e3, 5), "steps": w2.steps,
+            "launch": r2["launch"], "roofline": roof2}
+        print(f"# {w2.name}: {r2['mlups']:.0f} MLUPS, {r2['per_step'] * 1e3:.4f} ms/step; roofline "
+              f"{roof2['bound']} {roof2['achieved']} {roof2['unit']} = {100 * roof2['frac']:.1f}% of peak",
               file=sys.stderr, flush=True)
-        del w3
-        # the lattices without a rest direction (Eqs. (3-6), (3-9)) and with diagonal
-        # directions (Eqs. (3-8), (3-11)), one step per pass
-        for name, make in (("ternary_2d_d2q4_4096^2_f32", lambda: _on_lattice(make_workload("ternary_2d"), "D2Q4")),
-                           ("quaternary_3d_d3q6_512^3_f32",
-                            lambda: _on_lattice(make_workload("quaternary_3d"), "D3Q6")),
-                           ("ternary_2d_d2q9_4096^2_f32", lambda: _on_lattice(make_workload("ternary_2d"), "D2Q9")),
-                           ("quaternary_3d_d3q15_512^3_f32",
-                            lambda: _on_lattice(make_workload("quaternary_3d"), "D3Q15"))):
-            wr = make()
-            n_steps = 500 if wr.lattice.startswith("D2") else 100
-            sr, simr = time_sweep(wr, n_steps, 5)
-            rr = sweep_record(wr, sr, n_steps, simr.steps_per_pass())
-            simr.close()
-            extras[name] = {"MLUPS": round(rr["mlups"], 1), "ms_per_step": round(rr["per_step"] * 1e3, 4),
-                            "steps": n_steps, "GB_per_s": round(rr["achieved"], 1),
-                            "hbm_frac": round(rr["achieved"] / HBM_PEAK_GBS, 4)}
-            print(f"# {name}: {rr['mlups']:.0f} MLUPS, {rr['achieved']:.0f} GB/s "
-                  f"({100 * rr['achieved'] / HBM_PEAK_GBS:.1f}%)", file=sys.stderr, flush=True)
-            del wr
+        del w2
+        lattice_extras(extras)
         w1 = make_workload("ternary_1d")
         s1, sim1 = time_sweep(w1, w1.steps, 0)
         sim1.close()
@@ -488,12 +566,12 @@ def main():
         print(f"# {w1.name}: {m1:.1f} MLUPS, {w1.steps / s1:.0f} steps/s", file=sys.stderr, flush=True)
         bx = batched_extra()
         extras["batched_256_mixtures_d2q5_f32"] = bx
+        print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS fused vs {bx['MLUPS_one_launch_per_mixture']:.0f} "
+              f"one launch per mixture ({bx['speedup_vs_one_launch_per_mixture']:.2f}x)", file=sys.stderr, flush=True)
         ax = adjoint_extra()
         extras["adjoint_1024x1024_d2q5_ternary"] = ax
         print(f"# adjoint f32: backward/forward = {ax['f32']['backward_over_forward']:.2f}; FD check (f64) "
               f"max rel diff {ax['fd_check_f64']['max_relative_difference']:.2e}", file=sys.stderr, flush=True)
-        print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS fused vs {bx['MLUPS_one_launch_per_mixture']:.0f} "
-              f"one launch per mixture ({bx['speedup_vs_one_launch_per_mixture']:.2f}x)", file=sys.stderr, flush=True)
     if extras:
         out["extras"] = extras
     if not args.no_cpu_baseline:

@@ -40,7 +40,7 @@ extern "C" {
 #define MSD_API
 #endif
 
-#define MSD_ABI_VERSION 3
+#define MSD_ABI_VERSION 4
 #define MSD_MAX_SPECIES 8
 
 /* Lattices: velocity sets and weights of Sec. 3.1, Eqs. (3-5), (3-7), (3-10),
@@ -277,25 +277,41 @@ typedef struct msd_launch {
                                vector accesses; used when nx % vec == 0, else the largest
                                power of two dividing nx); 0 (default) selects the general
                                one-node-per-thread kernel */
-  int32_t temporal;         /* D2Q5 only: at most this many steps (2 .. 6) per pass over HBM
-                               (temporally blocked sweep: each workgroup marches along y
-                               with the intermediate time levels of a few rows on chip); 0 or
-                               1: one step per pass.  The library takes the largest count up
+  int32_t temporal;         /* at most this many steps per pass over HBM; 0 or 1: one step
+                               per pass.  D2Q5: 2 .. 6 (temporally blocked sweep: each
+                               workgroup marches along y with the intermediate time levels
+                               of a few rows on chip).  The library takes the largest count up
                                to this one whose on-chip window fits the species count and
                                precision (FP32: m <= 2 up to 6, m = 3 up to 5, m = 4 up to 3;
                                FP64: m = 1 up to 6, m = 2 up to 3; else one step per pass).
                                FP32 problems with nx >= 6144 use 512-column tiles for full
                                passes (m <= 2 at six steps; m = 3 at five steps when x and y
                                are periodic), all other passes 256-column tiles.
-                               Default 6 for D2Q5, 0 otherwise; other values are MSD_EINVAL */
-  int32_t seg_rows;         /* rows per workgroup of the blocked sweep; 0 (default):
+                               D3Q7 and D3Q6: 2 (two steps per pass: each workgroup marches
+                               along z over an x-y tile and a ring of one node, the first
+                               step's values kept on chip), for FP32 with m <= 3 and the full
+                               Maxwell-Stefan collision; any value >= 2 means 2 there.
+                               Default 6 for D2Q5, 2 for D3Q7 and D3Q6, 0 otherwise; values
+                               outside 0 .. 6 are MSD_EINVAL */
+  int32_t seg_rows;         /* D2Q5 blocked sweep: rows per workgroup; 0 (default):
                                automatic.  Forward: about k * 2 workgroups per CU in all,
                                with k doubling (up to 64) while segments stay at least 128
                                rows tall; the adjoint's blocked passes: about 1.35 times the
                                workgroups the device runs at once.  Segments are at least 8
                                rows, and one step per pass is used when 8-row segments give
                                fewer than 512 workgroups (small domains run faster
-                               unblocked); negative or above 2^20 is MSD_EINVAL */
+                               unblocked).  3D blocked sweep: z-planes per workgroup; 0:
+                               automatic (at least 8 planes, about eight workgroups per CU in
+                               all); one step per pass when 8-plane segments give fewer than
+                               512 workgroups.  Negative or above 2^20 is MSD_EINVAL */
+  int32_t tile_x;           /* 3D blocked sweep: output tile of tile_x * tile_y nodes per
+                               workgroup, which runs (tile_x + 2) * (tile_y + 2) threads: at
+                               most 1024 (768 for three evolved species; a larger tile runs
+                               one step per pass); 0 (default): automatic (64 x 13, 64 x 9
+                               for three evolved species, or the domain's extent where
+                               smaller).  Both 0, or both positive with at most 1024
+                               threads, else MSD_EINVAL */
+  int32_t tile_y;
 } msd_launch;
 
 MSD_API int msd_set_launch(msd_sim* sim, const msd_launch* launch);

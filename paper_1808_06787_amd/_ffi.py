@@ -11,7 +11,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsd.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_SPECIES = 8
 
 D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6, D2Q9, D3Q15 = 1, 2, 3, 4, 5, 6, 7, 8
@@ -59,6 +59,8 @@ class MsdLaunch(C.Structure):
         ("vec", C.c_int32),
         ("temporal", C.c_int32),
         ("seg_rows", C.c_int32),
+        ("tile_x", C.c_int32),
+        ("tile_y", C.c_int32),
     ]
 
 

@@ -20,7 +20,8 @@ import torch
 from . import _ffi as F
 from .batch import MODES, ORDERS
 
-LAUNCH_FIELDS = ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec", "temporal", "seg_rows")
+LAUNCH_FIELDS = ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec", "temporal", "seg_rows",
+                 "tile_x", "tile_y")
 MAX_LIBRARY_CANDIDATES = 256
 
 

@@ -229,8 +229,11 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
-  l->temporal = p->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass : 0;
+  l->temporal = p->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass
+                                       : ((p->lattice == MSD_D3Q7 || p->lattice == MSD_D3Q6) ? msd::k3dStepsPerPass : 0);
   l->seg_rows = 0;
+  l->tile_x = 0;
+  l->tile_y = 0;
 }
 
 }  // namespace host
@@ -258,7 +261,8 @@ struct msd_sim {
 
 static_assert(sizeof(msd_problem) == 120 && offsetof(msd_problem, c_t) == 64 && offsetof(msd_problem, bc) == 80 &&
                   offsetof(msd_problem, dilute) == 108 && offsetof(msd_problem, trt_magic) == 112,
-              "msd_problem layout (ABI version 3)");
+              "msd_problem layout (ABI version 3 and later)");
+static_assert(sizeof(msd_launch) == 40 && offsetof(msd_launch, tile_x) == 32, "msd_launch layout (ABI version 4)");
 
 namespace {
 
@@ -373,6 +377,51 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   return pl;
 }
 
+// Plan of the temporally blocked 3D sweep (D3Q7, D3Q6): output tile and
+// z-planes per workgroup, or tb = 0 for one step per pass.  Automatic segments
+// (seg_rows = 0) give about eight workgroups per CU in all (one workgroup of
+// up to 1024 threads fits a CU at a time), at least 8 planes each; if 8-plane
+// segments leave fewer than 512 workgroups the domain is too small to fill the
+// device and one step per pass is used.
+struct Blocked3dPlan {
+  int tb = 0;
+  int tx = 0, ty = 0, zseg = 0;
+};
+
+Blocked3dPlan blocked3d_plan(const msd_sim* s) {
+  Blocked3dPlan pl;
+  if (!msd::blocked3d_ok(s->prob.lattice, s->m, s->prob.precision) || s->prob.dilute) return pl;
+  if (s->launch.temporal < 2) return pl;
+  if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
+  const int maxt = msd::blocked3d_max_threads(s->m);
+  const int tx = s->launch.tile_x > 0 ? s->launch.tile_x : (int)std::min<int64_t>(msd::k3dTileX, s->prob.nx);
+  const int ty = s->launch.tile_y > 0 ? s->launch.tile_y : (int)std::min<int64_t>(maxt / (tx + 2) - 2, s->prob.ny);
+  if (tx < 1 || ty < 1 || (tx + 2) * (ty + 2) > maxt) return pl;
+  const int64_t tiles = ((s->prob.nx + tx - 1) / tx) * ((s->prob.ny + ty - 1) / ty);
+  int zseg = s->launch.seg_rows;
+  if (zseg <= 0) {
+    const int64_t nz = s->prob.nz;
+    if (tiles * ((nz + 7) / 8) < 512) return pl;
+    int cus = s->n_cu;
+    if (cus <= 0) {
+      int dev = 0, v = 0;
+      cus = (hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                ? v
+                : 256;
+      s->n_cu = cus;
+    }
+    const int64_t target = 8 * (int64_t)cus;
+    const int64_t segs = std::max<int64_t>(1, (target + tiles - 1) / tiles);
+    zseg = (int)std::max<int64_t>(8, (nz + segs - 1) / segs);
+  }
+  pl.tb = msd::k3dStepsPerPass;
+  pl.tx = tx;
+  pl.ty = ty;
+  pl.zseg = zseg;
+  return pl;
+}
+
 bool use_lds(const msd_sim* s) {
   if (!s->launch.lds_resident) return false;
   const int64_t cap = msd::lds_resident_max_nodes(s->m, s->q, s->prob.precision);
@@ -457,6 +506,10 @@ int msd_set_launch(msd_sim* s, const msd_launch* l) {
   if (v.temporal < 0 || v.temporal > msd::kMaxStepsPerPass)
     return fail(MSD_EINVAL, "temporal = %d must be 0..%d", v.temporal, msd::kMaxStepsPerPass);
   if (v.seg_rows < 0 || v.seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", v.seg_rows);
+  if (v.tile_x < 0 || v.tile_y < 0 || (v.tile_x > 0) != (v.tile_y > 0) ||
+      (v.tile_x > 0 && (v.tile_x + 2) * (v.tile_y + 2) > 1024))
+    return fail(MSD_EINVAL, "tile %d x %d: both 0, or both positive with (tile_x + 2) * (tile_y + 2) <= 1024",
+                v.tile_x, v.tile_y);
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4)
     return fail(MSD_EINVAL, "vec = %d must be 0, 1, 2 or 4", v.vec);
   if (v.block_x < 64 || v.block_x % 64 || v.block_y < 1 || v.block_x * v.block_y > 256)
@@ -474,7 +527,7 @@ int msd_get_launch(const msd_sim* s, msd_launch* l) {
 
 int msd_steps_per_pass(const msd_sim* s) {
   if (!s) return fail(MSD_EINVAL, "NULL argument");
-  const int tb = blocked_plan(s).tb;
+  const int tb = std::max(blocked_plan(s).tb, blocked3d_plan(s).tb);
   return tb >= 2 ? tb : 1;
 }
 
@@ -514,19 +567,34 @@ int msd_step(msd_sim* s, int64_t nsteps) {
     return MSD_OK;
   }
   const BlockedPlan plan = blocked_plan(s);
-  const int tb = plan.tb;
+  const Blocked3dPlan plan3 = blocked3d_plan(s);
+  const int tb = std::max(plan.tb, plan3.tb);
   int64_t n = 0;
+  // Blocked runs: the first step after msd_init reads pre-collision values and
+  // runs alone; the rest runs in ceil(rest / tb) passes of near-equal length
+  // (lengths floor and ceil of rest / passes, the longer ones first), so a run
+  // whose length is not a multiple of tb has no short remainder pass.
+  const int64_t first = (tb >= 2 && s->t == 0) ? 1 : 0;
+  const int64_t rest = nsteps - std::min<int64_t>(first, nsteps);
+  const int64_t passes = tb >= 2 ? (rest + tb - 1) / tb : 0;
+  const int64_t base = passes > 0 ? rest / passes : 0, longer = passes > 0 ? rest % passes : 0;
+  int64_t pass_index = 0;
   while (n < nsteps) {
     a.src = s->ws + s->L.half_off[s->cur];
     a.dst = s->ws + s->L.half_off[1 - s->cur];
     a.pull = s->t > 0 ? 1 : 0;
     int64_t done = 1;
     hipError_t e;
-    const int pass = (int)std::min<int64_t>(tb, nsteps - n);
-    if (tb >= 2 && s->t > 0 && pass >= 2) {
-      // tb steps in one pass (a remainder of two or more in one shorter pass);
-      // the first step after msd_init reads pre-collision values and is always
-      // a single step
+    const int pass = (tb >= 2 && n >= first) ? (int)(base + (pass_index < longer ? 1 : 0)) : 1;
+    if (pass >= 2 && plan3.tb >= 2) {
+      a.tb = pass;
+      a.tile_x = plan3.tx;
+      a.tile_y = plan3.ty;
+      a.seg_rows = plan3.zseg;
+      e = dispatch(msd::Op::StepBlocked3d, a);
+      done = pass;
+    } else if (pass >= 2) {
+      // the full-length passes take the plan's tile width, shorter ones kBlockedCols
       a.tb = pass;
       a.cols = pass == tb ? plan.cols : 0;
       a.seg_rows = plan.seg;
@@ -536,6 +604,7 @@ int msd_step(msd_sim* s, int64_t nsteps) {
       e = dispatch(msd::Op::Step, a);
     }
     if (e != hipSuccess) return hip_fail(e, "step kernel");
+    if (tb >= 2 && n >= first) ++pass_index;
     s->cur = 1 - s->cur;
     s->t += done;
     n += done;
@@ -886,15 +955,17 @@ int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t st
                 (long long)s->prob.nz, s->prob.bc[0], s->prob.bc[1], s->prob.bc[2], s->prob.bc[3], s->prob.bc[4],
                 s->prob.bc[5]);
   const std::string key = buf;
-  constexpr int K = 8;
+  constexpr int K = 10;
   auto pack = [](const msd_launch& l, int64_t* v) {
     v[0] = l.block_x; v[1] = l.block_y; v[2] = l.xcd_remap; v[3] = l.lds_resident;
     v[4] = l.nontemporal; v[5] = l.vec; v[6] = l.temporal; v[7] = l.seg_rows;
+    v[8] = l.tile_x; v[9] = l.tile_y;
   };
   auto unpack = [](const int64_t* v) {
     msd_launch l;
     l.block_x = (int32_t)v[0]; l.block_y = (int32_t)v[1]; l.xcd_remap = (int32_t)v[2]; l.lds_resident = (int32_t)v[3];
     l.nontemporal = (int32_t)v[4]; l.vec = (int32_t)v[5]; l.temporal = (int32_t)v[6]; l.seg_rows = (int32_t)v[7];
+    l.tile_x = (int32_t)v[8]; l.tile_y = (int32_t)v[9];
     return l;
   };
   int64_t cached[K];
@@ -931,6 +1002,17 @@ int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t st
             l.temporal = tb; l.seg_rows = seg; l.nontemporal = nt; l.vec = 0;
             cand.push_back(l);
           }
+    if (msd::blocked3d_ok(s->prob.lattice, s->m, s->prob.precision) && !s->prob.dilute) {
+      const int tiles[5][2] = {{0, 0}, {62, 14}, {30, 30}, {64, 6}, {126, 6}};
+      for (auto& t : tiles)
+        for (int zseg : {0, 16, 32, 64})
+          for (int xcd : {0, 1}) {
+            msd_launch l = base;
+            l.temporal = msd::k3dStepsPerPass; l.tile_x = t[0]; l.tile_y = t[1]; l.seg_rows = zseg;
+            l.xcd_remap = xcd; l.vec = 0;
+            cand.push_back(l);
+          }
+    }
   }
   const size_t sb = msd_state_bytes(s);
   if (!d_scratch || scratch_bytes < sb) return fail(MSD_ENOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, sb);

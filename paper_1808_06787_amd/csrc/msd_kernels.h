@@ -1412,6 +1412,12 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
     p[i] = 0.0;
 }
 
+}  // namespace msd
+
+#include "msd_blocked3d.h"
+
+namespace msd {
+
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
@@ -1785,6 +1791,14 @@ hipError_t run(Op op, const LaunchArgs& a) {
       } else {
         return hipErrorInvalidValue;
       }
+    case Op::StepBlocked3d:
+      if constexpr ((LAT == 3 || LAT == 6) && M <= 3 && sizeof(T) == 4) {
+        const hipError_t e = launch_blocked3d<LAT, M, T>(a);
+        if (e != hipSuccess) return e;
+      } else {
+        return hipErrorInvalidValue;
+      }
+      break;
     case Op::AdjointBlocked:
       if constexpr (LAT == 2) {
         const hipError_t e = launch_adjoint_blocked<M, T>(a);

@@ -11,7 +11,7 @@ namespace msd {
 enum class Op {
   Constants, Init, Step, StepLds, Read, DiagPartial, DiagFinal, BatchStep,
   AdjointSeed, AdjointStep, AdjointXi0, AdjointDD, FillZero, StepBlocked, BatchStepBlocked,
-  AdjointBlocked, BlockedResident
+  AdjointBlocked, BlockedResident, StepBlocked3d
 };
 
 // Constants block written once per problem by the setup kernel and read by
@@ -77,6 +77,7 @@ struct LaunchArgs {
   int adjoint = 0;           // BlockedResident: query the adjoint kernel
   int* out_int = nullptr;    // BlockedResident: [0] workgroups resident at once, [1] CUs
   int64_t nsteps = 1;        // StepLds: steps done inside one launch
+  int tile_x = 0, tile_y = 0; // StepBlocked3d: output tile per workgroup (seg_rows: z-planes per workgroup)
   // init
   const void* xi0 = nullptr;
   int in_prec = 8;
@@ -148,6 +149,22 @@ constexpr int adjoint_blocked_cols(int m, int tb, int bytes) {
              ? kBlockedCols
              : 0;
 }
+
+// Temporally blocked 3D sweep (k_step_blocked3d, D3Q7 and D3Q6): two steps
+// per pass, FP32, up to three evolved species, the full collision.  One
+// workgroup fills a CU; its thread count bounds the registers of each lane:
+// 1024 threads (128 VGPRs) for m <= 2, 768 (170 VGPRs) for m = 3, whose window
+// (prefetched source plane, two collisions, the z ring) does not fit 128
+// without spilling (read off the compiled kernels); larger m or FP64 would
+// spill at any size.  Default output tile 64 columns by as many rows as the
+// thread bound allows (64 x 13 and 64 x 9); LDS: two planes of the four
+// in-plane populations of m species per thread.
+constexpr int k3dStepsPerPass = 2;
+constexpr int k3dTileX = 64;
+constexpr bool blocked3d_ok(int lattice, int m, int bytes) {
+  return (lattice == 3 || lattice == 6) && bytes == 4 && m >= 1 && m <= 3;
+}
+constexpr int blocked3d_max_threads(int m) { return m <= 2 ? 1024 : 768; }
 
 // Nodes per thread of the adjoint sweep (see k_adjoint_step).
 constexpr int kAdjointNodesPerThread = 4;

@@ -143,7 +143,7 @@ class Sim:
         l = F.MsdLaunch()
         F.check(self.lib.msd_get_launch(self._h, C.byref(l)), "msd_get_launch")
         return {k: getattr(l, k) for k in ("block_x", "block_y", "xcd_remap", "lds_resident", "nontemporal", "vec",
-                                          "temporal", "seg_rows")}
+                                          "temporal", "seg_rows", "tile_x", "tile_y")}
 
     def steps_per_pass(self) -> int:
         """Time steps per launch of the sweep under the current launch configuration."""

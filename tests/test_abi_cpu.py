@@ -44,7 +44,7 @@ def test_struct_layouts():
     assert F.MsdProblem.bc.offset == 80
     assert F.MsdProblem.dilute.offset == 108
     assert F.MsdProblem.trt_magic.offset == 112
-    assert C.sizeof(F.MsdLaunch) == 32
+    assert C.sizeof(F.MsdLaunch) == 40
     assert F.lib().msd_abi_version() == F.ABI_VERSION
 
 
@@ -195,6 +195,7 @@ def test_blocked_plan_limits_without_device():
         ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f32", (32768, 32768), dict(seg_rows=16), 1),
         ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 5),
+        ("D2Q5", 4, "f32", (8192, 1024), dict(seg_rows=16), 5),
         ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 3),
         ("D2Q5", 6, "f32", (4096, 1024), dict(seg_rows=16), 1),
         ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 6),
@@ -203,7 +204,21 @@ def test_blocked_plan_limits_without_device():
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=3), 3),
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, temporal=0), 1),
         ("D2Q5", 3, "f32", (5, 3), dict(seg_rows=16), 6),
-        ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
+        # 3D: two steps per pass (FP32, m <= 3, full collision); automatic
+        # segments leave this small domain at one step per pass
+        ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=16), 2),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=16), 2),
+        ("D3Q7", 5, "f32", (64, 64, 64), dict(seg_rows=16), 1),
+        ("D3Q7", 3, "f64", (64, 64, 64), dict(seg_rows=16), 1),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=16, temporal=0), 1),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=16, temporal=6), 2),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=16, dilute=True), 1),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=0), 1),
+        ("D3Q7", 3, "f32", (64, 64, 64), dict(seg_rows=8, tile_x=30, tile_y=30), 2),
+        # three evolved species: at most 768 threads per workgroup
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=8, tile_x=30, tile_y=30), 1),
+        ("D3Q7", 4, "f32", (64, 64, 64), dict(seg_rows=8, tile_x=30, tile_y=22), 2),
+        ("D3Q6", 4, "f32", (64, 64, 64), dict(seg_rows=16), 2),
         ("D1Q3", 3, "f64", (256,), dict(seg_rows=16), 1),
         ("D2Q9", 3, "f32", (4096, 1024), dict(seg_rows=16), 1),
         ("D3Q15", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),

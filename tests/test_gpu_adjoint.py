@@ -268,8 +268,13 @@ def test_adjoint_dilute_mode_matches_autograd_twin_fp64(case, relax):
 
 def test_adjoint_with_wide_tile_recomputation_fp32():
     """A domain of 6144 columns or more: the forward recomputation of the adjoint
-    takes 512-column blocked passes; the gradients equal those of a run whose
-    passes stay on 256-column tiles (five steps per pass), to FP32 rounding."""
+    takes 512-column blocked passes (recording every state of a pass); the
+    gradients match the autograd twin of the oracle to the FP32 bound of the
+    other FP32 adjoint tests, and equal those of a run whose passes stay on
+    256-column tiles (five steps per pass) to FP32 rounding.  An explicit segment
+    height keeps both runs blocked on this short domain."""
+    from paper_1808_06787_amd.sim import Sim
+
     N = 3
     rng = np.random.default_rng(95)
     D = rand_D(rng, N)
@@ -277,6 +282,14 @@ def test_adjoint_with_wide_tile_recomputation_fp32():
     xi0 = smooth_field(rng, N, shape[::-1], 0.1)
     target = smooth_field(rng, N, shape[::-1], 0.1)
     steps, every = 26, 13
-    wide = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every)
-    narrow = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=dict(temporal=5))
+    wide_launch, narrow_launch = dict(seg_rows=8), dict(temporal=5, seg_rows=8)
+    for launch, want in ((wide_launch, 6), (narrow_launch, 5)):
+        probe = Sim("D2Q5", D, shape, "f32")
+        probe.set_launch(**launch)
+        assert probe.steps_per_pass() == want, launch
+        probe.close()
+    wide = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=wide_launch)
+    narrow = _gpu_grads("D2Q5", D, shape, "f32", xi0, target, steps, every, launch=narrow_launch)
+    ref = twin.misfit_gradients(oracle_problem("D2Q5", D, shape), xi0, target, steps)
+    _compare(ref, wide, 2e-4, "wide-tile recomputation vs twin")
     _compare(narrow, wide, 2e-5, "wide vs 256-column recomputation")

@@ -368,11 +368,17 @@ def test_temporally_blocked_sweep(case, tb, N, precision):
 @pytest.mark.parametrize("faces", [(("periodic", "periodic"), ("periodic", "periodic")),
                                    (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"))])
 def test_blocked_sweep_wide_tiles(N, faces):
-    """Domains of 6144 columns or more take 512-column tiles for full passes of six
-    steps (FP32, up to two evolved species); shorter passes use 256 columns.  20
-    steps in calls of 1, 6, 6, 4 and 3: a single step from the initial state, two
-    wide passes, then passes of 4 and 3 steps on 256-column tiles."""
+    """Domains of 6144 columns or more take 512-column tiles for full passes (FP32:
+    six steps for up to two evolved species, five for three when x and y are
+    periodic); shorter passes use 256 columns.  An explicit segment height keeps
+    the blocked plan on this short domain (automatic segments would leave too
+    few workgroups and fall back to one step per pass).  Calls of 1, tb, tb, 4 and
+    3 steps: a single step from the initial state, two full passes, then passes
+    of 4 and 3 steps on 256-column tiles."""
+    from paper_1808_06787_amd.sim import Sim
+
     shape = (6250, 23)
+    tb = 6 if N <= 3 else 5
     rng = np.random.default_rng(1600 + N)
     D = rand_D(rng, N)
     walls = {}
@@ -380,11 +386,39 @@ def test_blocked_sweep_wide_tiles(N, faces):
         for side, kind in enumerate((lo, hi)):
             if kind == "dirichlet":
                 walls[(a, side)] = rand_field(rng, N, ())
+    launch = dict(lds_resident=0, seg_rows=8)
+    probe = Sim("D2Q5", D, shape, "f32", bc=faces, xi_wall=walls)
+    probe.set_launch(**launch)
+    assert probe.steps_per_pass() == tb
+    probe.close()
+    split = [1, tb, tb, 4, 3]
+    steps = sum(split)
     xi0 = smooth_field(rng, N, shape[::-1], 0.15)
-    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=faces, xi_wall=walls), xi0, 20)
-    gpu = gpu_run("D2Q5", D, shape, "f32", xi0, 20, bc=faces, xi_wall=walls, launch=dict(lds_resident=0),
-                  split=[1, 6, 6, 4, 3])
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=faces, xi_wall=walls), xi0, steps)
+    gpu = gpu_run("D2Q5", D, shape, "f32", xi0, steps, bc=faces, xi_wall=walls, launch=launch, split=split)
     assert_parity(gpu, orc, "f32", f"wide tiles N={N} {faces}")
+
+
+@pytest.mark.parametrize("tb", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("steps", [1, 2, 7, 13, 20, 25])
+def test_blocked_runs_split_into_near_equal_passes(tb, steps):
+    """A run of `steps` from the initial state: one single step, then
+    ceil((steps - 1) / tb) passes of near-equal length (no short remainder pass);
+    the field matches the oracle whatever the split."""
+    shape, bc = BLOCKED_CASES[2]
+    rng = np.random.default_rng(1700 + tb)
+    N = 3
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls), xi0, steps)
+    gpu = gpu_run("D2Q5", D, shape, "f64" if tb <= 3 else "f32", xi0, steps, bc=bc, xi_wall=walls,
+                  launch=dict(temporal=tb, seg_rows=6, lds_resident=0))
+    assert_parity(gpu, orc, "f64" if tb <= 3 else "f32", f"split tb={tb} steps={steps}")
 
 
 @pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
@@ -474,3 +508,64 @@ def test_steps_per_pass_plan():
     sim = Sim("D3Q7", rand_D(rng, 3), (64, 64, 64), "f32")
     assert sim.steps_per_pass() == 1
     sim.close()
+
+
+BLOCKED3D_CASES = [
+    # shape, faces, (tile_x, tile_y), z-planes per workgroup
+    ((70, 21, 13), (("zero_flux", "zero_flux"), ("periodic", "periodic"), ("periodic", "periodic")), (16, 5), 4),
+    ((37, 19, 11), (("periodic", "periodic"), ("periodic", "periodic"), ("periodic", "periodic")), (64, 9), 8),
+    ((23, 17, 9), (("dirichlet", "zero_flux"), ("zero_flux", "dirichlet"), ("dirichlet", "zero_flux")), (8, 6), 3),
+    ((9, 30, 14), (("periodic", "periodic"), ("dirichlet", "dirichlet"), ("zero_flux", "zero_flux")), (5, 7), 5),
+    ((1, 13, 6), (("periodic", "periodic"), ("zero_flux", "dirichlet"), ("periodic", "periodic")), (4, 4), 2),
+    ((12, 1, 1), (("zero_flux", "dirichlet"), ("periodic", "periodic"), ("periodic", "periodic")), (7, 3), 1),
+    ((5, 4, 3), (("periodic", "periodic"), ("periodic", "periodic"), ("zero_flux", "dirichlet")), (2, 2), 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED3D_CASES)))
+@pytest.mark.parametrize("lattice", ["D3Q7", "D3Q6"])
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_temporally_blocked_sweep_3d(case, lattice, N):
+    """Two steps per pass in 3D (an x-y tile plus a ring of one node marching along
+    z, the first step's values on chip): ragged tiles and z-segments, every face
+    kind on every axis, extents of one node, the pre-collision first step and
+    passes of near-equal length (calls of 1, 6 and 16 steps), FP32 against the
+    oracle."""
+    from paper_1808_06787_amd.sim import Sim
+
+    shape, bc, (tx, ty), zseg = BLOCKED3D_CASES[case]
+    rng = np.random.default_rng(1800 + 10 * case + N)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    launch = dict(temporal=2, seg_rows=zseg, tile_x=tx, tile_y=ty, lds_resident=0)
+    probe = Sim(lattice, D, shape, "f32", bc=bc, xi_wall=walls)
+    probe.set_launch(**launch)
+    assert probe.steps_per_pass() == 2
+    probe.close()
+    steps = 23
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, xi_wall=walls), xi0, steps)
+    gpu = gpu_run(lattice, D, shape, "f32", xi0, steps, bc=bc, xi_wall=walls, launch=launch, split=[1, 6, 16])
+    assert_parity(gpu, orc, "f32", f"blocked 3D {lattice} {shape} N={N} tile {tx}x{ty} zseg {zseg}")
+
+
+@pytest.mark.parametrize("xcd_remap", [0, 1])
+def test_temporally_blocked_sweep_3d_default_tile(xcd_remap):
+    """The automatic tile (64 x 9 for three evolved species) on a domain of several
+    tiles and segments in each direction, zero-flux x walls as in the 512^3
+    workload, with and without the XCD remapping of workgroups."""
+    shape = (150, 40, 37)
+    bc = (("zero_flux", "zero_flux"), ("periodic", "periodic"), ("periodic", "periodic"))
+    rng = np.random.default_rng(1900 + xcd_remap)
+    N = 4
+    D = rand_D(rng, N, 0.02, 0.8)
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    steps = 9
+    orc = oracle_run(oracle_problem("D3Q7", D, shape, bc=bc), xi0, steps)
+    gpu = gpu_run("D3Q7", D, shape, "f32", xi0, steps, bc=bc,
+                  launch=dict(temporal=2, seg_rows=8, xcd_remap=xcd_remap, lds_resident=0))
+    assert_parity(gpu, orc, "f32", f"blocked 3D default tile remap={xcd_remap}")
