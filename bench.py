@@ -488,7 +488,10 @@ def main():
     ap.add_argument("--vec", type=int, default=0)
     ap.add_argument("--temporal", type=int, default=None,
                     help="steps per pass of the blocked sweep (0: one step per pass; default: library's)")
-    ap.add_argument("--seg-rows", type=int, default=None)
+    ap.add_argument("--seg-rows", type=int, default=None,
+                    help="rows (2D) or z-planes (3D) per workgroup of the blocked sweep (0: automatic)")
+    ap.add_argument("--tile", type=int, nargs=2, default=None, metavar=("TX", "TY"),
+                    help="output tile per workgroup of the 3D blocked sweep (0 0: automatic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -514,7 +517,8 @@ def main():
     w = make_workload(args.workload)
     steps = args.steps if args.steps is not None else w.steps
     launch = dict(block_x=args.block_x, block_y=args.block_y, xcd_remap=args.xcd_remap,
-                  nontemporal=args.nontemporal, vec=args.vec, temporal=args.temporal, seg_rows=args.seg_rows)
+                  nontemporal=args.nontemporal, vec=args.vec, temporal=args.temporal, seg_rows=args.seg_rows,
+                  tile_x=args.tile[0] if args.tile else None, tile_y=args.tile[1] if args.tile else None)
     print(f"# workload {w.name}: {w.lattice} N={w.N} shape={w.shape} {w.precision}; "
           f"warmup {args.warmup}, timing {steps} steps", file=sys.stderr, flush=True)
     rec, sim = measure(w, steps, args.warmup, launch)

@@ -301,8 +301,8 @@ typedef struct msd_launch {
                                rows, and one step per pass is used when 8-row segments give
                                fewer than 512 workgroups (small domains run faster
                                unblocked).  3D blocked sweep: z-planes per workgroup; 0:
-                               automatic (at least 8 planes, about eight workgroups per CU in
-                               all); one step per pass when 8-plane segments give fewer than
+                               automatic (at least 8 planes, about sixteen workgroups per CU
+                               in all); one step per pass when 8-plane segments give fewer than
                                512 workgroups.  Negative or above 2^20 is MSD_EINVAL */
   int32_t tile_x;           /* 3D blocked sweep: output tile of tile_x * tile_y nodes per
                                workgroup, which runs (tile_x + 2) * (tile_y + 2) threads: at

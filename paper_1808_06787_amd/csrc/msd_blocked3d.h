@@ -38,26 +38,51 @@ __host__ __device__ constexpr int inplane_slot(int k) {
 }
 
 template <int LAT, int M, typename T, bool WALLS>
-__global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(Problem p, const T* __restrict__ src, T* __restrict__ dst,
-                                                         const Consts<T>* __restrict__ cst, uint32_t tiles_x,
-                                                         uint32_t tiles_y, int zseg, int remap) {
+__global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
+    Problem p, const T* __restrict__ src, T* __restrict__ dst, const Consts<T>* __restrict__ cst, int TX, int TY,
+    uint32_t tiles_x, uint32_t tiles_y, int zseg, int remap) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
   static_assert(L::D == 3 && !L::diag, "axial 3D lattices only");
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
 
-  const int EX = (int)blockDim.x, EY = (int)blockDim.y;
-  const int TX = EX - 2, TY = EY - 2;
+  // Block position (cx, cy) of this thread: the first TX * TY threads hold the
+  // tile's own columns row by row, the others the ring around it (bottom and
+  // top rows, then the left and right columns), so that the second level (tile
+  // columns only) leaves whole waves idle instead of masking lanes.  LDS is
+  // indexed by block position, n = cy * EX + cx.
+  const int EX = TX + 2, EY = TY + 2;
   const int E1 = EX * EY;
-  const int cx = (int)threadIdx.x, cy = (int)threadIdx.y;
-  const int t = cy * EX + cx;
+  const int t = (int)threadIdx.x;
+  const int inner = TX * TY;
+  int cx, cy;
+  if (t < inner) {
+    cx = 1 + t % TX;
+    cy = 1 + t / TX;
+  } else {
+    const int h = t - inner;
+    if (h < EX) {
+      cx = h;
+      cy = 0;
+    } else if (h < 2 * EX) {
+      cx = h - EX;
+      cy = EY - 1;
+    } else if (h < 2 * EX + TY) {
+      cx = 0;
+      cy = 1 + (h - 2 * EX);
+    } else {
+      cx = EX - 1;
+      cy = 1 + (h - 2 * EX - TY);
+    }
+  }
+  const int n = cy * EX + cx;
 
   // Tile from the workgroup index; with remap each XCD (workgroups dealt round
   // robin over 8) walks a contiguous range of tiles, x fastest.
   uint32_t tile = blockIdx.x;
   if (remap) {
-    const uint32_t n = gridDim.x, q8 = n >> 3, r8 = n & 7u, xcd = tile & 7u;
+    const uint32_t ng = gridDim.x, q8 = ng >> 3, r8 = ng & 7u, xcd = tile & 7u;
     tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (tile >> 3);
   }
   const uint32_t bx = tile % tiles_x;
@@ -75,16 +100,21 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(Pro
   const bool col_ok = (x_in || px) && (y_in || py);
   const int xl = x_in ? gx : ((gx % nx) + nx) % nx;
   const int yl = y_in ? gy : ((gy % ny) + ny) % ny;
-  const bool out_col = cx >= 1 && cx <= TX && cy >= 1 && cy <= TY && x_in && y_in;
+  const bool inner_t = t < inner;
+  const bool out_col = inner_t && x_in && y_in;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const uint32_t col = (uint32_t)xl + (uint32_t)nx * (uint32_t)yl;
+  // a block whose columns include a node next to an x or y wall (uniform): only
+  // there can an in-plane pull need the face rule
+  const bool tile_wall = WALLS && ((!px && (x0 - 1 <= 0 || x0 + TX >= nx - 1)) ||
+                                   (!py && (y0 - 1 <= 0 || y0 + TY >= ny - 1)));
 
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
 
-  // In-plane sources of this column (fixed for the whole march): for each
-  // in-plane direction the source column (wrapped), or -1 where the source lies
-  // beyond a wall (then the face rule applies).
+  // In-plane sources of this column (fixed for the whole march): the source
+  // column of each in-plane direction (wrapped across periodic faces), and
+  // whether it lies beyond a wall (then the face rule applies).
   int32_t src_col[4];
   bool wall_dir[4];
 #pragma unroll
@@ -101,39 +131,51 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(Pro
   }
 
   const uint64_t pstride = (uint64_t)p.plane * sizeof(T);
-  // first-level loads of plane pl (wrapped); beyond a z wall nothing is loaded
+  // First-level loads of plane pl (wrapped); beyond a z wall nothing is loaded.
+  // Planes are walked from an opaque scalar base in steps of the plane stride
+  // (species-major, direction-minor), each access that base plus the lane's
+  // 32-bit offset.  Where a pull may hit a wall (a wall block, or a plane next
+  // to a z wall) the plane of the node's own opposite population is chosen per
+  // lane instead.
   auto load_plane = [&](int pl, T (&ld)[M][Q]) __attribute__((always_inline)) {
     const bool p_in = pl >= 0 && pl < nz;
     if (!col_ok || !(p_in || pz)) return;
     const int zl = p_in ? pl : ((pl % nz) + nz) % nz;
     const uint32_t own = (uint32_t)zl * nxy + col;
+    const bool z_edge = WALLS && !pz && (zl == 0 || zl == nz - 1);
+    uint32_t off[Q];
+    bool flip[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const int a = L::axis(k), s = L::sgn(k), d = inplane_slot<LAT>(k);
-      uint32_t off = own;
-      bool flip = false;
+      off[k] = own;
+      flip[k] = false;
       if (a == 2) {
         const bool edge = s > 0 ? (zl == 0) : (zl == nz - 1);
         const int face = 4 + (s > 0 ? 0 : 1);
-        flip = WALLS && edge && p.bc[face] != BC_PERIODIC;
+        flip[k] = WALLS && edge && p.bc[face] != BC_PERIODIC;
         const int zs = edge ? (s > 0 ? nz - 1 : 0) : zl - s;
-        off = flip ? own : (uint32_t)zs * nxy + col;
+        off[k] = flip[k] ? own : (uint32_t)zs * nxy + col;
       } else if (d >= 0) {
-        flip = wall_dir[d];
-        off = flip ? own : (uint32_t)zl * nxy + (uint32_t)src_col[d];
+        flip[k] = wall_dir[d];
+        off[k] = flip[k] ? own : (uint32_t)zl * nxy + (uint32_t)src_col[d];
       }
-      const int kb = L::opp(k);
+    }
+    uint64_t b = scalar_base(src);
+    if (!(tile_wall || z_edge)) {
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        uint64_t b = scalar_base(src) + (uint64_t)(i * Q + k) * pstride;
-        if constexpr (WALLS) {
-          if (a >= 0) {
-            const uint64_t bb = scalar_base(src) + (uint64_t)(i * Q + kb) * pstride;
-            b = flip ? bb : b;
-          }
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k, b += pstride) ld[i][k] = gload<T>(b, off[k] * (uint32_t)sizeof(T), false);
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < Q; ++k, b += pstride) {
+          const int kb = L::opp(k);
+          const uint64_t bb = b + (uint64_t)((int64_t)(kb - k) * (int64_t)pstride);
+          ld[i][k] = gload<T>(flip[k] ? bb : b, off[k] * (uint32_t)sizeof(T), false);
         }
-        ld[i][k] = gload<T>(b, off * (uint32_t)sizeof(T), false);
-      }
     }
   };
   // Dirichlet faces: the pulled own opposite population v becomes 2 w xi_wall - v
@@ -198,14 +240,14 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(Pro
       const int d = inplane_slot<LAT>(k);
       if (d < 0) continue;
 #pragma unroll
-      for (int i = 0; i < M; ++i) lds_at(B, d, i, t) = f1[i][k];
+      for (int i = 0; i < M; ++i) lds_at(B, d, i, n) = f1[i][k];
     }
-    if (j >= 2) {
-      // second level: plane qz = pl - 1 of the tile
+    if (j >= 2 && inner_t) {
+      // second level: plane qz = pl - 1 of the tile (inner threads, whose
+      // neighbours are all in the block)
       const int qz = pl - 1;
       T f2[M][Q];
-      const int tm_x = cx > 0 ? t - 1 : t, tp_x = cx < EX - 1 ? t + 1 : t;
-      const int tm_y = cy > 0 ? t - EX : t, tp_y = cy < EY - 1 ? t + EX : t;
+      const int tm_x = n - 1, tp_x = n + 1, tm_y = n - EX, tp_y = n + EX;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         const int a = L::axis(k), s = L::sgn(k), d = inplane_slot<LAT>(k);
@@ -238,7 +280,7 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(Pro
               const int kb = L::opp(k), db = inplane_slot<LAT>(kb);
 #pragma unroll
               for (int i = 0; i < M; ++i) {
-                const T own = lds_at(B ^ 1, db, i, t);
+                const T own = lds_at(B ^ 1, db, i, n);
                 f2[i][k] = p.bc[face] == BC_ZERO_FLUX ? own : T(2.0 * L::w(kb)) * nc.wall[face][i] - own;
               }
             }
@@ -288,7 +330,7 @@ hipError_t launch_blocked3d(const LaunchArgs& a) {
     const uint32_t segs = (uint32_t)((a.p.nz + zseg - 1) / zseg);
     const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC || a.p.bc[4] != BC_PERIODIC;
     const size_t shmem = blocked3d_lds_bytes(M, (int)sizeof(T), tx, ty);
-    const dim3 grid(tiles_x * tiles_y * segs), block(tx + 2, ty + 2);
+    const dim3 grid(tiles_x * tiles_y * segs), block((tx + 2) * (ty + 2));
     const T* src = static_cast<const T*>(a.src);
     T* dst = static_cast<T*>(a.dst);
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
@@ -298,16 +340,16 @@ hipError_t launch_blocked3d(const LaunchArgs& a) {
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL((k_step_blocked3d<LAT, M, T, true>), grid, block, shmem, a.stream, a.p, src, dst, cst, tiles_x,
-                         tiles_y, zseg, a.xcd_remap);
+      hipLaunchKernelGGL((k_step_blocked3d<LAT, M, T, true>), grid, block, shmem, a.stream, a.p, src, dst, cst, tx, ty,
+                         tiles_x, tiles_y, zseg, a.xcd_remap);
     } else {
       if (shmem > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step_blocked3d<LAT, M, T, false>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL((k_step_blocked3d<LAT, M, T, false>), grid, block, shmem, a.stream, a.p, src, dst, cst,
-                         tiles_x, tiles_y, zseg, a.xcd_remap);
+      hipLaunchKernelGGL((k_step_blocked3d<LAT, M, T, false>), grid, block, shmem, a.stream, a.p, src, dst, cst, tx,
+                         ty, tiles_x, tiles_y, zseg, a.xcd_remap);
     }
     return hipSuccess;
   }

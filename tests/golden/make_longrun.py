@@ -14,7 +14,7 @@ fixed sample of nodes together with whole-field diagnostics:
                      z, 500 steps.
 
 Nothing here calls the HIP library.  Output: ``longrun_<case>.npz`` next to
-this script (numpy arrays only, no pickles).  The 2D case takes about ten
+this script (numpy arrays only, no pickles).  The 2D case takes ten to thirty
 minutes on one core.
 """
 from __future__ import annotations

@@ -1,0 +1,86 @@
+"""FP32 parity over the full run lengths of the 2D and 3D workloads.
+
+Rounding builds up over the iteration of Eq. (3-13), so the FP32 bound (1e-5
+absolute on mole fractions, 2e-6 on fluxes and gradients) is checked after as
+many steps as the workloads run: 2000 steps of the 2D ternary field (on a
+1024^2 lattice, through the default launch: temporally blocked passes) and 500
+steps of the 3D quaternary two-slab problem (on a 64^3 lattice, zero-flux x
+walls).  The expected values were written by tests/golden/make_longrun.py,
+which runs only the FP64 oracle on the inputs of ``workloads``; they are
+compared element by element at a fixed sample of nodes (4096 random nodes plus
+whole lines along every axis through the centre and two corners), and the
+whole-field species totals, minima and maxima are compared too."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with np.load(os.path.join(GOLDEN, f"longrun_{name}.npz"), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _check(w, g, launch_check):
+    from paper_1808_06787_amd.sim import Sim
+
+    assert tuple(g["shape"]) == tuple(w.shape) and int(g["steps"]) == w.steps
+    np.testing.assert_array_equal(g["D"], w.D)
+    sim = Sim(w.lattice, w.D, w.shape, w.precision, bc=w.bc)
+    launch_check(sim)
+    sim.init(torch.from_numpy(w.xi0))
+    sim.step(w.steps)
+    totals, mins, maxs, bad = sim.diagnostics()
+    xi, J, grad = sim.read(torch.float64)
+    torch.cuda.synchronize()
+    sim.close()
+    assert bad == 0
+    N = w.N
+    idx = torch.from_numpy(g["idx"]).to(xi.device)
+    gxi = xi.reshape(N, -1)[:, idx].cpu().numpy()
+    gJ = J.reshape(N - 1, len(w.shape), -1)[:, :, idx].cpu().numpy()
+    gg = grad.reshape(N - 1, len(w.shape), -1)[:, :, idx].cpu().numpy()
+    err_xi = np.abs(gxi - g["xi"]).max()
+    err_J = np.abs(gJ - g["J"]).max()
+    err_g = np.abs(gg - g["grad"]).max()
+    print(f"{w.name} x {w.steps}: max |dxi| {err_xi:.2e}, |dJ| {err_J:.2e}, |dgrad| {err_g:.2e} "
+          f"over {g['idx'].size} nodes")
+    assert err_xi <= 1e-5, err_xi
+    assert err_J <= 2e-6, err_J
+    assert err_g <= 2e-6, err_g
+    # whole field: totals to FP32 rounding (the diagnostics accumulate in FP64),
+    # extremes to the mole-fraction bound
+    np.testing.assert_allclose(totals, g["totals"], rtol=2e-6)
+    assert np.abs(mins - g["mins"]).max() <= 1e-5 and np.abs(maxs - g["maxs"]).max() <= 1e-5
+
+
+def test_ternary_2d_2000_steps_blocked():
+    w = workloads.ternary_2d(shape=(1024, 1024), seed=1, steps=2000)
+    g = _golden("ternary_2d")
+
+    def blocked(sim):
+        assert sim.steps_per_pass() == 6, "the default launch should run six-step passes here"
+
+    _check(w, g, blocked)
+
+
+@pytest.mark.parametrize("blocked", [False, True])
+def test_quaternary_3d_500_steps(blocked):
+    """The default launch runs this small lattice one step per pass; with an
+    explicit segment height and tile the same run takes the two-step 3D passes."""
+    w = workloads.quaternary_3d(shape=(64, 64, 64), seed=2, steps=500)
+    g = _golden("quaternary_3d")
+
+    def plan(sim):
+        if blocked:
+            sim.set_launch(temporal=2, seg_rows=8, tile_x=30, tile_y=22)
+        assert sim.steps_per_pass() == (2 if blocked else 1)
+
+    _check(w, g, plan)
