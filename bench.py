@@ -39,7 +39,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 Q = {"D1Q3": 3, "D2Q5": 5, "D3Q7": 7, "D1Q2": 2, "D2Q4": 4, "D3Q6": 6, "D2Q9": 9, "D3Q15": 15}
-KERNEL_SOURCES = ["paper_1808_06787_amd/csrc/msd_device.h", "paper_1808_06787_amd/csrc/msd_kernels.h"]
+KERNEL_SOURCES = ["paper_1808_06787_amd/csrc/msd_device.h", "paper_1808_06787_amd/csrc/msd_kernels.h",
+                  "paper_1808_06787_amd/csrc/msd_blocked3d.h"]
 
 
 def kernel_hash() -> str:
@@ -197,13 +198,18 @@ def measure(w, steps, warmup, launch=None):
 
 
 def hbm_roofline(w, rec):
-    """HBM roofline of a one-step-per-launch sweep: algorithmic bytes per launch
-    over the measured launch duration, and the counted traffic when a profile of
-    the current kernel sources is committed."""
-    bpl = pass_bytes(w)
+    """HBM roofline of the sweep kernel: algorithmic bytes per launch (the
+    per-step model, 2 q (N-1) value sizes per node, times the steps one launch
+    performs) over the measured launch duration, so that frac is the metric's
+    "% of HBM peak" (MLUPS x bytes per node-component update / peak).  With two
+    steps per launch the first step's values stay on chip, so the kernel moves
+    fewer bytes than that: `traffic` (rocprofv3 FETCH_SIZE + WRITE_SIZE per
+    launch, when a profile of the current kernel sources is committed) and its
+    rate say how busy HBM actually is."""
+    bpl = pass_bytes(w) * rec["steps_per_pass"]
     achieved = bpl / rec["per_launch"] / 1e9
     traffic = load_traffic(w.name)
-    return {
+    out = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -216,7 +222,21 @@ def hbm_roofline(w, rec):
         "ms_per_launch": round(rec["per_launch"] * 1e3, 5),
         "ms_per_launch_measured_over": rec["per_launch_over"],
         "traffic_over_algorithmic": round(traffic / bpl, 4) if traffic else None,
+        "traffic_GBps": round(traffic / rec["per_launch"] / 1e9, 1) if traffic else None,
+        "traffic_frac_of_hbm_peak": round(traffic / rec["per_launch"] / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
     }
+    valu_time = load_valu_time(w.name)
+    if valu_time:
+        out["valu_busy_frac_at_2.4GHz"] = round(valu_time / rec["per_launch"], 4)
+    return out
+
+
+def sweep_roofline(w, rec):
+    """The HBM roofline of the per-step bytes model while it bounds the kernel
+    (frac <= 1); a kernel that performs enough steps per launch to run past it
+    is reported against the ALU roofline instead."""
+    roof = hbm_roofline(w, rec)
+    return roof if roof["frac"] <= 1.0 else alu_roofline(w, rec)
 
 
 def alu_roofline(w, rec):
@@ -256,8 +276,10 @@ def alu_roofline(w, rec):
 
 
 def batched_extra(steps: int = 1000, warmup: int = 5):
-    """256-mixture workload: one launch per step (tuned schedule) against one launch
-    of the single-mixture sweep per mixture per step, same steps, same device."""
+    """256-mixture workload under the tuned batch schedule (graph replay of full
+    passes) against two references on the same stream and device: each mixture
+    as its own single-mixture handle with the default launch, and one launch of
+    the single-step sweep per mixture and step."""
     import tempfile
 
     import torch
@@ -293,16 +315,25 @@ def batched_extra(steps: int = 1000, warmup: int = 5):
     t_fused = timed(b.step)
     b.restore(state, t0)
     t_each = timed(b.step_each)
+    b.restore(state, t0)
+    t_sep = timed(b.step_separate)
+    sched = b.get_schedule()
     b.close()
     return {
         "mixtures": 256, "steps": steps, "node_component_updates_per_step": upd,
         "MLUPS_batched": round(upd * steps / t_fused / 1e6, 1),
-        "MLUPS_one_launch_per_mixture": round(upd * steps / t_each / 1e6, 1),
-        "speedup_vs_one_launch_per_mixture": round(t_each / t_fused, 3),
+        "MLUPS_separate_handles": round(upd * steps / t_sep / 1e6, 1),
+        "MLUPS_one_single_step_launch_per_mixture": round(upd * steps / t_each / 1e6, 1),
+        "speedup_vs_separate_handles": round(t_sep / t_fused, 3),
+        "speedup_vs_one_single_step_launch_per_mixture": round(t_each / t_fused, 3),
         "ms_per_step_batched": round(t_fused / steps * 1e3, 4),
-        "ms_per_step_one_launch_per_mixture": round(t_each / steps * 1e3, 4),
+        "ms_per_step_separate_handles": round(t_sep / steps * 1e3, 4),
+        "ms_per_step_one_single_step_launch_per_mixture": round(t_each / steps * 1e3, 4),
         "GB_per_s_batched": round(byt * steps / t_fused / 1e9, 1),
-        "schedule": tune["best"],
+        "schedule": sched,
+        "baselines": "separate handles: each mixture stepped as its own single-mixture handle with the default "
+                     "launch (its own plan: blocked passes where the plan takes them); one single-step launch per "
+                     "mixture and step: the single-step sweep only",
     }
 
 
@@ -465,9 +496,10 @@ def lattice_extras(extras):
         n_steps = 500 if wr.lattice.startswith("D2") else 100
         rr, simr = measure(wr, n_steps, 5)
         simr.close()
-        a = pass_bytes(wr) / rr["per_launch"] / 1e9
+        a = pass_bytes(wr) / rr["per_step"] / 1e9
         extras[name] = {"MLUPS": round(rr["mlups"], 1), "ms_per_step": round(rr["per_step"] * 1e3, 4),
-                        "steps": n_steps, "GB_per_s": round(a, 1), "hbm_frac": round(a / HBM_PEAK_GBS, 4)}
+                        "steps": n_steps, "steps_per_launch": rr["steps_per_pass"], "GB_per_s": round(a, 1),
+                        "hbm_frac": round(a / HBM_PEAK_GBS, 4)}
         print(f"# {name}: {rr['mlups']:.0f} MLUPS, {a:.0f} GB/s ({100 * a / HBM_PEAK_GBS:.1f}%)",
               file=sys.stderr, flush=True)
         del wr
@@ -525,7 +557,7 @@ def main():
     _, _, _, bad = sim.diagnostics(raise_on_diverged=False)
     sim.close()
     del sim
-    roof = hbm_roofline(w, rec) if rec["steps_per_pass"] == 1 else alu_roofline(w, rec)
+    roof = sweep_roofline(w, rec)
     out = {
         "metric": "MLUPS (node-component updates per second) of the fused collide-and-stream sweep",
         "value": round(rec["mlups"], 1),
@@ -552,7 +584,7 @@ def main():
         w2 = make_workload("ternary_2d")
         r2, sim2 = measure(w2, w2.steps, 5)
         sim2.close()
-        roof2 = alu_roofline(w2, r2) if r2["steps_per_pass"] > 1 else hbm_roofline(w2, r2)
+        roof2 = sweep_roofline(w2, r2)
         extras["ternary_2d_d2q5_4096^2_f32"] = {
             "MLUPS": round(r2["mlups"], 1), "ms_per_step": round(r2["per_step"] * 1e3, 5), "steps": w2.steps,
             "launch": r2["launch"], "roofline": roof2}
@@ -570,8 +602,10 @@ def main():
         print(f"# {w1.name}: {m1:.1f} MLUPS, {w1.steps / s1:.0f} steps/s", file=sys.stderr, flush=True)
         bx = batched_extra()
         extras["batched_256_mixtures_d2q5_f32"] = bx
-        print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS fused vs {bx['MLUPS_one_launch_per_mixture']:.0f} "
-              f"one launch per mixture ({bx['speedup_vs_one_launch_per_mixture']:.2f}x)", file=sys.stderr, flush=True)
+        print(f"# batched: {bx['MLUPS_batched']:.0f} MLUPS vs {bx['MLUPS_separate_handles']:.0f} separate handles "
+              f"({bx['speedup_vs_separate_handles']:.2f}x) and {bx['MLUPS_one_single_step_launch_per_mixture']:.0f} "
+              f"single-step launches ({bx['speedup_vs_one_single_step_launch_per_mixture']:.2f}x)",
+              file=sys.stderr, flush=True)
         ax = adjoint_extra()
         extras["adjoint_1024x1024_d2q5_ternary"] = ax
         print(f"# adjoint f32: backward/forward = {ax['f32']['backward_over_forward']:.2f}; FD check (f64) "

@@ -378,6 +378,13 @@ typedef struct msd_schedule {
                                block_y, order apply to their single steps); 0 or 1: one step
                                per launch.  Default 6 for D2Q5, 0 otherwise */
   int32_t seg_rows;         /* rows per workgroup of the blocked sweep (0: 16) */
+  int32_t graph;            /* 1 (default): msd_batch_step captures the launches of a span of
+                               full passes (twice the least common multiple of the classes'
+                               steps per pass, so every class ends on the buffer half it
+                               started from) into a HIP graph once per schedule and replays
+                               it for as many whole spans as a call holds (at t > 0); the
+                               rest of the call, and calls shorter than a span, launch
+                               directly.  0: always launch directly */
 } msd_schedule;
 
 /* Workspace bytes for a batch (every mixture's buffers and constants plus the
@@ -400,9 +407,15 @@ MSD_API int msd_batch_init(msd_batch* batch, int32_t index, const void* d_xi0, i
  * mixture initialised).  Asynchronous. */
 MSD_API int msd_batch_step(msd_batch* batch, int64_t nsteps);
 
-/* Reference schedule: the same steps with one launch of the single-mixture
- * sweep per mixture per step (what `count` separate msd_sim handles would do). */
+/* Reference schedules, mixture after mixture on the batch's stream:
+ * msd_batch_step_each runs one launch of the single-step sweep per mixture per
+ * step; msd_batch_step_separate advances each mixture exactly as its own
+ * msd_sim handle with the default launch would (msd_step's plan: the
+ * LDS-resident kernel for tiny domains, temporally blocked passes where the
+ * plan takes them, else single steps), i.e. what `count` separate handles
+ * do. */
 MSD_API int msd_batch_step_each(msd_batch* batch, int64_t nsteps);
+MSD_API int msd_batch_step_separate(msd_batch* batch, int64_t nsteps);
 
 MSD_API int64_t msd_batch_time(const msd_batch* batch);
 

@@ -74,6 +74,7 @@ class MsdSchedule(C.Structure):
         ("nontemporal", C.c_int32),
         ("temporal", C.c_int32),
         ("seg_rows", C.c_int32),
+        ("graph", C.c_int32),
     ]
 
 
@@ -138,6 +139,7 @@ def lib():
         "msd_batch_init": (C.c_int, [vp, i32, vp, i32]),
         "msd_batch_step": (C.c_int, [vp, i64]),
         "msd_batch_step_each": (C.c_int, [vp, i64]),
+        "msd_batch_step_separate": (C.c_int, [vp, i64]),
         "msd_batch_time": (i64, [vp]),
         "msd_batch_read_moments": (C.c_int, [vp, i32, i32, vp, vp, vp]),
         "msd_batch_diagnostics": (C.c_int, [vp, i32, P(C.c_double), P(C.c_double), P(C.c_double), P(i64)]),

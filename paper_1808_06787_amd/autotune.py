@@ -34,6 +34,7 @@ def _schedule_struct(batch, cand: dict) -> F.MsdSchedule:
     s.order = ORDERS[cur["order"]] if isinstance(cur["order"], str) else int(cur["order"])
     s.xcd_remap, s.nontemporal = int(cur["xcd_remap"]), int(cur["nontemporal"])
     s.temporal, s.seg_rows = int(cur["temporal"]), int(cur["seg_rows"])
+    s.graph = int(cur["graph"])
     return s
 
 
@@ -41,7 +42,8 @@ def _schedule_dict(s: F.MsdSchedule) -> dict:
     inv_m = {v: k for k, v in MODES.items()}
     inv_o = {v: k for k, v in ORDERS.items()}
     return dict(block_x=s.block_x, block_y=s.block_y, mode=inv_m[s.mode], order=inv_o[s.order],
-                xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows)
+                xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows,
+                graph=s.graph)
 
 
 def _launch_struct(sim, cand: dict) -> F.MsdLaunch:

@@ -1,9 +1,12 @@
 """Python binding of a batch of independent mixtures (argument marshalling only).
 
 All mixtures share lattice and precision; N, extents, D_ij, faces and
-relaxation rule may differ.  One `step` launch advances every node of every
-mixture by one time step; `step_each` does the same with one launch of the
-single-mixture sweep per mixture (the reference schedule).
+relaxation rule may differ.  `step` advances every mixture under the batch
+schedule (a few launches per pass over all mixtures, replayed from a captured
+HIP graph for long calls); the reference schedules run the mixtures one after
+another: `step_each` with one launch of the single-step sweep per mixture and
+step, `step_separate` exactly as separate single-mixture handles with their
+default launches would.
 """
 from __future__ import annotations
 
@@ -86,6 +89,9 @@ class Batch:
     def step_each(self, n: int = 1):
         F.check(self.lib.msd_batch_step_each(self._h, int(n)), "msd_batch_step_each")
 
+    def step_separate(self, n: int = 1):
+        F.check(self.lib.msd_batch_step_separate(self._h, int(n)), "msd_batch_step_separate")
+
     @property
     def time(self) -> int:
         return int(self.lib.msd_batch_time(self._h))
@@ -129,6 +135,7 @@ class Batch:
         s.order = ORDERS[cur["order"]] if isinstance(cur["order"], str) else int(cur["order"])
         s.xcd_remap, s.nontemporal = int(cur["xcd_remap"]), int(cur["nontemporal"])
         s.temporal, s.seg_rows = int(cur["temporal"]), int(cur["seg_rows"])
+        s.graph = int(cur["graph"])
         F.check(self.lib.msd_batch_set_schedule(self._h, C.byref(s)), "msd_batch_set_schedule")
 
     def get_schedule(self) -> dict:
@@ -137,7 +144,8 @@ class Batch:
         inv_m = {v: k for k, v in MODES.items()}
         inv_o = {v: k for k, v in ORDERS.items()}
         return dict(block_x=s.block_x, block_y=s.block_y, mode=inv_m[s.mode], order=inv_o[s.order],
-                    xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows)
+                    xcd_remap=s.xcd_remap, nontemporal=s.nontemporal, temporal=s.temporal, seg_rows=s.seg_rows,
+                    graph=s.graph)
 
     def state_bytes(self) -> int:
         return int(self.lib.msd_batch_state_bytes(self._h))

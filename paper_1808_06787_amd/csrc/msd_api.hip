@@ -241,23 +241,6 @@ void default_launch(const msd_problem* p, msd_launch* l) {
 
 using namespace msd::host;
 
-struct msd_sim {
-  msd_problem prob;          // pointers inside are not kept
-  msd::Problem kp;           // kernel copy of the problem
-  Layout L;
-  int m = 0, q = 0, d = 0;
-  char* ws = nullptr;
-  hipStream_t stream = nullptr;
-  int cur = 0;               // which half holds the state
-  int64_t t = 0;
-  bool initialised = false;
-  msd_launch launch{};
-  // resident workgroups of the blocked kernels by steps per pass (0: not queried)
-  mutable int resident_fwd[msd::kMaxStepsPerPass + 1] = {};
-  mutable int resident_adj[msd::kMaxStepsPerPass + 1] = {};
-  mutable int n_cu = 0;
-  mutable int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
-};
 
 static_assert(sizeof(msd_problem) == 120 && offsetof(msd_problem, c_t) == 64 && offsetof(msd_problem, bc) == 80 &&
                   offsetof(msd_problem, dilute) == 108 && offsetof(msd_problem, trt_magic) == 112,

@@ -107,6 +107,14 @@ struct msd_batch {
   msd_schedule sched{};
   int64_t t = 0;
   int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
+  // HIP graph of one span of full passes (see msd_batch_step), captured on a
+  // stream of its own; valid for the current schedule and the buffer halves
+  // the ranges were on at capture (graph_cur)
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  int64_t graph_span = 0;
+  std::vector<int> graph_cur;
+  bool graph_failed = false;
 };
 
 namespace {
@@ -154,7 +162,15 @@ void push_tiles(std::vector<msd::BatchTile>& out, const std::vector<int>& g, con
   }
 }
 
+void drop_graph(msd_batch* b) {
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  b->graph_exec = nullptr;
+  b->graph_span = 0;
+  b->graph_cur.clear();
+}
+
 int build_tiles(msd_batch* b) {
+  drop_graph(b);
   const msd_schedule& sc = b->sched;
   // launches over several mixtures need them on the same buffer half
   for (Member& M : b->mem) {
@@ -315,6 +331,7 @@ int msd_batch_create(const msd_problem* problems, int32_t count, void* d_ws, siz
   b->sched.nontemporal = 0;
   b->sched.temporal = b->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass : 0;
   b->sched.seg_rows = 0;
+  b->sched.graph = 1;
   const int s2 = build_tiles(b);
   if (s2 != MSD_OK) {
     delete b;
@@ -335,6 +352,7 @@ int msd_batch_set_schedule(msd_batch* b, const msd_schedule* sc) {
   if (sc->temporal < 0 || sc->temporal > msd::kMaxStepsPerPass)
     return fail(MSD_EINVAL, "temporal = %d must be 0..%d", sc->temporal, msd::kMaxStepsPerPass);
   if (sc->seg_rows < 0 || sc->seg_rows > (1 << 20)) return fail(MSD_EINVAL, "seg_rows = %d", sc->seg_rows);
+  if (sc->graph != 0 && sc->graph != 1) return fail(MSD_EINVAL, "graph = %d must be 0 or 1", sc->graph);
   b->sched = *sc;
   return build_tiles(b);
 }
@@ -375,11 +393,13 @@ static int all_initialised(const msd_batch* b) {
   return MSD_OK;
 }
 
-int msd_batch_step(msd_batch* b, int64_t nsteps) {
-  if (!b) return fail(MSD_EINVAL, "batch is NULL");
-  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
-  const int st = all_initialised(b);
-  if (st != MSD_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Launches of nsteps steps of every range on b->stream; advances the ranges'
+// buffer halves and the batch time.
+int step_direct(msd_batch* b, int64_t nsteps) {
   msd::LaunchArgs a;
   a.lattice = b->lattice;
   a.prec = b->prec;
@@ -430,6 +450,143 @@ int msd_batch_step(msd_batch* b, int64_t nsteps) {
       n += done;
     }
     for (int i : r.members) b->mem[i].cur = cur;
+  }
+  b->t += nsteps;
+  return MSD_OK;
+}
+
+int64_t gcd64(int64_t x, int64_t y) { return y == 0 ? x : gcd64(y, x % y); }
+
+// Steps of one graph span: twice the least common multiple of the ranges'
+// steps per pass, so that every range runs whole passes and an even number of
+// them (and ends on the buffer half it started from).
+int64_t graph_span(const msd_batch* b) {
+  int64_t l = 1;
+  for (const Range& r : b->ranges) {
+    const int64_t tb = r.tb >= 2 ? r.tb : 1;
+    l = l / gcd64(l, tb) * tb;
+  }
+  return 2 * l;
+}
+
+std::vector<int> range_halves(const msd_batch* b) {
+  std::vector<int> c;
+  for (const Range& r : b->ranges) c.push_back(b->mem[r.members[0]].cur);
+  return c;
+}
+
+// Capture one span of launches (nothing runs) and instantiate it.
+int capture_graph(msd_batch* b, int64_t span) {
+  drop_graph(b);
+  hipError_t e = hipSuccess;
+  if (!b->capture_stream) {
+    e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      b->capture_stream = nullptr;
+      return hip_fail(e, "batch capture stream");
+    }
+  }
+  const std::vector<int> halves = range_halves(b);
+  const int64_t t0 = b->t;
+  hipStream_t keep = b->stream;
+  e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+  b->stream = b->capture_stream;
+  const int st = step_direct(b, span);
+  b->stream = keep;
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+  // the capture recorded launches only: put time and halves back
+  b->t = t0;
+  for (size_t k = 0; k < b->ranges.size(); ++k)
+    for (int i : b->ranges[k].members) b->mem[i].cur = halves[k];
+  if (st != MSD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "batch graph capture");
+  e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->graph_exec = nullptr;
+    return hip_fail(e, "batch graph instantiate");
+  }
+  b->graph_span = span;
+  b->graph_cur = halves;
+  return MSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msd_batch_step(msd_batch* b, int64_t nsteps) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  int st = all_initialised(b);
+  if (st != MSD_OK) return st;
+  int64_t n = 0;
+  if (b->sched.graph && !b->graph_failed && nsteps > 0) {
+    // the step from time 0 reads pre-collision values: always direct
+    if (b->t == 0) {
+      st = step_direct(b, 1);
+      if (st != MSD_OK) return st;
+      n = 1;
+    }
+    const int64_t span = graph_span(b);
+    const int64_t reps = (nsteps - n) / span;
+    if (reps >= 1) {
+      if (!b->graph_exec || b->graph_span != span || b->graph_cur != range_halves(b)) {
+        st = capture_graph(b, span);
+        if (st != MSD_OK) {
+          // no graph on this device or stream setup: launch directly from now on
+          b->graph_failed = true;
+          drop_graph(b);
+        }
+      }
+      if (b->graph_exec) {
+        for (int64_t r = 0; r < reps; ++r) {
+          const hipError_t e = hipGraphLaunch(b->graph_exec, b->stream);
+          if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+        }
+        b->t += reps * span;
+        n += reps * span;
+      }
+    }
+  }
+  return step_direct(b, nsteps - n);
+}
+
+int msd_batch_step_separate(msd_batch* b, int64_t nsteps) {
+  if (!b) return fail(MSD_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(MSD_EINVAL, "nsteps < 0");
+  const int st0 = all_initialised(b);
+  if (st0 != MSD_OK) return st0;
+  for (int i = 0; i < b->count; ++i) {
+    Member& M = b->mem[i];
+    // a single-mixture handle over this mixture's part of the batch workspace,
+    // with the default launch of a new handle
+    msd_sim s;
+    s.prob = M.prob;
+    s.kp = M.kp;
+    s.L.nodes = M.nodes;
+    s.L.plane = M.plane;
+    s.L.consts_off = M.consts_off;
+    s.L.half_off[0] = M.half_off[0];
+    s.L.half_off[1] = M.half_off[1];
+    s.L.half_bytes = M.state_bytes;
+    s.m = M.m;
+    s.q = b->q;
+    s.d = b->d;
+    s.ws = b->ws;
+    s.stream = b->stream;
+    s.cur = M.cur;
+    s.t = b->t;
+    s.initialised = true;
+    default_launch(&M.prob, &s.launch);
+    const int st = msd_step(&s, nsteps);
+    if (st != MSD_OK) return st;
+    M.cur = s.cur;
   }
   b->t += nsteps;
   return MSD_OK;
@@ -562,15 +719,16 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
   std::snprintf(buf, sizeof(buf), "%s|batch|%d|%d|%d|%016llx", device_arch().c_str(), b->lattice, b->prec, b->count,
                 (unsigned long long)h);
   const std::string key = buf;
-  constexpr int K = 8;
+  constexpr int K = 9;
   auto pack = [](const msd_schedule& c, int64_t* v) {
     v[0] = c.block_x; v[1] = c.block_y; v[2] = c.mode; v[3] = c.order;
-    v[4] = c.xcd_remap; v[5] = c.nontemporal; v[6] = c.temporal; v[7] = c.seg_rows;
+    v[4] = c.xcd_remap; v[5] = c.nontemporal; v[6] = c.temporal; v[7] = c.seg_rows; v[8] = c.graph;
   };
   auto unpack = [](const int64_t* v) {
     msd_schedule c;
     c.block_x = (int32_t)v[0]; c.block_y = (int32_t)v[1]; c.mode = (int32_t)v[2]; c.order = (int32_t)v[3];
     c.xcd_remap = (int32_t)v[4]; c.nontemporal = (int32_t)v[5]; c.temporal = (int32_t)v[6]; c.seg_rows = (int32_t)v[7];
+    c.graph = (int32_t)v[8];
     return c;
   };
   int64_t cached[K];
@@ -594,6 +752,7 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
           for (int xcd : {0, 1}) {
             msd_schedule c{};
             c.block_x = bl[0]; c.block_y = bl[1]; c.mode = mode; c.order = order; c.xcd_remap = xcd;
+            c.graph = b->sched.graph;
             cand.push_back(c);
           }
     if (b->lattice == MSD_D2Q5)
@@ -602,7 +761,7 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
           for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED}) {
             msd_schedule c{};
             c.block_x = 64; c.block_y = 4; c.mode = MSD_BATCH_PER_CLASS; c.order = order;
-            c.temporal = tb; c.seg_rows = seg;
+            c.temporal = tb; c.seg_rows = seg; c.graph = b->sched.graph;
             cand.push_back(c);
           }
   }
@@ -635,7 +794,11 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
 }
 
 int msd_batch_destroy(msd_batch* b) {
-  if (b) (void)hipStreamSynchronize(b->stream);
+  if (b) {
+    (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  }
   delete b;
   return MSD_OK;
 }

@@ -97,3 +97,23 @@ int time_candidates(hipStream_t stream, int n, int steps, double budget_ms, Appl
 
 }  // namespace host
 }  // namespace msd
+
+// Host handle of one mixture (msd_create); the batch layer also builds
+// temporary handles over parts of a batch workspace (msd_batch_step_separate).
+struct msd_sim {
+  msd_problem prob;          // pointers inside are not kept
+  msd::Problem kp;           // kernel copy of the problem
+  msd::host::Layout L;
+  int m = 0, q = 0, d = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;               // which half holds the state
+  int64_t t = 0;
+  bool initialised = false;
+  msd_launch launch{};
+  // resident workgroups of the blocked kernels by steps per pass (0: not queried)
+  mutable int resident_fwd[msd::kMaxStepsPerPass + 1] = {};
+  mutable int resident_adj[msd::kMaxStepsPerPass + 1] = {};
+  mutable int n_cu = 0;
+  mutable int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
+};

@@ -245,3 +245,62 @@ def test_batched_workload_sampled():
             assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= 1e-5
             assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= 2e-6
     b.close()
+
+
+def test_graph_replays_match_direct_launches():
+    """msd_batch_step replays a captured graph of a span of full passes (twice the
+    least common multiple of the classes' steps per pass) for as many whole spans
+    as a call holds; the fields equal those of direct launches bit for bit after
+    every call, with reads, diagnostics and direct steps of the other batch in
+    between (graph replays are checked after the first one too)."""
+    rng = np.random.default_rng(76)
+    specs, fields = _specs("D2Q5", rng)
+    g = _batch("D2Q5", "f32", specs, fields)
+    d = _batch("D2Q5", "f32", specs, fields)
+    g.set_schedule(temporal=4, seg_rows=8, graph=1)
+    d.set_schedule(temporal=4, seg_rows=8, graph=0)
+    span = 24      # classes at 4 and 3 steps per pass (and single steps)
+    for n in (1, 3 * span + 5, 2 * span + 2, span, 7, span):
+        g.step(n)
+        d.step(n)
+        assert g.time == d.time
+        got, ref = _read_all(g), _read_all(d)
+        for a, b_ in zip(got, ref):
+            for x, y in zip(a, b_):
+                np.testing.assert_array_equal(x, y, err_msg=f"after {g.time} steps")
+        g.diagnostics(0)
+    t = g.time
+    for i, (sp, f) in enumerate(zip(specs, fields)):
+        p = oracle_problem("D2Q5", sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"],
+                           trt_magic=sp["trt_magic"])
+        if i in (0, 3):
+            assert_parity(got[i], oracle_run(p, f, t), "f32", f"graph mixture {i}")
+    g.close()
+    d.close()
+
+
+def test_separate_handles_reference_matches_oracle():
+    """msd_batch_step_separate advances each mixture as its own handle with the
+    default launch would: the tiny mixtures through the LDS-resident kernel, the
+    1024^2 one through automatic blocked passes, the rest one step per pass; every
+    mixture matches the oracle."""
+    from paper_1808_06787_amd.sim import Sim
+
+    rng = np.random.default_rng(77)
+    specs, fields = _specs("D2Q5", rng)
+    big = dict(D=rand_D(rng, 3), shape=(1024, 1024), bc=None, xi_wall=None, relax="paper", trt_magic=0.4)
+    specs.append(big)
+    fields.append(smooth_field(rng, 3, (1024, 1024), 0.1))
+    probe = Sim("D2Q5", big["D"], big["shape"], "f32")
+    assert probe.steps_per_pass() == 6
+    probe.close()
+    b = _batch("D2Q5", "f32", specs, fields)
+    b.step_separate(1)
+    b.step_separate(12)
+    assert b.time == 13
+    got = _read_all(b)
+    for i, (sp, f) in enumerate(zip(specs, fields)):
+        p = oracle_problem("D2Q5", sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"],
+                           trt_magic=sp["trt_magic"])
+        assert_parity(got[i], oracle_run(p, f, 13), "f32", f"separate mixture {i}")
+    b.close()
