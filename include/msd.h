@@ -257,6 +257,24 @@ MSD_API int msd_forward_checkpointed(msd_sim* sim, int64_t nsteps, int64_t every
 MSD_API int msd_adjoint(msd_sim* sim, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
                         double* d_dL_dxi0, double* h_dL_dD, void* d_scratch, size_t scratch_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * msd_adjoint with its scratch (accumulator, adjoint buffers, recomputation
+ * stack) in a device array that the library's code object holds, one per GPU
+ * the library runs on, MSD_STATIC_SCRATCH_BYTES in size and kept until the
+ * process ends.  Arguments and results as msd_adjoint; the caller still passes
+ * the checkpoints, dL/dxi and the outputs.  Nothing is allocated: no hipMalloc,
+ * hipFree or allocating library routine.  The array's address on the current
+ * device is looked up once per device (the handle's device must be current).
+ * MSD_ENOMEM when msd_adjoint_scratch_bytes for this handle and `every` exceeds
+ * MSD_STATIC_SCRATCH_BYTES (nothing is launched then).  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind (the accumulator is
+ * cleared by a kernel at the start of each call): calls that overlap on one
+ * GPU, from two threads or on two streams, race and give wrong results. */
+#define MSD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+MSD_API int msd_adjoint_noalloc(msd_sim* sim, int64_t nsteps, int64_t every, const void* d_ckpts,
+                                const double* d_dL_dxi, double* d_dL_dxi0, double* h_dL_dD);
+
 /* ---------------------------------------------------------------------------
  * Launch tuning of the single-mixture sweep
  * ------------------------------------------------------------------------- */

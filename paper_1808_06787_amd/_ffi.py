@@ -12,6 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmsd.so")
 
 ABI_VERSION = 4
+STATIC_SCRATCH_BYTES = 64 << 20   # MSD_STATIC_SCRATCH_BYTES
 MAX_SPECIES = 8
 
 D1Q3, D2Q5, D3Q7, D1Q2, D2Q4, D3Q6, D2Q9, D3Q15 = 1, 2, 3, 4, 5, 6, 7, 8
@@ -134,6 +135,7 @@ def lib():
         "msd_adjoint_scratch_bytes": (sz, [vp, i64]),
         "msd_forward_checkpointed": (C.c_int, [vp, i64, i64, vp]),
         "msd_adjoint": (C.c_int, [vp, i64, i64, vp, vp, vp, P(C.c_double), vp, sz]),
+        "msd_adjoint_noalloc": (C.c_int, [vp, i64, i64, vp, vp, vp, P(C.c_double)]),
         "msd_batch_workspace_bytes": (sz, [P(MsdProblem), i32, P(i32)]),
         "msd_batch_create": (C.c_int, [P(MsdProblem), i32, vp, sz, vp, P(vp)]),
         "msd_batch_init": (C.c_int, [vp, i32, vp, i32]),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -924,6 +925,56 @@ int msd_adjoint(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, 
     if (in_b) std::swap(a, b);
   }
   return msd_adjoint_finish(s, a, acc, d_dL_dxi0, h_dL_dD);
+}
+
+}  // extern "C"
+
+// Scratch of msd_adjoint_noalloc: a device array in this file's code object
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code its name stands for a host-side symbol, not a device address:
+// the device address comes from hipGetSymbolAddress, once per device, and only
+// that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[MSD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+int static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MSD_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msd_adjoint_noalloc(msd_sim* s, int64_t nsteps, int64_t every, const void* d_ckpts, const double* d_dL_dxi,
+                        double* d_dL_dxi0, double* h_dL_dD) {
+  if (!s || !d_dL_dxi) return fail(MSD_EINVAL, "NULL argument");
+  if (every < 1) return fail(MSD_EINVAL, "every = %lld", (long long)every);
+  const size_t need = adjoint_scratch(s, every).total;
+  if (need > MSD_STATIC_SCRATCH_BYTES)
+    return fail(MSD_ENOMEM, "adjoint scratch of %zu bytes exceeds the static array of %zu bytes (msd_adjoint takes "
+                "caller scratch of any size)", need, (size_t)MSD_STATIC_SCRATCH_BYTES);
+  void* p = nullptr;
+  const int st = static_scratch(&p);
+  if (st != MSD_OK) return st;
+  return msd_adjoint(s, nsteps, every, d_ckpts, d_dL_dxi, d_dL_dxi0, h_dL_dD, p, MSD_STATIC_SCRATCH_BYTES);
 }
 
 int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t steps, double budget_ms,
