@@ -167,8 +167,45 @@ MSD_API int msd_read_moments(msd_sim* sim, int32_t out_precision, void* d_xi, vo
  * call synchronises the stream): per-species totals sum_x xi_i (constant for
  * periodic and zero-flux faces, Eq. (2-1)), per-species minimum and maximum
  * (arrays of N; may be NULL) and the number of non-finite mole fractions.
- * Returns MSD_EDIVERGED when that number is non-zero. */
+ * Returns MSD_EDIVERGED (outputs filled, msd_last_error names the check) when
+ *   - any mole fraction is not finite;
+ *   - a mole fraction is below -neg_tol (msd_health; mole fractions of a
+ *     converging run stay in [0, 1] up to rounding);
+ *   - a species total differs from its value at msd_init by more than
+ *     mass_rtol times the node count (checked only when no face is Dirichlet:
+ *     periodic and zero-flux faces conserve every total, Eq. (2-1)).  msd_init
+ *     records the totals of the initial field; msd_restore keeps them. */
 MSD_API int msd_diagnostics(msd_sim* sim, double* h_mass, double* h_min, double* h_max, int64_t* h_nonfinite);
+
+/* Limits of the divergence checks in msd_diagnostics; a negative value turns a
+ * check off.  Defaults: neg_tol = 1e-2, mass_rtol = 1e-4. */
+typedef struct msd_health {
+  double neg_tol;
+  double mass_rtol;
+} msd_health;
+MSD_API int msd_set_health(msd_sim* sim, const msd_health* health);
+MSD_API int msd_get_health(const msd_sim* sim, msd_health* health);
+
+/* Linear stability of the relaxation (host computation, no device work).  At
+ * each of `count` compositions (N mole fractions each, xi_N taken as 1 - the sum
+ * of the first N - 1 as in the sweep; with problem->linearized the composition
+ * is ignored and B is taken at xi_ref) this forms B (Eq. (2-10), or the
+ * dilute-species B of Remark III), Lambda_1 = 2 (I - (I + (a/2) B)^-1) (Eq. (3-26)
+ * with D~ = B^-1) and Lambda_2 (Eq. (3-16), TRT or SRT as the problem says), and
+ * returns the spectral radii of I - Lambda_1 and I - Lambda_2 in h_rho[2 c] and
+ * h_rho[2 c + 1]: the factors by which one collision scales the odd and the even
+ * non-equilibrium moments.  Both below 1 is needed for the relaxation to damp
+ * them (eig Lambda in (0, 2) for real eigenvalues); Eq. (3-16) can exceed that
+ * at extreme compositions.  Radii come from Gelfand's formula (norms of
+ * repeated squares), accurate to far below 1e-6.  Errors: MSD_EINVAL and the
+ * problem validation codes. */
+MSD_API int msd_relaxation_radius(const msd_problem* problem, const double* h_xi, int32_t count, double* h_rho);
+
+/* The largest radii msd_create found over the compositions it checks: the N
+ * pure species, the equimolar mixture, the Dirichlet face compositions and
+ * xi_ref (linearised theory).  A value >= 1 warns that the relaxation does not
+ * damp every mode there (the handle is still created). */
+MSD_API int msd_stability(const msd_sim* sim, double* h_rho1, double* h_rho2);
 
 /* Checkpoint / restart: the state is the m*q planes of distributions of the
  * current buffer; msd_state_bytes is its size.  msd_save copies it (device to

@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmsd.so")
+# MSD_LIBRARY selects another build of the same library (e.g. the host
+# AddressSanitizer build of build_asan.py for the CPU tests of the C ABI)
+LIB_PATH = os.environ.get("MSD_LIBRARY") or os.path.join(_PKG, "libmsd.so")
 
 ABI_VERSION = 4
 STATIC_SCRATCH_BYTES = 64 << 20   # MSD_STATIC_SCRATCH_BYTES
@@ -84,6 +86,13 @@ TUNE_IGNORE_CACHE = 1
 ORDER_INSTANCE, ORDER_INTERLEAVED = 0, 1
 
 
+class MsdHealth(C.Structure):
+    _fields_ = [
+        ("neg_tol", C.c_double),
+        ("mass_rtol", C.c_double),
+    ]
+
+
 class MsdError(RuntimeError):
     def __init__(self, status: int, what: str, detail: str):
         self.status = status
@@ -121,6 +130,10 @@ def lib():
         "msd_time": (i64, [vp]),
         "msd_read_moments": (C.c_int, [vp, i32, vp, vp, vp]),
         "msd_diagnostics": (C.c_int, [vp, P(C.c_double), P(C.c_double), P(C.c_double), P(i64)]),
+        "msd_set_health": (C.c_int, [vp, P(MsdHealth)]),
+        "msd_get_health": (C.c_int, [vp, P(MsdHealth)]),
+        "msd_relaxation_radius": (C.c_int, [P(MsdProblem), P(C.c_double), i32, P(C.c_double)]),
+        "msd_stability": (C.c_int, [vp, P(C.c_double), P(C.c_double)]),
         "msd_state_bytes": (sz, [vp]),
         "msd_save": (C.c_int, [vp, vp, P(i64)]),
         "msd_restore": (C.c_int, [vp, vp, i64]),

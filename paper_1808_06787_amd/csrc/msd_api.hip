@@ -205,6 +205,9 @@ Layout layout_for(const msd_problem* p) {
   L.diag_out_off = off;
   // diagnostics use 3N + 1 values, the adjoint's dL/dD N * N
   off = align_up(off + sizeof(double) * (MSD_MAX_SPECIES * MSD_MAX_SPECIES + 3 * MSD_MAX_SPECIES + 1), 256);
+  // diagnostics of the initial field (its species totals are the reference of the drift check)
+  L.ref_off = off;
+  off = align_up(off + sizeof(double) * (3 * MSD_MAX_SPECIES + 1), 256);
   L.half_bytes = align_up((size_t)m * q * (size_t)L.plane * s, 256);
   L.half_off[0] = off;
   off += L.half_bytes;
@@ -408,6 +411,117 @@ Blocked3dPlan blocked3d_plan(const msd_sim* s) {
   return pl;
 }
 
+// ---------------------------------------------------------------------------
+// Relaxation radii on the host (msd_relaxation_radius, msd_create).
+// ---------------------------------------------------------------------------
+double lattice_cs2(int lat) {
+  switch (lat) {
+    case MSD_D3Q7: return 0.25;
+    case MSD_D1Q2: return 1.0;
+    case MSD_D2Q4: return 0.5;
+    default: return 1.0 / 3.0;   // D1Q3, D2Q5, D3Q6, D2Q9, D3Q15
+  }
+}
+
+constexpr int kMaxM = MSD_MAX_SPECIES - 1;
+
+// Spectral radius of the m x m matrix A by Gelfand's formula: A^(2^s) by
+// repeated squaring, renormalised by its largest entry each time, the log
+// scale accumulated; log rho = lim log ||A^k|| / k.
+double spectral_radius(const double (&A)[kMaxM][kMaxM], int m) {
+  double P[kMaxM][kMaxM], Q[kMaxM][kMaxM];
+  double big = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) big = std::max(big, std::fabs(A[i][j]));
+  if (big == 0.0) return 0.0;
+  double logs = std::log(big);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) P[i][j] = A[i][j] / big;
+  double k = 1.0;
+  for (int it = 0; it < 48; ++it) {
+    double mx = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += P[i][l] * P[l][j];
+        Q[i][j] = acc;
+        mx = std::max(mx, std::fabs(acc));
+      }
+    if (mx == 0.0) return 0.0;   // nilpotent
+    logs = 2.0 * logs + std::log(mx);
+    k *= 2.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) P[i][j] = Q[i][j] / mx;
+  }
+  return std::exp(logs / k);
+}
+
+// Radii of I - Lambda_1 and I - Lambda_2 at composition xi (N values; the
+// first N - 1 are used, xi_N = 1 - their sum), for a validated problem.
+void relax_radius(const msd_problem* p, const double* xi, double* rho1, double* rho2) {
+  const int N = p->n_species, m = N - 1;
+  double xb[MSD_MAX_SPECIES];
+  double xn = 1.0;
+  for (int i = 0; i < m; ++i) {
+    xb[i] = p->linearized && p->xi_ref ? p->xi_ref[i] : xi[i];
+    xn -= xb[i];
+  }
+  auto R = [&](int i, int j) { return 1.0 / p->D[i * N + j]; };
+  const double h = 0.5 * lattice_cs2(p->lattice);
+  // A = I + (a/2) B with B of Eq. (2-10) (or the diagonal dilute-species B)
+  double A[kMaxM][2 * kMaxM] = {};
+  for (int i = 0; i < m; ++i) {
+    double bii;
+    if (p->dilute) {
+      bii = xn * R(i, m);
+      for (int k = 0; k < m; ++k)
+        if (k != i) bii += xb[k] * R(i, k);
+    } else {
+      bii = R(i, m);
+      for (int k = 0; k < m; ++k) {
+        if (k == i) continue;
+        const double S = R(i, k) - R(i, m);
+        bii += xb[k] * S;
+        A[i][k] = -h * xb[i] * S;
+      }
+    }
+    A[i][i] = 1.0 + h * bii;
+    A[i][m + i] = 1.0;
+  }
+  // K = A^-1 by Gauss-Jordan elimination with partial pivoting
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int j = 0; j < 2 * m; ++j) std::swap(A[c][j], A[piv][j]);
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 2 * m; ++j) A[c][j] *= inv;
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c];
+      for (int j = 0; j < 2 * m; ++j) A[r][j] -= f * A[c][j];
+    }
+  }
+  // I - Lambda_1 = 2K - I; Lambda_2 replaces the diagonal by the product rule
+  // (1/l1 - 1/2)(1/l2 - 1/2) = magic (Eq. (3-16) is magic = 3/16) unless SRT
+  double M1[kMaxM][kMaxM], M2[kMaxM][kMaxM];
+  const double magic = p->relax == MSD_RELAX_TRT ? p->trt_magic : 3.0 / 16.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const double l1 = (i == j ? 2.0 : 0.0) - 2.0 * A[i][m + j];
+      M1[i][j] = (i == j ? 1.0 : 0.0) - l1;
+      double l2 = l1;
+      if (i == j && p->relax != MSD_RELAX_SRT) {
+        const double g1 = 1.0 - 4.0 * magic;
+        l2 = 2.0 * (2.0 - l1) / (2.0 - g1 * l1);
+      }
+      M2[i][j] = (i == j ? 1.0 : 0.0) - l2;
+    }
+  *rho1 = spectral_radius(M1, m);
+  *rho2 = spectral_radius(M2, m);
+}
+
 bool use_lds(const msd_sim* s) {
   if (!s->launch.lds_resident) return false;
   const int64_t cap = msd::lds_resident_max_nodes(s->m, s->q, s->prob.precision);
@@ -469,6 +583,34 @@ int msd_create(const msd_problem* problem, void* d_ws, size_t ws_bytes, void* st
   s->stream = static_cast<hipStream_t>(stream);
   fill_kernel_problem(problem, L.plane, &s->kp);
   default_launch(problem, &s->launch);
+  // relaxation radii at the pure species, the equimolar mixture, the Dirichlet
+  // face compositions and the linearisation composition
+  {
+    const int N = problem->n_species;
+    double xi[MSD_MAX_SPECIES];
+    auto check = [&]() {
+      double r1 = 0.0, r2 = 0.0;
+      relax_radius(problem, xi, &r1, &r2);
+      s->rho1 = std::max(s->rho1, r1);
+      s->rho2 = std::max(s->rho2, r2);
+    };
+    for (int v = 0; v < N; ++v) {
+      for (int i = 0; i < N; ++i) xi[i] = i == v ? 1.0 : 0.0;
+      check();
+    }
+    for (int i = 0; i < N; ++i) xi[i] = 1.0 / N;
+    check();
+    if (problem->xi_wall)
+      for (int f = 0; f < 6; ++f)
+        if (problem->bc[f] == MSD_BC_DIRICHLET) {
+          for (int i = 0; i < N; ++i) xi[i] = problem->xi_wall[f * N + i];
+          check();
+        }
+    if (problem->linearized && problem->xi_ref) {
+      for (int i = 0; i < N; ++i) xi[i] = problem->xi_ref[i];
+      check();
+    }
+  }
   *out = s;
   return MSD_OK;
 }
@@ -530,6 +672,16 @@ int msd_init(msd_sim* s, const void* d_xi0, int32_t xi0_precision) {
   a.dst = s->ws + s->L.half_off[0];
   e = dispatch(msd::Op::Init, a);
   if (e != hipSuccess) return hip_fail(e, "init kernel");
+  // totals of the initial field: the reference of the drift check in msd_diagnostics
+  a.src = s->ws + s->L.half_off[0];
+  a.pull = 0;
+  a.partials = reinterpret_cast<double*>(s->ws + s->L.partials_off);
+  a.diag_out = reinterpret_cast<double*>(s->ws + s->L.ref_off);
+  a.diag_blocks = s->L.diag_blocks;
+  e = dispatch(msd::Op::DiagPartial, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics kernel");
+  e = dispatch(msd::Op::DiagFinal, a);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics reduction kernel");
   s->t = 0;
   s->initialised = true;
   return MSD_OK;
@@ -630,8 +782,10 @@ int msd_diagnostics(msd_sim* s, double* h_mass, double* h_min, double* h_max, in
   e = dispatch(msd::Op::DiagFinal, a);
   if (e != hipSuccess) return hip_fail(e, "diagnostics reduction kernel");
   const int N = s->prob.n_species;
-  double host[3 * MSD_MAX_SPECIES + 1];
+  double host[3 * MSD_MAX_SPECIES + 1], ref[MSD_MAX_SPECIES];
   e = hipMemcpyAsync(host, a.diag_out, sizeof(double) * (3 * N + 1), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
+  e = hipMemcpyAsync(ref, s->ws + s->L.ref_off, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics synchronise");
@@ -643,6 +797,47 @@ int msd_diagnostics(msd_sim* s, double* h_mass, double* h_min, double* h_max, in
   const int64_t bad = (int64_t)host[3 * N];
   if (h_nonfinite) *h_nonfinite = bad;
   if (bad) return fail(MSD_EDIVERGED, "%lld non-finite mole fractions", (long long)bad);
+  const msd_health& hl = s->health;
+  for (int i = 0; i < N; ++i)
+    if (hl.neg_tol >= 0.0 && host[N + i] < -hl.neg_tol)
+      return fail(MSD_EDIVERGED, "mole fraction of species %d down to %g (below -%g)", i + 1, host[N + i],
+                  hl.neg_tol);
+  bool dirichlet = false;
+  for (int f = 0; f < 6; ++f) dirichlet = dirichlet || s->prob.bc[f] == MSD_BC_DIRICHLET;
+  if (!dirichlet && hl.mass_rtol >= 0.0)
+    for (int i = 0; i < N; ++i)
+      if (std::fabs(host[i] - ref[i]) > hl.mass_rtol * (double)s->L.nodes)
+        return fail(MSD_EDIVERGED, "total of species %d drifted from %.17g to %.17g (more than %g per node)", i + 1,
+                    ref[i], host[i], hl.mass_rtol);
+  return MSD_OK;
+}
+
+int msd_set_health(msd_sim* s, const msd_health* h) {
+  if (!s || !h) return fail(MSD_EINVAL, "NULL argument");
+  if (std::isnan(h->neg_tol) || std::isnan(h->mass_rtol)) return fail(MSD_EINVAL, "NaN limit");
+  s->health = *h;
+  return MSD_OK;
+}
+
+int msd_get_health(const msd_sim* s, msd_health* h) {
+  if (!s || !h) return fail(MSD_EINVAL, "NULL argument");
+  *h = s->health;
+  return MSD_OK;
+}
+
+int msd_relaxation_radius(const msd_problem* problem, const double* h_xi, int32_t count, double* h_rho) {
+  const int st = validate(problem);
+  if (st != MSD_OK) return st;
+  if (count < 0 || (count > 0 && (!h_xi || !h_rho))) return fail(MSD_EINVAL, "count = %d or NULL arrays", count);
+  const int N = problem->n_species;
+  for (int32_t c = 0; c < count; ++c) relax_radius(problem, h_xi + (size_t)c * N, &h_rho[2 * c], &h_rho[2 * c + 1]);
+  return MSD_OK;
+}
+
+int msd_stability(const msd_sim* s, double* h_rho1, double* h_rho2) {
+  if (!s) return fail(MSD_EINVAL, "sim is NULL");
+  if (h_rho1) *h_rho1 = s->rho1;
+  if (h_rho2) *h_rho2 = s->rho2;
   return MSD_OK;
 }
 

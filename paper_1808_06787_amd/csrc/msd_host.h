@@ -31,7 +31,7 @@ constexpr int kDiagBlocksMax = 1024;
 // Workspace layout of one mixture (byte offsets from the workspace base).
 struct Layout {
   int64_t nodes = 0, plane = 0;
-  size_t consts_off = 0, partials_off = 0, diag_out_off = 0, half_off[2] = {0, 0};
+  size_t consts_off = 0, partials_off = 0, diag_out_off = 0, ref_off = 0, half_off[2] = {0, 0};
   size_t half_bytes = 0, total = 0;
   int diag_blocks = 0;
 };
@@ -116,4 +116,6 @@ struct msd_sim {
   mutable int resident_adj[msd::kMaxStepsPerPass + 1] = {};
   mutable int n_cu = 0;
   mutable int lds_per_cu = -1;   // LDS bytes per CU of the device (0: unknown)
+  msd_health health{1e-2, 1e-4};  // limits of the divergence checks in msd_diagnostics
+  double rho1 = 0.0, rho2 = 0.0;  // largest relaxation radii found by msd_create
 };

@@ -8,6 +8,7 @@ gradients (N-1, d, ...), all in lattice units.
 from __future__ import annotations
 
 import ctypes as C
+import warnings
 from typing import Optional, Sequence
 
 import numpy as np
@@ -79,6 +80,23 @@ def make_problem(lattice: str, D, shape: Sequence[int], precision: str = "f32", 
     return p, keep
 
 
+def relaxation_radius(lattice: str, D, compositions, relax: str = "paper", trt_magic: float = F.MAGIC_PAPER,
+                      dilute: bool = False, xi_ref=None):
+    """Spectral radii of I - Lambda_1 and I - Lambda_2 (msd_relaxation_radius) at each of
+    the given compositions (array (count, N)); host computation, no device.  Returns
+    an array (count, 2)."""
+    Dm = np.asarray(D, dtype=np.float64)
+    N = Dm.shape[0]
+    shape = (1,) * DIMS[lattice]
+    p, keep = make_problem(lattice, Dm, shape, "f64", relax=relax, trt_magic=trt_magic, dilute=dilute,
+                           xi_ref=xi_ref)
+    xi = np.ascontiguousarray(np.asarray(compositions, dtype=np.float64).reshape(-1, N))
+    out = np.zeros((xi.shape[0], 2))
+    F.check(F.lib().msd_relaxation_radius(C.byref(p), xi.ctypes.data_as(C.POINTER(C.c_double)), xi.shape[0],
+                                          out.ctypes.data_as(C.POINTER(C.c_double))), "msd_relaxation_radius")
+    return out
+
+
 class Sim:
     """One mixture on one lattice, evolved by the HIP sweep."""
 
@@ -104,6 +122,11 @@ class Sim:
         F.check(self.lib.msd_create(C.byref(self.problem), C.c_void_p(_dptr(self.workspace)), C.c_size_t(nbytes),
                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)), "msd_create")
         self._h = h
+        r1, r2 = self.stability()
+        if r1 >= 1.0 or r2 >= 1.0:
+            warnings.warn(f"relaxation does not damp every mode at some checked composition (spectral radii of "
+                          f"I - Lambda_1, I - Lambda_2: {r1:.6f}, {r2:.6f}); the run may diverge", RuntimeWarning,
+                          stacklevel=2)
 
     # -- lifetime ---------------------------------------------------------------
     def close(self):
@@ -194,6 +217,23 @@ class Sim:
         if st != F.OK and (raise_on_diverged or st != -6):
             F.check(st, "msd_diagnostics")
         return np.array(mass[:]), np.array(mn[:]), np.array(mx[:]), int(bad.value)
+
+    def set_health(self, neg_tol: Optional[float] = None, mass_rtol: Optional[float] = None):
+        """Limits of the divergence checks of diagnostics() (negative: off)."""
+        h = F.MsdHealth()
+        F.check(self.lib.msd_get_health(self._h, C.byref(h)), "msd_get_health")
+        if neg_tol is not None:
+            h.neg_tol = float(neg_tol)
+        if mass_rtol is not None:
+            h.mass_rtol = float(mass_rtol)
+        F.check(self.lib.msd_set_health(self._h, C.byref(h)), "msd_set_health")
+
+    def stability(self):
+        """(rho1, rho2): the largest spectral radii of I - Lambda_1 and I - Lambda_2 found
+        at the compositions checked when the handle was created."""
+        r1, r2 = C.c_double(0.0), C.c_double(0.0)
+        F.check(self.lib.msd_stability(self._h, C.byref(r1), C.byref(r2)), "msd_stability")
+        return float(r1.value), float(r2.value)
 
     def state_bytes(self) -> int:
         return int(self.lib.msd_state_bytes(self._h))

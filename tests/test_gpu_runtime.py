@@ -67,6 +67,75 @@ def test_diagnostics_flag_non_finite_input():
     s.close()
 
 
+def test_diagnostics_flag_negative_mole_fractions():
+    """A mole fraction below -neg_tol (default 1e-2) is divergence; the check can
+    be loosened or turned off."""
+    from paper_1808_06787_amd._ffi import MsdError
+
+    rng = np.random.default_rng(14)
+    D = rand_D(rng, 3)
+    xi0 = smooth_field(rng, 3, (30, 40), 0.1)
+    xi0[0, 3, 5] = -0.2
+    xi0[1, 3, 5] = 1.2 - xi0[2, 3, 5]
+    s = _sim("D2Q5", D, (40, 30), "f32", xi0)
+    with pytest.raises(MsdError) as e:
+        s.diagnostics()
+    assert e.value.status == -6 and "species 1" in str(e.value)
+    s.set_health(neg_tol=0.5)
+    s.diagnostics()
+    s.set_health(neg_tol=-1.0)
+    s.diagnostics()
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_diagnostics_flag_species_total_drift(precision):
+    """Species totals are conserved with periodic and zero-flux faces (Eq. (2-1));
+    restoring a state with other totals (forced from the host) is drift past
+    mass_rtol per node.  With a Dirichlet face, which exchanges species with the
+    outside, the drift check is off."""
+    from paper_1808_06787_amd._ffi import MsdError
+
+    rng = np.random.default_rng(15)
+    D = rand_D(rng, 3)
+    shape = (40, 30)
+    a = _sim("D2Q5", D, shape, precision, smooth_field(rng, 3, shape[::-1], 0.1))
+    other = smooth_field(rng, 3, shape[::-1], 0.1)
+    other[0] *= 0.9
+    other[1] = 1.0 - other[0] - other[2]
+    b = _sim("D2Q5", D, shape, precision, other)
+    a.step(7)
+    a.diagnostics()                  # conserved: no error
+    state, t = b.save()
+    a.restore(state, t)
+    with pytest.raises(MsdError) as e:
+        a.diagnostics()
+    assert e.value.status == -6 and "drifted" in str(e.value)
+    a.set_health(mass_rtol=-1.0)
+    a.diagnostics()
+    a.close()
+    b.close()
+    bc = (("dirichlet", "zero_flux"), ("periodic", "periodic"))
+    walls = {(0, 0): np.array([0.8, 0.1, 0.1])}
+    c = _sim("D2Q5", D, shape, precision, smooth_field(rng, 3, shape[::-1], 0.1), bc=bc, xi_wall=walls)
+    c.step(200)
+    c.diagnostics()                  # totals change through the Dirichlet face
+    c.close()
+
+
+def test_create_warns_where_the_relaxation_does_not_damp():
+    """A Dirichlet face at a composition where Eq. (3-16) gives rho(I - Lambda_2) > 1."""
+    from paper_1808_06787_amd.sim import Sim
+    from test_stability_cpu import UNSTABLE_D, UNSTABLE_XI
+
+    bc = (("dirichlet", "zero_flux"), ("periodic", "periodic"), ("periodic", "periodic"))
+    with pytest.warns(RuntimeWarning, match="does not damp"):
+        s = Sim("D3Q7", UNSTABLE_D, (8, 8, 8), "f32", bc=bc, xi_wall={(0, 0): UNSTABLE_XI})
+    r1, r2 = s.stability()
+    assert r2 > 1.0
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_checkpoint_restore_is_bitwise(precision):
     rng = np.random.default_rng(14)

@@ -1,0 +1,139 @@
+"""Host-side stability and health checks of the C ABI (no device work):
+msd_relaxation_radius against eigenvalues of the oracle's relaxation matrices
+(Eqs. (2-10), (2-11), (3-26), (3-16)), closed forms, an unstable composition
+that msd_create flags, and the health-limit calls."""
+import ctypes as C
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import lattice as olat
+from oracle import ms
+from paper_1808_06787_amd import _ffi as F
+from paper_1808_06787_amd.sim import make_problem, relaxation_radius
+
+RELAX = {"paper": ms.RELAX_PAPER, "srt": ms.RELAX_SRT, "trt": ms.RELAX_TRT}
+
+
+def _rand_D(rng, n, lo=0.02, hi=0.8):
+    D = np.ones((n, n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            D[i, j] = D[j, i] = np.exp(rng.uniform(np.log(lo), np.log(hi)))
+    return D
+
+
+def _oracle_radii(lattice, D, xi, relax, magic, dilute, xi_ref):
+    """Spectral radii of I - Lambda_1, I - Lambda_2 from the oracle's literal route
+    (B -> D~ = B^-1 -> Lambda_1 by inverting Eq. (3-26) -> Lambda_2), numpy eigenvalues."""
+    x = np.asarray(xi_ref if xi_ref is not None else xi, dtype=np.float64)[None]
+    B = (ms.ms_B_dilute if dilute else ms.ms_B)(x, D)
+    L1 = ms.lambda1_from_fick(ms.fick_matrix(B), olat.get(lattice).cs2, 1.0)
+    L2 = ms.lambda2_from_lambda1(L1, RELAX[relax], magic)
+    m = D.shape[0] - 1
+    r1 = np.abs(np.linalg.eigvals(np.eye(m) - L1[0])).max()
+    r2 = np.abs(np.linalg.eigvals(np.eye(m) - L2[0])).max()
+    return r1, r2
+
+
+@pytest.mark.parametrize("lattice", ["D1Q3", "D2Q5", "D3Q7", "D2Q4", "D3Q6", "D1Q2"])
+@pytest.mark.parametrize("relax", ["paper", "srt", "trt"])
+@pytest.mark.parametrize("mode", ["full", "dilute", "linearised"])
+def test_relaxation_radius_matches_oracle_eigenvalues(lattice, relax, mode):
+    rng = np.random.default_rng(zlib.crc32(f"{lattice}/{relax}/{mode}".encode()))
+    for N in (2, 3, 4, 5):
+        D = _rand_D(rng, N)
+        xi = rng.dirichlet(np.ones(N), size=6)
+        xi_ref = rng.dirichlet(np.ones(N)) if mode == "linearised" else None
+        got = relaxation_radius(lattice, D, xi, relax=relax, trt_magic=0.3, dilute=mode == "dilute", xi_ref=xi_ref)
+        for c in range(xi.shape[0]):
+            want = _oracle_radii(lattice, D, xi[c], relax, 0.3 if relax == "trt" else ms.MAGIC_PAPER,
+                                 mode == "dilute", xi_ref)
+            np.testing.assert_allclose(got[c], want, rtol=1e-9, atol=1e-12, err_msg=f"N={N} c={c}")
+
+
+def test_relaxation_radius_closed_forms():
+    """Binary mixture: Lambda_1 = 2 (1 - 1/(1 + (a/2)/D)) is a scalar and Eq. (3-16)
+    gives lambda_2 = 8 (2 - lambda_1)/(8 - lambda_1); SRT: rho_2 = rho_1; equal
+    diffusivities (Remark II): B = I/D for every composition."""
+    for lattice, cs2 in (("D2Q5", 1 / 3), ("D3Q7", 1 / 4), ("D2Q4", 1 / 2)):
+        for d in (0.01, 0.1, 1.0, 10.0):
+            D = np.array([[1.0, d], [d, 1.0]])
+            r = relaxation_radius(lattice, D, [[0.3, 0.7], [1.0, 0.0]])
+            l1 = 2 * (1 - 1 / (1 + 0.5 * cs2 / d))
+            l2 = 8 * (2 - l1) / (8 - l1)
+            np.testing.assert_allclose(r, [[abs(1 - l1), abs(1 - l2)]] * 2, rtol=1e-12)
+            rs = relaxation_radius(lattice, D, [[0.3, 0.7]], relax="srt")
+            np.testing.assert_allclose(rs[0, 1], rs[0, 0], rtol=1e-12)
+    D = np.full((4, 4), 0.2)
+    r = relaxation_radius("D2Q5", D, np.random.default_rng(1).dirichlet(np.ones(4), size=5))
+    l1 = 2 * (1 - 1 / (1 + 0.5 / 3 / 0.2))
+    np.testing.assert_allclose(r[:, 0], abs(1 - l1), rtol=1e-9)
+
+
+# Eq. (3-16) applied entry by entry to a coupled Lambda_1 does not always damp
+# the even moments: this quaternary D3Q7 mixture (D_ij in [0.02, 0.8]) at a
+# nearly ternary composition has rho(I - Lambda_2) = 1.10.
+UNSTABLE_D = np.array([[1.0, 0.65890112, 0.57972844, 0.08045864],
+                       [0.65890112, 1.0, 0.52712183, 0.02641258],
+                       [0.57972844, 0.52712183, 1.0, 0.04631764],
+                       [0.08045864, 0.02641258, 0.04631764, 1.0]])
+UNSTABLE_XI = np.array([0.347198985, 0.169926415, 0.482843827, 0.0])
+UNSTABLE_XI[3] = 1.0 - UNSTABLE_XI[:3].sum()
+
+
+def test_unstable_composition_is_found_and_flagged_at_create():
+    r = relaxation_radius("D3Q7", UNSTABLE_D, [UNSTABLE_XI])[0]
+    want = _oracle_radii("D3Q7", UNSTABLE_D, UNSTABLE_XI, "paper", ms.MAGIC_PAPER, False, None)
+    np.testing.assert_allclose(r, want, rtol=1e-9)
+    assert r[1] > 1.05 and r[0] < 1.0
+    lib = F.lib()
+    # msd_create checks the Dirichlet face compositions (among others)
+    walls = {(0, 0): UNSTABLE_XI}
+    for face_walls, expect_unstable in ((walls, True), (None, None)):
+        bc = (("dirichlet", "zero_flux"), ("periodic", "periodic"), ("periodic", "periodic")) if face_walls else None
+        p, keep = make_problem("D3Q7", UNSTABLE_D, (8, 8, 8), "f32", bc=bc, xi_wall=face_walls)
+        st = C.c_int32(0)
+        n = lib.msd_workspace_bytes(C.byref(p), C.byref(st))
+        h = C.c_void_p()
+        assert lib.msd_create(C.byref(p), C.c_void_p(1 << 40), C.c_size_t(n), None, C.byref(h)) == 0
+        r1, r2 = C.c_double(), C.c_double()
+        assert lib.msd_stability(h, C.byref(r1), C.byref(r2)) == 0
+        if expect_unstable:
+            assert r2.value >= r[1] - 1e-12
+        # the pure species and the equimolar mixture are always checked
+        corners = np.vstack([np.eye(4), np.full((1, 4), 0.25)])
+        assert r2.value >= relaxation_radius("D3Q7", UNSTABLE_D, corners)[:, 1].max() - 1e-12
+        lib.msd_destroy(h)
+
+
+def test_health_limits_roundtrip_and_validation():
+    lib = F.lib()
+    D = _rand_D(np.random.default_rng(3), 3)
+    p, keep = make_problem("D2Q5", D, (16, 16), "f32")
+    st = C.c_int32(0)
+    n = lib.msd_workspace_bytes(C.byref(p), C.byref(st))
+    h = C.c_void_p()
+    assert lib.msd_create(C.byref(p), C.c_void_p(1 << 40), C.c_size_t(n), None, C.byref(h)) == 0
+    hl = F.MsdHealth()
+    assert lib.msd_get_health(h, C.byref(hl)) == 0
+    assert (hl.neg_tol, hl.mass_rtol) == (1e-2, 1e-4)
+    hl.neg_tol, hl.mass_rtol = -1.0, 3e-5
+    assert lib.msd_set_health(h, C.byref(hl)) == 0
+    back = F.MsdHealth()
+    assert lib.msd_get_health(h, C.byref(back)) == 0
+    assert (back.neg_tol, back.mass_rtol) == (-1.0, 3e-5)
+    hl.neg_tol = float("nan")
+    assert lib.msd_set_health(h, C.byref(hl)) == -1
+    assert lib.msd_set_health(None, C.byref(hl)) == -1
+    assert lib.msd_stability(None, None, None) == -1
+    lib.msd_destroy(h)
+    # invalid problems and arguments
+    bad, keep2 = make_problem("D2Q5", D, (16, 16), "f32")
+    bad.n_species = 1
+    out = (C.c_double * 2)()
+    xi = (C.c_double * 3)(0.2, 0.3, 0.5)
+    assert lib.msd_relaxation_radius(C.byref(bad), xi, 1, out) == -1
+    assert lib.msd_relaxation_radius(C.byref(p), None, 1, out) == -1
+    assert lib.msd_relaxation_radius(C.byref(p), xi, 0, None) == 0
