@@ -109,8 +109,16 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
   const bool tile_wall = WALLS && ((!px && (x0 - 1 <= 0 || x0 + TX >= nx - 1)) ||
                                    (!py && (y0 - 1 <= 0 || y0 + TY >= ny - 1)));
 
-  NodeConsts<M, T> nc;
-  load_consts<M, T>(cst, nc);
+  // Collision coefficients in registers; the Dirichlet face values are read
+  // from the constants block where a face rule needs them (rarely), which keeps
+  // registers free for the march.
+  CollideCoef<M, T> cc;
+  {
+    NodeConsts<M, T> nc;
+    load_consts<M, T>(cst, nc);
+    cc = nc.cc;
+  }
+  auto wall_at = [&](int face, int i) -> T { return cst->wall[face][i]; };
 
   // In-plane sources of this column (fixed for the whole march): the source
   // column of each in-plane direction (wrapped across periodic faces), and
@@ -194,7 +202,7 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
           fix = wall_dir[d] && p.bc[face] == BC_DIRICHLET;
         if (fix) {
 #pragma unroll
-          for (int i = 0; i < M; ++i) f[i][k] = T(2.0 * L::w(kb)) * nc.wall[face][i] - f[i][k];
+          for (int i = 0; i < M; ++i) f[i][k] = T(2.0 * L::w(kb)) * wall_at(face, i) - f[i][k];
         }
       }
     }
@@ -231,7 +239,7 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
     const bool pl_ok = col_ok && ((pl >= 0 && pl < nz) || pz);
     if (pl_ok) {
       dirichlet_fix(pl, f1);
-      collide_node<LAT, M, T>(f1, nc.cc);
+      collide_node<LAT, M, T>(f1, cc);
     }
     // the next plane's source values travel while this iteration computes
     if (j + 1 < nj) load_plane(pl + 1, ld);
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
 #pragma unroll
               for (int i = 0; i < M; ++i) {
                 const T own = s > 0 ? zm[B ^ 1][i] : zp[B ^ 1][i];   // plane qz's own opposite population
-                f2[i][k] = p.bc[face] == BC_ZERO_FLUX ? own : T(2.0 * L::w(kb)) * nc.wall[face][i] - own;
+                f2[i][k] = p.bc[face] == BC_ZERO_FLUX ? own : T(2.0 * L::w(kb)) * wall_at(face, i) - own;
               }
             }
           }
@@ -281,13 +289,13 @@ __global__ __launch_bounds__(blocked3d_max_threads(M)) void k_step_blocked3d(
 #pragma unroll
               for (int i = 0; i < M; ++i) {
                 const T own = lds_at(B ^ 1, db, i, n);
-                f2[i][k] = p.bc[face] == BC_ZERO_FLUX ? own : T(2.0 * L::w(kb)) * nc.wall[face][i] - own;
+                f2[i][k] = p.bc[face] == BC_ZERO_FLUX ? own : T(2.0 * L::w(kb)) * wall_at(face, i) - own;
               }
             }
           }
         }
       }
-      collide_node<LAT, M, T>(f2, nc.cc);
+      collide_node<LAT, M, T>(f2, cc);
       if (out_col) {
         const uint32_t off = ((uint32_t)qz * nxy + col) * (uint32_t)sizeof(T);
         uint64_t b = scalar_base(dst);

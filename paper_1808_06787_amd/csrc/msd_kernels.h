@@ -945,22 +945,35 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(Problem p, const 
 }
 
 // Templated on the lattice only so that each per-lattice unit owns its copy.
+// One workgroup of kDiagThreads threads: thread t combines the partials of
+// workgroups t, t + kDiagThreads, ... in that order, then a halving tree in
+// LDS combines the threads; the order is fixed, so the result is
+// deterministic.
 template <int LAT>
-__global__ void k_diag_final(const double* __restrict__ partials, int blocks, int N, double* __restrict__ out) {
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __restrict__ partials, int blocks, int N,
+                                                            double* __restrict__ out) {
+  __shared__ double red[kDiagThreads];
   const int W = 3 * N + 1;
-  const int e = threadIdx.x;
-  if (e >= W) return;
-  double v = partials[e];
-  for (int b = 1; b < blocks; ++b) {
-    const double u = partials[(int64_t)b * W + e];
-    if (e < N || e == 3 * N)
-      v += u;
-    else if (e < 2 * N)
-      v = fmin(v, u);
-    else
-      v = fmax(v, u);
+  const int t = (int)threadIdx.x;
+  for (int e = 0; e < W; ++e) {
+    const int kind = (e < N || e == 3 * N) ? 0 : (e < 2 * N ? 1 : 2);   // sum, min, max
+    double v = kind == 0 ? 0.0 : (kind == 1 ? __builtin_huge_val() : -__builtin_huge_val());
+    for (int b = t; b < blocks; b += kDiagThreads) {
+      const double u = partials[(int64_t)b * W + e];
+      v = kind == 0 ? v + u : (kind == 1 ? fmin(v, u) : fmax(v, u));
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int h = kDiagThreads / 2; h > 0; h >>= 1) {
+      if (t < h) {
+        const double u = red[t + h];
+        red[t] = kind == 0 ? red[t] + u : (kind == 1 ? fmin(red[t], u) : fmax(red[t], u));
+      }
+      __syncthreads();
+    }
+    if (t == 0) out[e] = red[0];
+    __syncthreads();
   }
-  out[e] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1722,8 +1735,8 @@ hipError_t run(Op op, const LaunchArgs& a) {
                          static_cast<const T*>(a.src), cst, a.pull, a.partials);
       break;
     case Op::DiagFinal:
-      hipLaunchKernelGGL(k_diag_final<LAT>, dim3(1), dim3(64), 0, a.stream, a.partials, a.diag_blocks, M + 1,
-                         a.diag_out);
+      hipLaunchKernelGGL(k_diag_final<LAT>, dim3(1), dim3(kDiagThreads), 0, a.stream, a.partials, a.diag_blocks,
+                         M + 1, a.diag_out);
       break;
     case Op::AdjointSeed: {
       const Tiling tl = make_tiling(a);
