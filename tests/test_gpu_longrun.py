@@ -7,9 +7,9 @@ many steps as the workloads run: 2000 steps of the 2D ternary field (on a
 steps of the 3D quaternary two-slab problem (on a 64^3 lattice, zero-flux x
 walls).  The expected values were written by tests/golden/make_longrun.py,
 which runs only the FP64 oracle on the inputs of ``workloads``; they are
-compared element by element at a fixed sample of nodes (4096 random nodes plus
-whole lines along every axis through the centre and two corners), and the
-whole-field species totals, minima and maxima are compared too."""
+compared element by element at a fixed sample of nodes (2048 random nodes plus
+whole lines along every axis through the centre and through the origin), and
+the whole-field species totals, minima and maxima are compared too."""
 import os
 
 import numpy as np

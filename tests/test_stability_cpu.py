@@ -137,3 +137,17 @@ def test_health_limits_roundtrip_and_validation():
     assert lib.msd_relaxation_radius(C.byref(bad), xi, 1, out) == -1
     assert lib.msd_relaxation_radius(C.byref(p), None, 1, out) == -1
     assert lib.msd_relaxation_radius(C.byref(p), xi, 0, None) == 0
+
+
+def test_workload_compositions_are_damped():
+    """The 512^3 quaternary workload's two slab compositions (and the pure species,
+    the equimolar mixture) and the 2D ternary workload's mean composition: every
+    relaxation radius below 1 for the workloads' diffusivities."""
+    import workloads
+
+    w3 = workloads.quaternary_3d(shape=(4, 4, 4))
+    slabs = [[0.50, 0.25, 0.15, 0.10], [0.10, 0.25, 0.15, 0.50]]
+    corners = np.vstack([slabs, np.eye(4), np.full((1, 4), 0.25)])
+    assert relaxation_radius("D3Q7", w3.D, corners).max() < 1.0
+    w2 = workloads.ternary_2d(shape=(8, 8))
+    assert relaxation_radius("D2Q5", w2.D, np.vstack([np.full((1, 3), 1 / 3), np.eye(3)])).max() < 1.0
