@@ -298,7 +298,7 @@ def batched_extra(steps: int = 1000, warmup: int = 5):
     byt = sum(w.nodes * (w.N - 1) * 2 * 5 * 4 for w in ws)
     del ws
     cache = os.path.join(tempfile.gettempdir(), "msd_autotune.json")
-    tune = autotune.tune_batch(b, cache_path=cache, steps=12, warmup=2)
+    tune = autotune.tune_batch(b, cache_path=cache, steps=30, warmup=2)
     state, t0 = b.save()
 
     def timed(fn):

@@ -333,9 +333,16 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
       s->n_cu = res[1];
     }
     if (adjoint) {
-      // about 1.35 rounds of the resident workgroups
+      // about 1.35 rounds of the resident workgroups; where that would take
+      // segments below 8 rows (small domains), about two workgroups per CU
+      // instead (1024^2 ternary FP32: 10-row segments 42.5 ms per 2000 adjoint
+      // steps, 8 rows 44.5 ms, 12 rows 47.7 ms, 16 rows 57.3 ms)
       const int64_t target = (int64_t)cached * 27 / 20;
-      const int64_t rows = (tiles_x * s->prob.ny + target - 1) / target;
+      int64_t rows = (tiles_x * s->prob.ny + target - 1) / target;
+      if (rows < 8) {
+        const int64_t two_per_cu = 2 * std::max(s->n_cu, 1);
+        rows = (tiles_x * s->prob.ny + two_per_cu - 1) / two_per_cu;
+      }
       seg = (int)std::max<int64_t>(8, std::min<int64_t>(rows, s->prob.ny));
     } else {
       // Forward sweep: about k * 2 workgroups per CU in all (at most what the

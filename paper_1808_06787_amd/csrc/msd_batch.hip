@@ -431,14 +431,21 @@ int step_direct(msd_batch* b, int64_t nsteps) {
       a.cur = cur;
       int64_t done = 1;
       hipError_t e;
-      if (r.tb >= 2 && t > 0 && nsteps - n >= r.tb) {
-        a.tb = r.tb;
+      const int64_t rest = nsteps - n;
+      if (r.tb >= 2 && t > 0 && rest >= 2) {
+        // full passes of tb steps, then one shorter pass for a remainder of at
+        // least two steps (so that a call runs the same passes whether or not
+        // its whole spans come from a graph).  A shorter pass reuses the tile
+        // table of tb-step passes: its tiles are at least as wide, so the table
+        // covers the mixture, and entries past its last segment store nothing.
+        const int len = (int)std::min<int64_t>(r.tb, rest);
+        a.tb = len;
         a.seg_rows = r.seg;
         a.walls = r.walls;
         a.tile_begin = r.bbegin;
         a.ntiles = r.bcount;
         e = dispatch(msd::Op::BatchStepBlocked, a);
-        done = r.tb;
+        done = len;
       } else {
         a.pull = t > 0 ? 1 : 0;
         a.tile_begin = r.begin;
@@ -757,7 +764,7 @@ int msd_batch_tune(msd_batch* b, const msd_schedule* candidates, int32_t count, 
           }
     if (b->lattice == MSD_D2Q5)
       for (int tb : {2, 3, 4, 5, 6})
-        for (int seg : {8, 16, 32, 64, 128})
+        for (int seg : {8, 12, 16, 24, 32, 48, 64, 128})
           for (int order : {MSD_ORDER_INSTANCE, MSD_ORDER_INTERLEAVED}) {
             msd_schedule c{};
             c.block_x = 64; c.block_y = 4; c.mode = MSD_BATCH_PER_CLASS; c.order = order;

@@ -1224,9 +1224,12 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   auto load_row = [&](int r) {
     const bool r_in = r >= 0 && r < ny;
     const int rl = r_in ? r : (((r % ny) + ny) % ny);
+    // planes walked from one scalar base in steps of the plane stride
+    uint64_t b = scalar_base(adj_in);
     if (col_ok && (r_in || py)) {
+      const uint32_t off = ((uint32_t)rl * (uint32_t)nx + (uint32_t)xl) * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int pl = 0; pl < P; ++pl) ld_row[pl] = at(adj_in, pl, rl, xl);
+      for (int pl = 0; pl < P; ++pl, b += pstride) ld_row[pl] = gload<T>(b, off, false);
     } else {
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) ld_row[pl] = T(0);
@@ -1290,20 +1293,24 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
         u[i][KYP] = nxt[lp][1][i];
         u[i][KYM] = yprev[lp][i];
       }
-      // f = f^{t-l} at this node: the pull of s_{t-l}
+      // f = f^{t-l} at this node: the pull of s_{t-l}, planes walked from one scalar base
       const int rl = (r >= 0 && r < ny) ? r : (((r % ny) + ny) % ny);
       const int rlm = rl > 0 ? rl - 1 : ny - 1, rlp = rl < ny - 1 ? rl + 1 : 0;
       const T* st = S.s[lp];
       T f[M][Q];
       if (col_ok) {
+        const uint32_t row = (uint32_t)rl * (uint32_t)nx, sz = (uint32_t)sizeof(T);
+        uint32_t off[Q];
+        off[0] = (row + (uint32_t)xl) * sz;
+        off[KXP] = (row + (uint32_t)xlm) * sz;
+        off[KXM] = (row + (uint32_t)xlp) * sz;
+        off[KYP] = ((uint32_t)rlm * (uint32_t)nx + (uint32_t)xl) * sz;
+        off[KYM] = ((uint32_t)rlp * (uint32_t)nx + (uint32_t)xl) * sz;
+        uint64_t b = scalar_base(st);
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-          f[i][0] = at(st, i * Q, rl, xl);
-          f[i][KXP] = at(st, i * Q + KXP, rl, xlm);
-          f[i][KXM] = at(st, i * Q + KXM, rl, xlp);
-          f[i][KYP] = at(st, i * Q + KYP, rlm, xl);
-          f[i][KYM] = at(st, i * Q + KYM, rlp, xl);
-        }
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int k = 0; k < Q; ++k, b += pstride) f[i][k] = gload<T>(b, off[k], false);
       } else {
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -1350,11 +1357,11 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
         enter(lvl, r, g);
       } else if (col_own && r >= y0 && r < y1) {
         const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+        uint64_t b = scalar_base(adj_out);
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-          for (int k = 0; k < Q; ++k)
-            gstore<T>(scalar_base(adj_out) + (uint64_t)(i * Q + k) * opaque_u64(pstride), off, g[i][k], 0);
+          for (int k = 0; k < Q; ++k, b += pstride) gstore<T>(b, off, g[i][k], 0);
       }
     }
   }
