@@ -781,12 +781,14 @@ __device__ __forceinline__ void pull_dir(const Problem& p, const Planes<T, A32>&
 //   phi(l) = 2 (2 - l) / (2 - g1 l)  (the product rule; g1 = 1 - 4 magic, g0 = 8 magic,
 //   so phi'(l) = -2 g0 / (2 - g1 l)^2; for magic = 3/16 phi(l) = 8 (l - 2)/(l - 8)),
 // with sigma, g1, g0 = rule[0], rule[5], rule[6] of the collision coefficients.
-// DIL = true differentiates the dilute-species collision (diagonal B).
-template <int LAT, int M, typename T, bool DIL = false>
+// DIL = true differentiates the dilute-species collision (diagonal B).  The
+// dL/dR terms of the node are added into Rbar in its own type RT (the callers
+// keep a per-thread sum in the sweep's precision and reduce it in FP64).
+template <int LAT, int M, typename T, bool DIL = false, typename RT>
 __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT>::Q], const T (&u)[M][Lattice<LAT>::Q],
                                                      const T (&R)[M][M + 1], const T (&xref)[M], bool linearized,
                                                      const CollideCoef<M, T>& cc, T (&fbar)[M][Lattice<LAT>::Q],
-                                                     double (&Rbar)[M][M + 1]) {
+                                                     RT (&Rbar)[M][M + 1]) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
   const T h = T(0.5 * L::cs2);
@@ -816,7 +818,7 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
     delta[i] = cc.rule[0] * (T(2) * (T(2) - l) * rd - l);
     dphi[i] = cc.rule[0] * (T(-2) * cc.rule[6] * rd * rd - T(1));   // d delta / d lambda
   }
-  T neq[M][Q], ev[M][Q];
+  T neq[M][Q];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     T s = T(0);
@@ -827,21 +829,23 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
     }
     neq[i][0] = -s;
   }
-#pragma unroll
-  for (int i = 0; i < M; ++i)
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const int kb = L::opp(k);
-      ev[i][k] = (k == kb) ? neq[i][k] : T(0.5) * (neq[i][k] + neq[i][kb]);
-    }
 
-  // g_ik = f_ik - sum_j L1_ij neq_jk - delta_i ev_ik
+  // g_ik = f_ik - sum_j L1_ij neq_jk - delta_i ev_ik, with the even part
+  // ev_ik = (neq_ik + neq_ikbar)/2 equal on the two directions of a pair
+  // (k != kbar) and ev_ik = neq_ik on a direction that is its own opposite:
+  // the pair terms of dL/ddelta and of dL/dneq are taken once per pair.
   T nbar[M][Q], L1bar[M][M], dbar[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     T d = T(0);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) d -= u[i][k] * ev[i][k];
+    for (int k = 0; k < Q; ++k) {
+      const int kb = L::opp(k);
+      if (k == kb)
+        d -= u[i][k] * neq[i][k];
+      else if (k < kb)
+        d -= (u[i][k] + u[i][kb]) * (T(0.5) * (neq[i][k] + neq[i][kb]));
+    }
     dbar[i] = d;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -860,18 +864,18 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
       for (int i = 0; i < M; ++i) acc -= L1[i][j] * u[i][k];
       nbar[j][k] = acc;
     }
-  // even part: ev_ik = (neq_ik + neq_ikbar)/2 (k != 0), ev_i0 = neq_i0; evbar = -delta u
+  // even part: dL/dev_ik = -delta_i u_ik, spread back over the pair
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const int kb = L::opp(k);
-      const T e_k = -delta[i] * u[i][k];
       if (k == kb) {
-        nbar[i][k] += e_k;
-      } else {
-        const T e_kb = -delta[i] * u[i][kb];
-        nbar[i][k] += T(0.5) * (e_k + e_kb);
+        nbar[i][k] -= delta[i] * u[i][k];
+      } else if (k < kb) {
+        const T e = T(-0.5) * delta[i] * (u[i][k] + u[i][kb]);
+        nbar[i][k] += e;
+        nbar[i][kb] += e;
       }
     }
 #pragma unroll
@@ -929,10 +933,10 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
       for (int j = 0; j < M; ++j) {
         if (j == i) continue;
         if (!linearized) xibar[j] += bb * (R[i][j] - R[i][M]);
-        Rbar[i][j] += (double)(bb * xb[j]);
+        Rbar[i][j] += RT(bb * xb[j]);
       }
       if (!linearized) xibar[i] -= bb * R[i][M];
-      Rbar[i][M] += (double)(bb * xN);
+      Rbar[i][M] += RT(bb * xN);
     }
 #pragma unroll
     for (int i = 0; i < M; ++i)
@@ -940,25 +944,24 @@ __device__ __forceinline__ void collide_node_adjoint(const T (&f)[M][Lattice<LAT
       for (int k = 0; k < Q; ++k) fbar[i][k] += xibar[i];
     return;
   }
-  // B_ij = -xb_i S_ij (i != j), B_ii = R_iN + sum_{k != i} xb_k S_ik,  S_ik = R_ik - R_iN
+  // B_ij = -xb_i S_ij (i != j), B_ii = R_iN + sum_{k != i} xb_k S_ik,  S_ik = R_ik - R_iN:
+  //   dL/dR_ij = Bbar_ii xb_j - Bbar_ij xb_i = c_ij (j != i),  dL/dR_iN = Bbar_ii - sum_{j != i} c_ij
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    double rN = 0.0;
+    T rN = Bbar[i][i];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       if (j == i) continue;
       const T S = R[i][j] - R[i][M];
-      // off-diagonal B_ij
-      if (!linearized) xibar[i] -= Bbar[i][j] * S;
-      Rbar[i][j] += (double)(-Bbar[i][j] * xb[i]);
-      rN += (double)(Bbar[i][j] * xb[i]);
-      // diagonal B_ii depends on xb_j through S_ij
-      if (!linearized) xibar[j] += Bbar[i][i] * S;
-      Rbar[i][j] += (double)(Bbar[i][i] * xb[j]);
-      rN -= (double)(Bbar[i][i] * xb[j]);
+      if (!linearized) {
+        xibar[i] -= Bbar[i][j] * S;            // off-diagonal B_ij
+        xibar[j] += Bbar[i][i] * S;            // diagonal B_ii depends on xb_j through S_ij
+      }
+      const T c = Bbar[i][i] * xb[j] - Bbar[i][j] * xb[i];
+      Rbar[i][j] += RT(c);
+      rN -= c;
     }
-    rN += (double)Bbar[i][i];
-    Rbar[i][M] += rN;
+    Rbar[i][M] += RT(rN);
   }
 #pragma unroll
   for (int i = 0; i < M; ++i)

@@ -1088,11 +1088,12 @@ __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __rest
   const uint32_t rest = tile / tl.tiles_x;
   const uint32_t ty = rest % tl.tiles_y;
   const uint32_t tz = rest / tl.tiles_y;
-  double Rbar[M][M + 1];
+  // this thread's dL/dR over its nodes in the sweep's precision, reduced in FP64 below
+  T Rbar[M][M + 1];
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
-    for (int j = 0; j <= M; ++j) Rbar[i][j] = 0.0;
+    for (int j = 0; j <= M; ++j) Rbar[i][j] = T(0);
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
   const Planes<T, A32> S{state_prev, p.plane}, A{adj_in, p.plane};
@@ -1135,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(Problem p, const T* __rest
   for (int i = 0; i < M; ++i)
 #pragma unroll
     for (int j = 0; j <= M; ++j) {
-      const double s = wave_sum(Rbar[i][j]);
+      const double s = wave_sum((double)Rbar[i][j]);
       if (lane == 0) red[wv][i * (M + 1) + j] = s;
     }
   __syncthreads();
@@ -1198,11 +1199,13 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   NodeConsts<M, T> nc;
   load_consts<M, T>(cst, nc);
   const bool lin = p.linearized != 0;
-  double Rbar[M][M + 1];
+  // this thread's dL/dR over a pass (at most TB (seg_rows + 2 TB) nodes) in the
+  // sweep's precision, reduced in FP64 below
+  T Rbar[M][M + 1];
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
-    for (int j = 0; j <= M; ++j) Rbar[i][j] = 0.0;
+    for (int j = 0; j <= M; ++j) Rbar[i][j] = T(0);
 
   // Per level (0 .. TB-1): -y of row r-1; rest/+y/-y of rows r (cur) and r+1 (nxt).
   T yprev[TB][M], cur[TB][3][M], nxt[TB][3][M];
@@ -1350,7 +1353,7 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
       if (r >= y0 && r < y1) {
         collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rbar);
       } else {
-        double Rhalo[M][M + 1] = {};
+        T Rhalo[M][M + 1] = {};
         collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rhalo);
       }
       if (lvl < TB) {
@@ -1371,7 +1374,7 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   for (int i = 0; i < M; ++i)
 #pragma unroll
     for (int j = 0; j <= M; ++j) {
-      const double v = wave_sum(col_own ? Rbar[i][j] : 0.0);
+      const double v = wave_sum(col_own ? (double)Rbar[i][j] : 0.0);
       if (lane == 0) red[wv][i * (M + 1) + j] = v;
     }
   __syncthreads();
