@@ -337,11 +337,11 @@ def batched_extra(steps: int = 1000, warmup: int = 5):
     }
 
 
-def adjoint_extra():
+def adjoint_extra(precisions=("f32", "f64"), fd_check=True):
     """Gradient workload: 1024^2 ternary D2Q5, 2000 steps, checkpoints every 100.
     Per precision: time of the plain forward run (default launch, and one step per
     pass), of the checkpointed forward run and of the backward pass (recompute +
-    adjoint).  FP64: the adjoint gradients against central
+    adjoint).  FP64 (with fd_check): the adjoint gradients against central
     differences (h = 1e-4) for the three D_ij pairs and one direction of the
     initial field."""
     import torch
@@ -375,7 +375,7 @@ def adjoint_extra():
         return a.elapsed_time(b) / 1e3, out
 
     res = {"extents": list(w.shape), "steps": w.steps, "checkpoint_every": every}
-    for prec in ("f32", "f64"):
+    for prec in precisions:
         s = Sim(w.lattice, w.D, w.shape, prec, bc=w.bc)
         s.init(torch.from_numpy(w.xi0))             # warm-up of every kernel used below
         ck = adjoint.forward_with_checkpoints(s, 5, 2)
@@ -400,7 +400,7 @@ def adjoint_extra():
                      "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3),
                      "forward_one_step_per_pass_s": round(t_plain1, 4),
                      "backward_over_forward_one_step_per_pass": round(t_bwd / t_plain1, 3)}
-        if prec == "f64":
+        if prec == "f64" and fd_check:
             h = 1e-4
 
             def loss(D, x0):
@@ -526,6 +526,9 @@ def main():
                     help="output tile per workgroup of the 3D blocked sweep (0 0: automatic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy kernel of this size first (calibrates HBM byte counters)")
+    ap.add_argument("--only", choices=("adjoint", "batch"), default=None,
+                    help="run only this extra (FP32 adjoint without the FD check, or the 256-mixture batch) "
+                         "and print its JSON record; for profiling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -537,6 +540,10 @@ def main():
 
     lib()   # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.only:
+        rec = adjoint_extra(precisions=("f32",), fd_check=False) if args.only == "adjoint" else batched_extra()
+        print(json.dumps({"extra": args.only, **rec}), flush=True)
+        return
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
