@@ -394,8 +394,9 @@ MSD_API int msd_tune(msd_sim* sim, const msd_launch* candidates, int32_t count, 
 
 /* Time steps the sweep advances per pass over HBM (one kernel launch) under the
  * current launch configuration: the temporally blocked count (2..6) or 1.  The
- * step from time 0 (from the state msd_init writes) runs alone, and a remainder
- * shorter than a pass runs as one shorter pass (a single step if it is one).  Negative status (MSD_EINVAL) for a NULL
+ * step from time 0 (from the state msd_init writes) runs alone; msd_step splits
+ * the rest of a call into passes of at most this many steps whose lengths differ
+ * by at most one (longer passes first).  Negative status (MSD_EINVAL) for a NULL
  * handle. */
 MSD_API int msd_steps_per_pass(const msd_sim* sim);
 
@@ -459,7 +460,10 @@ MSD_API int msd_batch_create(const msd_problem* problems, int32_t count, void* d
 MSD_API int msd_batch_init(msd_batch* batch, int32_t index, const void* d_xi0, int32_t xi0_precision);
 
 /* Advance every mixture by nsteps with the batch schedule (requires every
- * mixture initialised).  Asynchronous. */
+ * mixture initialised).  With blocked passes each class runs full passes of its
+ * steps per pass, then one shorter pass for a remainder of two or more steps (a
+ * single step for a remainder of one), the same passes whether or not whole
+ * spans are replayed from the graph.  Asynchronous. */
 MSD_API int msd_batch_step(msd_batch* batch, int64_t nsteps);
 
 /* Reference schedules, mixture after mixture on the batch's stream:
