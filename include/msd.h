@@ -333,20 +333,21 @@ typedef struct msd_launch {
                                power of two dividing nx); 0 (default) selects the general
                                one-node-per-thread kernel */
   int32_t temporal;         /* at most this many steps per pass over HBM; 0 or 1: one step
-                               per pass.  D2Q5: 2 .. 6 (temporally blocked sweep: each
-                               workgroup marches along y with the intermediate time levels
-                               of a few rows on chip).  The library takes the largest count up
+                               per pass.  D2Q5 and D2Q4: 2 .. 6 (temporally blocked sweep:
+                               each workgroup marches along y with the intermediate time
+                               levels of a few rows on chip; the blocked adjoint pass is
+                               D2Q5-only).  The library takes the largest count up
                                to this one whose on-chip window fits the species count and
                                precision (FP32: m <= 2 up to 6, m = 3 up to 5, m = 4 up to 3;
                                FP64: m = 1 up to 6, m = 2 up to 3; else one step per pass).
-                               FP32 problems with nx >= 6144 use 512-column tiles for full
-                               passes (m <= 2 at six steps; m = 3 at five steps when x and y
-                               are periodic), all other passes 256-column tiles.
+                               D2Q5 FP32 problems with nx >= 6144 use 512-column tiles for
+                               full passes (m <= 2 at six steps; m = 3 at five steps when x
+                               and y are periodic), all other passes 256-column tiles.
                                D3Q7 and D3Q6: 2 (two steps per pass: each workgroup marches
                                along z over an x-y tile and a ring of one node, the first
                                step's values kept on chip), for FP32 with m <= 3 and the full
                                Maxwell-Stefan collision; any value >= 2 means 2 there.
-                               Default 6 for D2Q5, 2 for D3Q7 and D3Q6, 0 otherwise; values
+                               Default 6 for D2Q5 and D2Q4, 2 for D3Q7 and D3Q6, 0 otherwise; values
                                outside 0 .. 6 are MSD_EINVAL */
   int32_t seg_rows;         /* D2Q5 blocked sweep: rows per workgroup; 0 (default):
                                automatic.  Forward: about k * 2 workgroups per CU in all,

@@ -233,8 +233,9 @@ void default_launch(const msd_problem* p, msd_launch* l) {
   l->lds_resident = 1;
   l->nontemporal = 0;
   l->vec = 0;
-  l->temporal = p->lattice == MSD_D2Q5 ? msd::kMaxStepsPerPass
-                                       : ((p->lattice == MSD_D3Q7 || p->lattice == MSD_D3Q6) ? msd::k3dStepsPerPass : 0);
+  l->temporal = (p->lattice == MSD_D2Q5 || p->lattice == MSD_D2Q4)
+                    ? msd::kMaxStepsPerPass
+                    : ((p->lattice == MSD_D3Q7 || p->lattice == MSD_D3Q6) ? msd::k3dStepsPerPass : 0);
   l->seg_rows = 0;
   l->tile_x = 0;
   l->tile_y = 0;
@@ -296,8 +297,10 @@ struct BlockedPlan {
 
 BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   BlockedPlan pl;
-  if (s->prob.lattice != MSD_D2Q5) return pl;
-  if (adjoint && s->prob.dilute) return pl;   // the blocked adjoint pass: B of Eq. (2-10) only
+  // the forward sweep on D2Q5 and D2Q4, the blocked adjoint pass on D2Q5 with B of Eq. (2-10)
+  const bool d2q5 = s->prob.lattice == MSD_D2Q5;
+  if (!d2q5 && !(s->prob.lattice == MSD_D2Q4 && !adjoint)) return pl;
+  if (adjoint && s->prob.dilute) return pl;
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)
@@ -308,7 +311,7 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
     }
   if (tb == 0) return pl;
   const bool xy_walls = s->prob.bc[0] != MSD_BC_PERIODIC || s->prob.bc[2] != MSD_BC_PERIODIC;
-  if (!adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
+  if (d2q5 && !adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
       (!xy_walls || msd::blocked_wide_walls_ok(s->m)) && s->prob.nx >= msd::kWideMinNx)
     pl.cols = msd::kBlockedColsWide;
   const int64_t W = pl.cols - 2 * tb;
@@ -1232,7 +1235,7 @@ int msd_tune(msd_sim* s, const msd_launch* candidates, int32_t count, int32_t st
             l.block_x = b[0]; l.block_y = b[1]; l.vec = vec; l.xcd_remap = xcd; l.nontemporal = nt; l.temporal = 0;
             cand.push_back(l);
           }
-    if (s->prob.lattice == MSD_D2Q5)
+    if (s->prob.lattice == MSD_D2Q5 || s->prob.lattice == MSD_D2Q4)
       for (int tb : {2, 3, 4, 5, 6})
         for (int seg : {0, 16, 32, 48})
           for (int nt : {0, 1}) {

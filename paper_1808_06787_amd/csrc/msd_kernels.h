@@ -411,7 +411,8 @@ __device__ __forceinline__ void bstore(uint64_t base, uint32_t bytes, uint32_t o
 }
 
 // ---------------------------------------------------------------------------
-// Temporally blocked D2Q5 sweep: TB time steps per pass over HBM.
+// Temporally blocked sweep on the axial 2D lattices (D2Q5; D2Q4, which has no
+// rest direction, the same way without it): TB time steps per pass over HBM.
 //
 // Workgroup (tile, segment) owns output columns [x0, x0 + W), W = C - 2 TB, and
 // output rows [y0, y1).  Thread c holds column x = x0 - TB + c (a halo of TB
@@ -453,16 +454,18 @@ __device__ __forceinline__ void for_each_iter(F&& f, std::integer_sequence<int, 
   (f(Iter<Js>{}), ...);
 }
 
-template <int M, typename T, int TB, int C, bool WALLS, bool DIL = false>
+template <int M, typename T, int TB, int C, bool WALLS, bool DIL = false, int LAT = 2>
 __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restrict__ src, T* __restrict__ dst,
                                              const Consts<T>* __restrict__ cst, int seg_rows, uint32_t tx,
                                              uint32_t seg, int nontemporal, int64_t rec_stride = 0) {
-  using L = Lattice<2>;
+  using L = Lattice<LAT>;
+  static_assert(LAT == 2 || LAT == 5, "the axial 2D lattices D2Q5 and D2Q4");
   constexpr int Q = L::Q, P = M * Q, W = C - 2 * TB;
-  // D2Q5 order: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y.
-  static_assert(L::axis(1) == 0 && L::sgn(1) > 0 && L::axis(3) == 0 && L::sgn(3) < 0, "x directions");
-  static_assert(L::axis(2) == 1 && L::sgn(2) > 0 && L::axis(4) == 1 && L::sgn(4) < 0, "y directions");
-  constexpr int KXP = 1, KYP = 2, KXM = 3, KYM = 4;
+  // D2Q5 order: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y; D2Q4 (no rest): 0 +x, 1 +y, 2 -x, 3 -y.
+  constexpr bool REST = LAT == 2;
+  constexpr int KXP = REST ? 1 : 0, KYP = KXP + 1, KXM = KXP + 2, KYM = KXP + 3;
+  static_assert(L::axis(KXP) == 0 && L::sgn(KXP) > 0 && L::axis(KXM) == 0 && L::sgn(KXM) < 0, "x directions");
+  static_assert(L::axis(KYP) == 1 && L::sgn(KYP) > 0 && L::axis(KYM) == 1 && L::sgn(KYM) < 0, "y directions");
   // x-direction populations of the two most recent rows of levels 1 .. TB-1:
   // [level - 1][slot][+x/-x][species][column].  Level 0 (the input rows)
   // takes its x-neighbours straight from memory instead.
@@ -560,7 +563,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      ring[0][J % 3][0][i] = ld[B][i * Q];
+      if constexpr (REST) ring[0][J % 3][0][i] = ld[B][i * Q];
       ring[0][J % 3][1][i] = ld[B][i * Q + KYP];
       ring[0][J % 3][2][i] = ld[B][i * Q + KYM];
       own[B][0][i] = ld[B][i * Q + KXP];
@@ -582,7 +585,7 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       T f[M][Q];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        f[i][0] = ring[lp][s0][0][i];
+        if constexpr (REST) f[i][0] = ring[lp][s0][0][i];
         f[i][KXP] = lp == 0 ? nb[B ^ 1][0][i] : xs[lp > 0 ? lp - 1 : 0][sx][0][i][cm];
         f[i][KXM] = lp == 0 ? nb[B ^ 1][1][i] : xs[lp > 0 ? lp - 1 : 0][sx][1][i][cp];
         f[i][KYP] = ring[lp][sm][1][i];
@@ -607,13 +610,13 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
           for (int i = 0; i < M; ++i) f[i][KYM] = face(3, KYP, i, ring[lp][s0][1][i]);
         }
       }
-      collide_node<2, M, T, DIL>(f, nc.cc);
+      collide_node<LAT, M, T, DIL>(f, nc.cc);
       if (lvl < TB) {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
           xs[lvl < TB ? lvl - 1 : 0][sx][0][i][c] = f[i][KXP];
           xs[lvl < TB ? lvl - 1 : 0][sx][1][i][c] = f[i][KXM];
-          ring[lvl < TB ? lvl : 0][sp][0][i] = f[i][0];
+          if constexpr (REST) ring[lvl < TB ? lvl : 0][sp][0][i] = f[i][0];
           ring[lvl < TB ? lvl : 0][sp][1][i] = f[i][KYP];
           ring[lvl < TB ? lvl : 0][sp][2][i] = f[i][KYM];
         }
@@ -660,24 +663,24 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
   }
 }
 
-template <int M, typename T, int TB, int C, bool WALLS>
+template <int M, typename T, int TB, int C, bool WALLS, int LAT = 2>
 __global__ __launch_bounds__(C) void k_step_blocked(Problem p, const T* __restrict__ src, T* __restrict__ dst,
                                                     const Consts<T>* __restrict__ cst, int seg_rows,
                                                     uint32_t tiles_x, int nontemporal, int64_t rec_stride) {
-  blocked_tile<M, T, TB, C, WALLS>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
-                                   nontemporal, rec_stride);
+  blocked_tile<M, T, TB, C, WALLS, false, LAT>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x,
+                                               blockIdx.x / tiles_x, nontemporal, rec_stride);
 }
 
 // The same sweep with the dilute-species collision (diagonal A).  Its register
 // needs differ from the full model's, so it asks the compiler for the two
 // waves per SIMD the host plan assumes.
-template <int M, typename T, int TB, int C, bool WALLS>
+template <int M, typename T, int TB, int C, bool WALLS, int LAT = 2>
 __global__ __launch_bounds__(C, 2) void k_step_blocked_dilute(Problem p, const T* __restrict__ src,
                                                               T* __restrict__ dst, const Consts<T>* __restrict__ cst,
                                                               int seg_rows, uint32_t tiles_x, int nontemporal,
                                                               int64_t rec_stride) {
-  blocked_tile<M, T, TB, C, WALLS, true>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x, blockIdx.x / tiles_x,
-                                         nontemporal, rec_stride);
+  blocked_tile<M, T, TB, C, WALLS, true, LAT>(p, src, dst, cst, seg_rows, blockIdx.x % tiles_x,
+                                              blockIdx.x / tiles_x, nontemporal, rec_stride);
 }
 
 // The blocked sweep over the mixtures of one batch class (equal m): workgroup
@@ -1495,13 +1498,15 @@ size_t blocked_lds_pad(const LaunchArgs& a) {
 // Workgroups of a blocked kernel (sweep or adjoint) that the whole device holds
 // at once: resident workgroups per CU (registers and LDS, with the sweep's
 // reservation) times the CU count; out[1] is the CU count.
-template <int M, typename T, int TB>
+template <int M, typename T, int TB, int LAT = 2>
 hipError_t blocked_resident(const LaunchArgs& a, int* out) {
   out[0] = out[1] = 0;
   constexpr int C = blocked_cols(M, TB, (int)sizeof(T)), CA = adjoint_blocked_cols(M, TB, (int)sizeof(T));
   const bool walls = a.p.bc[0] != BC_PERIODIC || a.p.bc[2] != BC_PERIODIC;
   int per_cu = 0;
   hipError_t e = hipSuccess;
+  // D2Q4 has the forward sweep in 256-column tiles only (no wide tiles, no blocked adjoint)
+  if (LAT != 2 && (a.adjoint || a.cols == kBlockedColsWide)) return hipErrorInvalidValue;
   if (a.adjoint) {
     if constexpr (CA > 0) {
       e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint_blocked<M, T, TB, CA, true>, CA, 0)
@@ -1525,8 +1530,9 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
   } else {
     if constexpr (C > 0) {
       const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
-      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true>, C, pad)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false>, C, pad);
+      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true, LAT>, C, pad)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false, LAT>, C,
+                                                               pad);
     }
   }
   if (e != hipSuccess) return e;
@@ -1577,10 +1583,15 @@ hipError_t launch_blocked_wide(const LaunchArgs& a) {
   }
 }
 
-template <int M, typename T, int TB>
+template <int M, typename T, int TB, int LAT = 2>
 hipError_t launch_blocked_tb(const LaunchArgs& a) {
   constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
-  if (a.cols == kBlockedColsWide) return launch_blocked_wide<M, T, TB>(a);
+  if (a.cols == kBlockedColsWide) {
+    if constexpr (LAT == 2)
+      return launch_blocked_wide<M, T, TB>(a);
+    else
+      return hipErrorInvalidValue;
+  }
   if constexpr (C == 0) {
     return hipErrorInvalidValue;
   } else {
@@ -1595,18 +1606,18 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     const dim3 grid(tiles_x * segs);
     if (a.p.dilute) {
       if (walls)
-        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.p, src, dst,
-                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, true, LAT>), grid, dim3(C), pad, a.stream, a.p, src,
+                           dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
       else
-        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.p, src, dst,
-                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src,
+                           dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     } else {
       if (walls)
-        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
+        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true, LAT>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
                            a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
       else
-        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
-                           a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src, dst,
+                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     }
     return hipSuccess;
   }
@@ -1650,13 +1661,13 @@ hipError_t launch_batch_blocked(const LaunchArgs& a) {
   return hipErrorInvalidValue;
 }
 
-template <int M, typename T>
+template <int M, typename T, int LAT = 2>
 hipError_t launch_blocked(const LaunchArgs& a) {
-  if (a.tb == 2) return launch_blocked_tb<M, T, 2>(a);
-  if (a.tb == 3) return launch_blocked_tb<M, T, 3>(a);
-  if (a.tb == 4) return launch_blocked_tb<M, T, 4>(a);
-  if (a.tb == 5) return launch_blocked_tb<M, T, 5>(a);
-  if (a.tb == 6) return launch_blocked_tb<M, T, 6>(a);
+  if (a.tb == 2) return launch_blocked_tb<M, T, 2, LAT>(a);
+  if (a.tb == 3) return launch_blocked_tb<M, T, 3, LAT>(a);
+  if (a.tb == 4) return launch_blocked_tb<M, T, 4, LAT>(a);
+  if (a.tb == 5) return launch_blocked_tb<M, T, 5, LAT>(a);
+  if (a.tb == 6) return launch_blocked_tb<M, T, 6, LAT>(a);
   return hipErrorInvalidValue;
 }
 
@@ -1795,21 +1806,21 @@ hipError_t run(Op op, const LaunchArgs& a) {
       hipLaunchKernelGGL(k_fill_zero<LAT>, dim3(256), dim3(256), 0, a.stream, a.partials, a.fill_count);
       break;
     case Op::StepBlocked:
-      if constexpr (LAT == 2) {
-        const hipError_t e = launch_blocked<M, T>(a);
+      if constexpr (LAT == 2 || LAT == 5) {
+        const hipError_t e = launch_blocked<M, T, LAT>(a);
         if (e != hipSuccess) return e;
       } else {
         return hipErrorInvalidValue;
       }
       break;
     case Op::BlockedResident:
-      if constexpr (LAT == 2) {
+      if constexpr (LAT == 2 || LAT == 5) {
         hipError_t e = hipErrorInvalidValue;
-        if (a.tb == 2) e = blocked_resident<M, T, 2>(a, a.out_int);
-        if (a.tb == 3) e = blocked_resident<M, T, 3>(a, a.out_int);
-        if (a.tb == 4) e = blocked_resident<M, T, 4>(a, a.out_int);
-        if (a.tb == 5) e = blocked_resident<M, T, 5>(a, a.out_int);
-        if (a.tb == 6) e = blocked_resident<M, T, 6>(a, a.out_int);
+        if (a.tb == 2) e = blocked_resident<M, T, 2, LAT>(a, a.out_int);
+        if (a.tb == 3) e = blocked_resident<M, T, 3, LAT>(a, a.out_int);
+        if (a.tb == 4) e = blocked_resident<M, T, 4, LAT>(a, a.out_int);
+        if (a.tb == 5) e = blocked_resident<M, T, 5, LAT>(a, a.out_int);
+        if (a.tb == 6) e = blocked_resident<M, T, 6, LAT>(a, a.out_int);
         return e;
       } else {
         return hipErrorInvalidValue;

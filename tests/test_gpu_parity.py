@@ -569,3 +569,37 @@ def test_temporally_blocked_sweep_3d_default_tile(xcd_remap):
     gpu = gpu_run("D3Q7", D, shape, "f32", xi0, steps, bc=bc,
                   launch=dict(temporal=2, seg_rows=8, xcd_remap=xcd_remap, lds_resident=0))
     assert_parity(gpu, orc, "f32", f"blocked 3D default tile remap={xcd_remap}")
+
+
+@pytest.mark.parametrize("case", range(len(BLOCKED_CASES)))
+@pytest.mark.parametrize("tb", [2, 3, 5, 6])
+@pytest.mark.parametrize("N", [2, 3, 5])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_temporally_blocked_sweep_d2q4(case, tb, N, precision):
+    """The blocked sweep on D2Q4 (Eq. (3-6), no rest direction): the D2Q5 row march
+    without the rest population, on the same ragged tiles and segments, every face
+    kind and the pre-collision first step; steps per pass as the plan gives them."""
+    from paper_1808_06787_amd.sim import Sim
+
+    shape, bc = BLOCKED_CASES[case]
+    rng = np.random.default_rng(1800 + 10 * case + N)
+    D = rand_D(rng, N)
+    walls = {}
+    for a, (lo, hi) in enumerate(bc):
+        for s, kind in enumerate((lo, hi)):
+            if kind == "dirichlet":
+                walls[(a, s)] = rand_field(rng, N, ())
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 23
+    orc = oracle_run(oracle_problem("D2Q4", D, shape, bc=bc, xi_wall=walls), xi0, steps)
+    # FP32: m <= 2 up to six steps, m = 4 up to three; FP64: m = 1 up to six, m = 2 up to three, m = 4 one
+    want = {2: min(tb, 6), 3: min(tb, 6), 5: min(tb, 3)}[N] if precision == "f32" else \
+        {2: min(tb, 6), 3: min(tb, 3), 5: 1}[N]
+    for seg in (5, 32):
+        launch = dict(temporal=tb, seg_rows=seg, lds_resident=0)
+        probe = Sim("D2Q4", D, shape, precision, bc=bc, xi_wall=walls)
+        probe.set_launch(**launch)
+        assert probe.steps_per_pass() == want, (N, precision, tb)
+        probe.close()
+        gpu = gpu_run("D2Q4", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, launch=launch, split=[1, 6, 16])
+        assert_parity(gpu, orc, precision, f"D2Q4 blocked tb={tb} seg={seg} {shape} N={N} {precision}")
