@@ -642,6 +642,16 @@ __device__ __forceinline__ void blocked_tile(const Problem& p, const T* __restri
       }
     }
   };
+  // The tile needs its output columns and TB halo columns on either side.  In the
+  // last tile of a row (nx not a multiple of W) whole waves can lie beyond them:
+  // such a wave (uniform flag) only takes part in the march's barriers, one per
+  // row.  What the live lanes then read of its LDS columns reaches halo lanes
+  // only, as at the tile's right edge.
+  const bool live = __builtin_amdgcn_readfirstlane((c & ~63) < min(W, nx - x0) + 2 * TB ? 1 : 0) != 0;
+  if (!live) {
+    for (int j = 0; j < max(y1 - y0, 0) + 2 * TB; ++j) __syncthreads();
+    return;
+  }
   load_row(y0 - TB, ld[0], ldn[0]);
   for_each_iter([&](auto jc) __attribute__((always_inline)) {
     iteration(y0 - TB + decltype(jc)::value, jc, std::false_type{});
@@ -1267,107 +1277,115 @@ __global__ __launch_bounds__(C) void k_adjoint_blocked(Problem p, AdjStates<T> S
   };
 
   const int r_last = y1 - 1 + TB;
+  // waves wholly beyond the tile's output and halo columns (the last tile of a
+  // row) take part in the barriers only and add nothing to dL/dR, as in the
+  // forward row march
+  const bool live = __builtin_amdgcn_readfirstlane((c & ~63) < min(W, nx - x0) + 2 * TB ? 1 : 0) != 0;
   int r_in = y0 - TB;
-  load_row(r_in);
-  for (; r_in <= r_last; ++r_in) {
-    __syncthreads();
-    {
-      T g[M][Q];
-#pragma unroll
-      for (int i = 0; i < M; ++i)
-#pragma unroll
-        for (int k = 0; k < Q; ++k) g[i][k] = ld_row[i * Q + k];
-      advance(0);
-      enter(0, r_in, g);
-    }
-    if (r_in < r_last) load_row(r_in + 1);
-#pragma unroll
-    for (int lvl = 1; lvl <= TB; ++lvl) {
-      const int r = r_in - lvl;
-      const int lp = lvl - 1;
-      const int s = r & 1;
-      const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
-      if (lvl < TB) advance(lvl);
-      if (!row_ok) continue;
-      // u = dL/dg at this node: the transposed pull of a_{t-l+1}
-      T u[M][Q];
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        u[i][0] = cur[lp][0][i];
-        u[i][KXP] = xs[lp][s][0][i][cp];
-        u[i][KXM] = xs[lp][s][1][i][cm];
-        u[i][KYP] = nxt[lp][1][i];
-        u[i][KYM] = yprev[lp][i];
-      }
-      // f = f^{t-l} at this node: the pull of s_{t-l}, planes walked from one scalar base
-      const int rl = (r >= 0 && r < ny) ? r : (((r % ny) + ny) % ny);
-      const int rlm = rl > 0 ? rl - 1 : ny - 1, rlp = rl < ny - 1 ? rl + 1 : 0;
-      const T* st = S.s[lp];
-      T f[M][Q];
-      if (col_ok) {
-        const uint32_t row = (uint32_t)rl * (uint32_t)nx, sz = (uint32_t)sizeof(T);
-        uint32_t off[Q];
-        off[0] = (row + (uint32_t)xl) * sz;
-        off[KXP] = (row + (uint32_t)xlm) * sz;
-        off[KXM] = (row + (uint32_t)xlp) * sz;
-        off[KYP] = ((uint32_t)rlm * (uint32_t)nx + (uint32_t)xl) * sz;
-        off[KYM] = ((uint32_t)rlp * (uint32_t)nx + (uint32_t)xl) * sz;
-        uint64_t b = scalar_base(st);
+  if (!live) {
+    for (; r_in <= r_last; ++r_in) __syncthreads();
+  } else {
+    load_row(r_in);
+    for (; r_in <= r_last; ++r_in) {
+      __syncthreads();
+      {
+        T g[M][Q];
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-          for (int k = 0; k < Q; ++k, b += pstride) f[i][k] = gload<T>(b, off[k], false);
-      } else {
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-          for (int k = 0; k < Q; ++k) f[i][k] = T(0);
+          for (int k = 0; k < Q; ++k) g[i][k] = ld_row[i * Q + k];
+        advance(0);
+        enter(0, r_in, g);
       }
-      if constexpr (WALLS) {
-        if (tile_xwall) {
+      if (r_in < r_last) load_row(r_in + 1);
 #pragma unroll
-          for (int i = 0; i < M; ++i) {
-            if (wall_xlo) {
-              f[i][KXP] = face(0, KXM, i, at(st, i * Q + KXM, rl, xl));
-              u[i][KXM] = tface(0, xs[lp][s][0][i][c]);
+      for (int lvl = 1; lvl <= TB; ++lvl) {
+        const int r = r_in - lvl;
+        const int lp = lvl - 1;
+        const int s = r & 1;
+        const bool row_ok = r >= y0 - TB + lvl && r <= r_last - lvl && (py || (r >= 0 && r < ny));
+        if (lvl < TB) advance(lvl);
+        if (!row_ok) continue;
+        // u = dL/dg at this node: the transposed pull of a_{t-l+1}
+        T u[M][Q];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          u[i][0] = cur[lp][0][i];
+          u[i][KXP] = xs[lp][s][0][i][cp];
+          u[i][KXM] = xs[lp][s][1][i][cm];
+          u[i][KYP] = nxt[lp][1][i];
+          u[i][KYM] = yprev[lp][i];
+        }
+        // f = f^{t-l} at this node: the pull of s_{t-l}, planes walked from one scalar base
+        const int rl = (r >= 0 && r < ny) ? r : (((r % ny) + ny) % ny);
+        const int rlm = rl > 0 ? rl - 1 : ny - 1, rlp = rl < ny - 1 ? rl + 1 : 0;
+        const T* st = S.s[lp];
+        T f[M][Q];
+        if (col_ok) {
+          const uint32_t row = (uint32_t)rl * (uint32_t)nx, sz = (uint32_t)sizeof(T);
+          uint32_t off[Q];
+          off[0] = (row + (uint32_t)xl) * sz;
+          off[KXP] = (row + (uint32_t)xlm) * sz;
+          off[KXM] = (row + (uint32_t)xlp) * sz;
+          off[KYP] = ((uint32_t)rlm * (uint32_t)nx + (uint32_t)xl) * sz;
+          off[KYM] = ((uint32_t)rlp * (uint32_t)nx + (uint32_t)xl) * sz;
+          uint64_t b = scalar_base(st);
+#pragma unroll
+          for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = 0; k < Q; ++k, b += pstride) f[i][k] = gload<T>(b, off[k], false);
+        } else {
+#pragma unroll
+          for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = 0; k < Q; ++k) f[i][k] = T(0);
+        }
+        if constexpr (WALLS) {
+          if (tile_xwall) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+              if (wall_xlo) {
+                f[i][KXP] = face(0, KXM, i, at(st, i * Q + KXM, rl, xl));
+                u[i][KXM] = tface(0, xs[lp][s][0][i][c]);
+              }
+              if (wall_xhi) {
+                f[i][KXM] = face(1, KXP, i, at(st, i * Q + KXP, rl, xl));
+                u[i][KXP] = tface(1, xs[lp][s][1][i][c]);
+              }
             }
-            if (wall_xhi) {
-              f[i][KXM] = face(1, KXP, i, at(st, i * Q + KXP, rl, xl));
-              u[i][KXP] = tface(1, xs[lp][s][1][i][c]);
+          }
+          if (!py && r == 0) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+              f[i][KYP] = face(2, KYM, i, at(st, i * Q + KYM, rl, xl));
+              u[i][KYM] = tface(2, cur[lp][1][i]);
+            }
+          }
+          if (!py && r == ny - 1) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+              f[i][KYM] = face(3, KYP, i, at(st, i * Q + KYP, rl, xl));
+              u[i][KYP] = tface(3, cur[lp][2][i]);
             }
           }
         }
-        if (!py && r == 0) {
-#pragma unroll
-          for (int i = 0; i < M; ++i) {
-            f[i][KYP] = face(2, KYM, i, at(st, i * Q + KYM, rl, xl));
-            u[i][KYM] = tface(2, cur[lp][1][i]);
-          }
+        T g[M][Q];
+        if (r >= y0 && r < y1) {
+          collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rbar);
+        } else {
+          T Rhalo[M][M + 1] = {};
+          collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rhalo);
         }
-        if (!py && r == ny - 1) {
+        if (lvl < TB) {
+          enter(lvl, r, g);
+        } else if (col_own && r >= y0 && r < y1) {
+          const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
+          uint64_t b = scalar_base(adj_out);
 #pragma unroll
-          for (int i = 0; i < M; ++i) {
-            f[i][KYM] = face(3, KYP, i, at(st, i * Q + KYP, rl, xl));
-            u[i][KYP] = tface(3, cur[lp][2][i]);
-          }
+          for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = 0; k < Q; ++k, b += pstride) gstore<T>(b, off, g[i][k], 0);
         }
-      }
-      T g[M][Q];
-      if (r >= y0 && r < y1) {
-        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rbar);
-      } else {
-        T Rhalo[M][M + 1] = {};
-        collide_node_adjoint<2, M, T>(f, u, nc.R, nc.xref, lin, nc.cc, g, Rhalo);
-      }
-      if (lvl < TB) {
-        enter(lvl, r, g);
-      } else if (col_own && r >= y0 && r < y1) {
-        const uint32_t off = ((uint32_t)r * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(T);
-        uint64_t b = scalar_base(adj_out);
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-          for (int k = 0; k < Q; ++k, b += pstride) gstore<T>(b, off, g[i][k], 0);
       }
     }
   }
