@@ -228,6 +228,33 @@ def test_blocked_adjoint_fp32_ternary(case, tb):
     _compare(ref, got, 2e-4, f"fp32 blocked tb={tb} case {case}")
 
 
+# Widths at which the last column tile of the blocked adjoint pass needs exactly 64 or 65 lanes
+# (output columns and TB halo columns on either side), with one tile and with two.
+LAST_TILE_WIDTHS = {2: (60, 61, 312, 313), 3: (58, 59, 308, 309)}
+
+
+@pytest.mark.parametrize("tb", [2, 3])
+@pytest.mark.parametrize("k", range(4))
+@pytest.mark.parametrize("xbc", [("periodic", "periodic"), ("dirichlet", "zero_flux")])
+def test_blocked_adjoint_last_tile_wave_boundary(tb, k, xbc):
+    """Blocked adjoint passes and recording where the last tile's live lanes end exactly at a
+    wave boundary or one lane past it; FP64 binary against the oracle's autograd twin."""
+    N = 2
+    shape = (LAST_TILE_WIDTHS[tb][k], 9)
+    rng = np.random.default_rng(2300 + 10 * tb + k)
+    D = rand_D(rng, N)
+    bc = (xbc, ("periodic", "periodic"))
+    walls = {(0, 0): rand_field(rng, N, ())} if xbc[0] == "dirichlet" else {}
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    target = smooth_field(rng, N, shape[::-1], 0.1)
+    steps, every = 2 * tb + 3, tb + 2
+    p = oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls)
+    ref = twin.misfit_gradients(p, xi0, target, steps)
+    got = _gpu_grads("D2Q5", D, shape, "f64", xi0, target, steps, every,
+                     launch=dict(temporal=tb, seg_rows=4), bc=bc, xi_wall=walls)
+    _compare(ref, got, 1e-10, f"last tile tb={tb} {shape} {xbc}")
+
+
 DILUTE_CASES = [
     ("D2Q5", (13, 9), (("dirichlet", "zero_flux"), ("periodic", "periodic")), None),
     ("D1Q3", (23,), (("zero_flux", "dirichlet"),), None),

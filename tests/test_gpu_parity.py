@@ -603,3 +603,36 @@ def test_temporally_blocked_sweep_d2q4(case, tb, N, precision):
         probe.close()
         gpu = gpu_run("D2Q4", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, launch=launch, split=[1, 6, 16])
         assert_parity(gpu, orc, precision, f"D2Q4 blocked tb={tb} seg={seg} {shape} N={N} {precision}")
+
+
+# Widths at which the last tile of a row needs exactly 64 or 65 lanes (its output columns and TB
+# halo columns on either side), with one column tile and with two: the boundary between the waves
+# that run the row march and the waves past it, which only join the march's barriers.
+LAST_TILE_WIDTHS = {6: (52, 53, 296, 297), 3: (58, 59, 308, 309)}
+
+
+@pytest.mark.parametrize("tb", [3, 6])
+@pytest.mark.parametrize("k", range(4))
+@pytest.mark.parametrize("xbc", [("periodic", "periodic"), ("zero_flux", "dirichlet")])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_blocked_sweep_last_tile_wave_boundary(tb, k, xbc, precision):
+    """The blocked sweep where the last tile's live lanes end exactly at a wave boundary or one
+    lane past it, periodic and walled in x (the wall at the last column lies in that tile)."""
+    from paper_1808_06787_amd.sim import Sim
+
+    shape = (LAST_TILE_WIDTHS[tb][k], 14)
+    N = 3 if precision == "f32" else 2          # six steps per pass: FP32 m <= 2, FP64 m = 1
+    bc = (xbc, ("periodic", "periodic"))
+    rng = np.random.default_rng(2200 + 10 * tb + k)
+    D = rand_D(rng, N)
+    walls = {(0, 1): rand_field(rng, N, ())} if xbc[1] == "dirichlet" else {}
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    steps = 2 * tb + 2
+    orc = oracle_run(oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls), xi0, steps)
+    launch = dict(temporal=tb, seg_rows=5, lds_resident=0)
+    probe = Sim("D2Q5", D, shape, precision, bc=bc, xi_wall=walls)
+    probe.set_launch(**launch)
+    assert probe.steps_per_pass() == tb, (shape, tb, precision)
+    probe.close()
+    gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, launch=launch)
+    assert_parity(gpu, orc, precision, f"last tile tb={tb} {shape} {xbc} {precision}")
