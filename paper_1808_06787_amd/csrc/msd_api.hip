@@ -302,15 +302,16 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
   if (!d2q5 && !(s->prob.lattice == MSD_D2Q4 && !adjoint)) return pl;
   if (adjoint && s->prob.dilute) return pl;
   if ((uint64_t)s->kp.plane * (uint64_t)s->prob.precision >= (1ull << 32)) return pl;
+  const bool xy_walls = s->prob.bc[0] != MSD_BC_PERIODIC || s->prob.bc[2] != MSD_BC_PERIODIC;
   int tb = 0;
   for (int t = s->launch.temporal; t >= 2; --t)
-    if ((adjoint ? msd::adjoint_blocked_cols(s->m, t, s->prob.precision)
-                 : msd::blocked_cols(s->m, t, s->prob.precision)) > 0) {
+    if (adjoint ? msd::adjoint_blocked_cols(s->m, t, s->prob.precision) > 0
+                : msd::blocked_cols(s->m, t, s->prob.precision) > 0 &&
+                      (!xy_walls || msd::blocked_walls_ok(s->m, t, s->prob.precision))) {
       tb = t;
       break;
     }
   if (tb == 0) return pl;
-  const bool xy_walls = s->prob.bc[0] != MSD_BC_PERIODIC || s->prob.bc[2] != MSD_BC_PERIODIC;
   if (d2q5 && !adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
       (!xy_walls || msd::blocked_wide_walls_ok(s->m)) && s->prob.nx >= msd::kWideMinNx)
     pl.cols = msd::kBlockedColsWide;

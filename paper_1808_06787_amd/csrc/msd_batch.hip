@@ -144,7 +144,7 @@ int class_steps_per_pass(const msd_batch* b, const std::vector<int>& g, int m) {
   for (int i : g)
     if ((uint64_t)b->mem[i].plane * (uint64_t)b->prec >= (1ull << 32)) return 0;
   for (int t = b->sched.temporal; t >= 2; --t)
-    if (msd::blocked_cols(m, t, b->prec) > 0) return t;
+    if (msd::blocked_cols(m, t, b->prec) > 0 && msd::blocked_walls_ok(m, t, b->prec)) return t;
   return 0;
 }
 

@@ -1548,9 +1548,14 @@ hipError_t blocked_resident(const LaunchArgs& a, int* out) {
   } else {
     if constexpr (C > 0) {
       const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
-      e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true, LAT>, C, pad)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false, LAT>, C,
-                                                               pad);
+      if (walls) {
+        if constexpr (blocked_walls_ok(M, TB, (int)sizeof(T)))
+          e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, true, LAT>, C, pad);
+        else
+          return hipErrorInvalidValue;
+      } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_blocked<M, T, TB, C, false, LAT>, C, pad);
+      }
     }
   }
   if (e != hipSuccess) return e;
@@ -1622,20 +1627,23 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
     const Consts<T>* cst = static_cast<const Consts<T>*>(a.consts);
     const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
     const dim3 grid(tiles_x * segs);
-    if (a.p.dilute) {
-      if (walls)
+    if (walls) {
+      // walled instantiations only up to their own (smaller) window
+      if constexpr (!blocked_walls_ok(M, TB, (int)sizeof(T))) {
+        return hipErrorInvalidValue;
+      } else if (a.p.dilute) {
         hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, true, LAT>), grid, dim3(C), pad, a.stream, a.p, src,
                            dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
-      else
-        hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src,
-                           dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
-    } else {
-      if (walls)
+      } else {
         hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, true, LAT>), grid, dim3(C), pad, a.stream, a.p, src, dst, cst,
                            a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
-      else
-        hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src, dst,
-                           cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+      }
+    } else if (a.p.dilute) {
+      hipLaunchKernelGGL((k_step_blocked_dilute<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src,
+                         dst, cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
+    } else {
+      hipLaunchKernelGGL((k_step_blocked<M, T, TB, C, false, LAT>), grid, dim3(C), pad, a.stream, a.p, src, dst,
+                         cst, a.seg_rows, tiles_x, a.nontemporal, a.rec_stride);
     }
     return hipSuccess;
   }
@@ -1643,7 +1651,8 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
 
 template <int M, typename T, int TB>
 hipError_t launch_batch_blocked_tb(const LaunchArgs& a) {
-  constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
+  // the batched kernels hold more registers: the walled window at any faces
+  constexpr int C = blocked_walls_ok(M, TB, (int)sizeof(T)) ? blocked_cols(M, TB, (int)sizeof(T)) : 0;
   if constexpr (C == 0) {
     return hipErrorInvalidValue;
   } else {

@@ -489,7 +489,8 @@ def test_steps_per_pass_plan():
         (3, "f32", (4096, 4096), dict(temporal=4, seg_rows=0), 4),
         (2, "f64", (2048, 512), {}, 6),
         (4, "f32", (2048, 1024), {}, 5),
-        (5, "f32", (2048, 1024), {}, 3),
+        (5, "f32", (2048, 1024), {}, 4),
+        (5, "f32", (2048, 1024), dict(bc=(("zero_flux", "zero_flux"), ("periodic", "periodic"))), 3),
         (3, "f64", (2048, 1024), {}, 3),
         (4, "f64", (2048, 1024), {}, 1),
         (3, "f32", (2048, 1024), dict(temporal=3), 3),
@@ -500,7 +501,9 @@ def test_steps_per_pass_plan():
         (3, "f32", (200, 100), dict(seg_rows=8), 6),
     ]
     for N, prec, shape, launch, want in cases:
-        sim = Sim("D2Q5", rand_D(rng, N), shape, prec)
+        launch = dict(launch)
+        bc = launch.pop("bc", None)
+        sim = Sim("D2Q5", rand_D(rng, N), shape, prec, bc=bc)
         if launch:
             sim.set_launch(**launch)
         assert sim.steps_per_pass() == want, (N, prec, shape, launch)
@@ -592,8 +595,10 @@ def test_temporally_blocked_sweep_d2q4(case, tb, N, precision):
     xi0 = smooth_field(rng, N, shape[::-1], 0.15)
     steps = 23
     orc = oracle_run(oracle_problem("D2Q4", D, shape, bc=bc, xi_wall=walls), xi0, steps)
-    # FP32: m <= 2 up to six steps, m = 4 up to three; FP64: m = 1 up to six, m = 2 up to three, m = 4 one
-    want = {2: min(tb, 6), 3: min(tb, 6), 5: min(tb, 3)}[N] if precision == "f32" else \
+    # FP32: m <= 2 up to six steps, m = 4 up to four with x and y periodic and three otherwise;
+    # FP64: m = 1 up to six, m = 2 up to three, m = 4 one
+    periodic = all(kind == "periodic" for pair in bc for kind in pair)
+    want = {2: min(tb, 6), 3: min(tb, 6), 5: min(tb, 4 if periodic else 3)}[N] if precision == "f32" else \
         {2: min(tb, 6), 3: min(tb, 3), 5: 1}[N]
     for seg in (5, 32):
         launch = dict(temporal=tb, seg_rows=seg, lds_resident=0)
@@ -636,3 +641,32 @@ def test_blocked_sweep_last_tile_wave_boundary(tb, k, xbc, precision):
     probe.close()
     gpu = gpu_run("D2Q5", D, shape, precision, xi0, steps, bc=bc, xi_wall=walls, launch=launch)
     assert_parity(gpu, orc, precision, f"last tile tb={tb} {shape} {xbc} {precision}")
+
+
+@pytest.mark.parametrize("lattice", ["D2Q5", "D2Q4"])
+@pytest.mark.parametrize("shape", [(301, 29), (600, 41), (90, 130)])
+@pytest.mark.parametrize("dilute", [False, True])
+def test_blocked_sweep_quinary_four_steps(lattice, shape, dilute):
+    """Five species in FP32 on a periodic domain: four steps per pass (three with walls), over
+    several column tiles and ragged segments, calls of 1, 4, 4, 3 and 2 steps."""
+    from paper_1808_06787_amd.sim import Sim
+
+    N = 5
+    rng = np.random.default_rng(2400 + shape[0])
+    D = rand_D(rng, N)
+    bc = (("periodic", "periodic"), ("periodic", "periodic"))
+    xi0 = smooth_field(rng, N, shape[::-1], 0.15)
+    split = [1, 4, 4, 3, 2]
+    orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, dilute=dilute), xi0, sum(split))
+    launch = dict(seg_rows=7, lds_resident=0)
+    probe = Sim(lattice, D, shape, "f32", bc=bc, dilute=dilute)
+    probe.set_launch(**launch)
+    assert probe.steps_per_pass() == 4, (lattice, shape)
+    probe.close()
+    walled = Sim(lattice, D, shape, "f32", bc=(("zero_flux", "zero_flux"), ("periodic", "periodic")),
+                 dilute=dilute)
+    walled.set_launch(**launch)
+    assert walled.steps_per_pass() == 3, (lattice, shape)
+    walled.close()
+    gpu = gpu_run(lattice, D, shape, "f32", xi0, sum(split), bc=bc, launch=launch, split=split, dilute=dilute)
+    assert_parity(gpu, orc, "f32", f"quinary four steps {lattice} {shape} dilute={dilute}")
