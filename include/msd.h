@@ -381,10 +381,12 @@ MSD_API int msd_get_launch(const msd_sim* sim, msd_launch* launch);
  * tuning leaves the simulation unchanged.  candidates: `count` launches, or
  * count = 0 for the library's list (tile shapes, vector widths, XCD remapping,
  * streaming hints, and for D2Q5 steps per pass and segment heights).
- * budget_ms > 0 stops once that much timed GPU work is spent.  The fastest
- * launch is applied and returned in *h_best with its milliseconds per step;
- * h_trial_ms (NULL, or one entry per candidate) receives every trial's time
- * (-1 if not run).  cache_path (NULL: none) is a text file of lines "<key>
+ * budget_ms > 0 stops once that much timed GPU work is spent.  The four
+ * fastest candidates are then timed twice more (up to twice the budget) and
+ * keep their best time, since one trial of a few milliseconds can be off by
+ * several per cent.  The fastest launch is applied and returned in *h_best
+ * with its milliseconds per step; h_trial_ms (NULL, or one entry per
+ * candidate) receives every candidate's best time (-1 if not run).  cache_path (NULL: none) is a text file of lines "<key>
  * <8 launch fields> <ms>" keyed by GPU architecture, lattice, precision,
  * species count, extents and faces: a hit is applied without timing (unless
  * flags has MSD_TUNE_IGNORE_CACHE) and a new result is appended.  Errors:

@@ -3,9 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/msd.h"
 #include "msd_launch.h"
@@ -58,11 +60,13 @@ void cache_store(const char* path, const std::string& key, int k, const int64_t*
 // Times candidates 0..n-1: apply(i) selects one (nonzero status: skipped, time
 // -1), then one warm-up step, `steps` steps between two events on `stream`, and
 // restore() puts state and time back.  Stops once budget_ms of timed GPU work
-// is spent (<= 0: no limit; untried candidates get -1).  Returns the index of
-// the fastest candidate in *best (-1 if none ran) or a status.
+// is spent (<= 0: no limit; untried candidates get -1).  One trial of a few
+// milliseconds can be off by several per cent, so the `refine` fastest
+// candidates are then timed twice more and keep their best time.  Returns the
+// index of the fastest candidate in *best (-1 if none ran) or a status.
 template <class Apply, class Step, class Restore>
 int time_candidates(hipStream_t stream, int n, int steps, double budget_ms, Apply apply, Step step, Restore restore,
-                    double* ms, int* best) {
+                    double* ms, int* best, int refine = 4) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -70,26 +74,44 @@ int time_candidates(hipStream_t stream, int n, int steps, double budget_ms, Appl
   *best = -1;
   double spent = 0.0;
   int st = MSD_OK;
+  // one timed trial of candidate i: its ms per step, or -1 if it does not apply
+  auto trial = [&](int i, double* out) -> int {
+    *out = -1.0;
+    if (apply(i) != MSD_OK) return MSD_OK;
+    int s = step(1);
+    if (s != MSD_OK) return s;
+    hipError_t he = hipEventRecord(e0, stream);
+    if (he != hipSuccess) return hip_fail(he, "tuning event");
+    s = step(steps);
+    if (s != MSD_OK) return s;
+    he = hipEventRecord(e1, stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+    if (he != hipSuccess) return hip_fail(he, "tuning timing");
+    spent += t;
+    *out = (double)t / steps;
+    return restore();
+  };
   for (int i = 0; i < n; ++i) ms[i] = -1.0;
   for (int i = 0; i < n && st == MSD_OK; ++i) {
     if (budget_ms > 0 && spent >= budget_ms) break;
-    if (apply(i) != MSD_OK) continue;
-    st = step(1);
-    if (st != MSD_OK) break;
-    e = hipEventRecord(e0, stream);
-    if (e != hipSuccess) { st = hip_fail(e, "tuning event"); break; }
-    st = step(steps);
-    if (st != MSD_OK) break;
-    e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float t = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-    if (e != hipSuccess) { st = hip_fail(e, "tuning timing"); break; }
-    spent += t;
-    ms[i] = (double)t / steps;
-    if (*best < 0 || ms[i] < ms[*best]) *best = i;
-    st = restore();
+    st = trial(i, &ms[i]);
   }
+  std::vector<int> top;
+  for (int i = 0; i < n; ++i)
+    if (ms[i] >= 0) top.push_back(i);
+  std::sort(top.begin(), top.end(), [&](int a, int b) { return ms[a] < ms[b]; });
+  if ((int)top.size() > refine) top.resize((size_t)std::max(refine, 0));
+  for (int round = 0; round < 2 && st == MSD_OK && top.size() > 1; ++round)
+    for (int i : top) {
+      if (st != MSD_OK || (budget_ms > 0 && spent >= 2 * budget_ms)) break;
+      double t = -1.0;
+      st = trial(i, &t);
+      if (t >= 0 && t < ms[i]) ms[i] = t;
+    }
+  for (int i = 0; i < n; ++i)
+    if (ms[i] >= 0 && (*best < 0 || ms[i] < ms[*best])) *best = i;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
