@@ -138,13 +138,19 @@ msd::LaunchArgs member_args(const msd_batch* b, int idx) {
 }
 
 // Steps per pass for a class of `m` evolved species under schedule `sc`: the
-// largest count up to sc.temporal whose on-chip window fits, 0 for one step.
+// largest count up to sc.temporal whose on-chip window fits (the walled window
+// if any member has an x or y wall: the class then launches the walled
+// instantiation), 0 for one step.
 int class_steps_per_pass(const msd_batch* b, const std::vector<int>& g, int m) {
   if (b->lattice != MSD_D2Q5 || b->sched.temporal < 2) return 0;
-  for (int i : g)
+  bool walls = false;
+  for (int i : g) {
     if ((uint64_t)b->mem[i].plane * (uint64_t)b->prec >= (1ull << 32)) return 0;
+    const msd_problem& p = b->mem[i].prob;
+    if (p.bc[0] != MSD_BC_PERIODIC || p.bc[2] != MSD_BC_PERIODIC) walls = true;
+  }
   for (int t = b->sched.temporal; t >= 2; --t)
-    if (msd::blocked_cols(m, t, b->prec) > 0 && msd::blocked_walls_ok(m, t, b->prec)) return t;
+    if (msd::blocked_cols(m, t, b->prec) > 0 && (!walls || msd::blocked_walls_ok(m, t, b->prec))) return t;
   return 0;
 }
 

@@ -696,10 +696,16 @@ __global__ __launch_bounds__(C, 2) void k_step_blocked_dilute(Problem p, const T
 // The blocked sweep over the mixtures of one batch class (equal m): workgroup
 // g takes tile table entry tile_begin + g, i.e. (mixture, column tile + segment
 // * column tiles of that mixture); cur selects each mixture's source buffer.
+// rec_stride is 0 in every launch (a batch records nothing); it is taken at run
+// time, as in the single-mixture sweep, because with a compile-time 0 the
+// compiler schedules the march differently and holds more registers (quinary,
+// three steps: 256 VGPRs instead of 186; four steps would not fit two waves
+// per SIMD).
 template <int M, typename T, int TB, int C, bool WALLS, bool DIL>
 __device__ __forceinline__ void batch_blocked_body(const BatchInst* __restrict__ insts,
                                                    const BatchTile* __restrict__ tiles, uint32_t tile_begin,
-                                                   char* __restrict__ ws, int cur, int seg_rows, int nontemporal) {
+                                                   char* __restrict__ ws, int cur, int seg_rows, int nontemporal,
+                                                   int64_t rec_stride) {
   constexpr int W = C - 2 * TB;
   // The table entries are uniform but read by vector loads: move the fields the
   // tile uses to scalar registers (the tile addresses planes from scalar bases).
@@ -722,15 +728,16 @@ __device__ __forceinline__ void batch_blocked_body(const BatchInst* __restrict__
   T* dst = reinterpret_cast<T*>(ws + u64(I->half_off[1 - cur]));
   const Consts<T>* cst = reinterpret_cast<const Consts<T>*>(ws + u64(I->consts_off));
   blocked_tile<M, T, TB, C, WALLS, DIL>(p, src, dst, cst, seg_rows, bt.tile % tiles_x, bt.tile / tiles_x,
-                                        nontemporal);
+                                        nontemporal, rec_stride);
 }
 
 template <int M, typename T, int TB, int C, bool WALLS>
 __global__ __launch_bounds__(C) void k_batch_step_blocked(const BatchInst* __restrict__ insts,
                                                           const BatchTile* __restrict__ tiles, uint32_t tile_begin,
                                                           char* __restrict__ ws, int cur, int seg_rows,
-                                                          int nontemporal) {
-  batch_blocked_body<M, T, TB, C, WALLS, false>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal);
+                                                          int nontemporal, int64_t rec_stride) {
+  batch_blocked_body<M, T, TB, C, WALLS, false>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal,
+                                                rec_stride);
 }
 
 // A class of dilute-species mixtures (diagonal A); two waves per SIMD as for
@@ -739,8 +746,10 @@ template <int M, typename T, int TB, int C, bool WALLS>
 __global__ __launch_bounds__(C, 2) void k_batch_step_blocked_dilute(const BatchInst* __restrict__ insts,
                                                                     const BatchTile* __restrict__ tiles,
                                                                     uint32_t tile_begin, char* __restrict__ ws, int cur,
-                                                                    int seg_rows, int nontemporal) {
-  batch_blocked_body<M, T, TB, C, WALLS, true>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal);
+                                                                    int seg_rows, int nontemporal,
+                                                                    int64_t rec_stride) {
+  batch_blocked_body<M, T, TB, C, WALLS, true>(insts, tiles, tile_begin, ws, cur, seg_rows, nontemporal,
+                                               rec_stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -1651,28 +1660,31 @@ hipError_t launch_blocked_tb(const LaunchArgs& a) {
 
 template <int M, typename T, int TB>
 hipError_t launch_batch_blocked_tb(const LaunchArgs& a) {
-  // the batched kernels hold more registers: the walled window at any faces
-  constexpr int C = blocked_walls_ok(M, TB, (int)sizeof(T)) ? blocked_cols(M, TB, (int)sizeof(T)) : 0;
+  constexpr int C = blocked_cols(M, TB, (int)sizeof(T));
   if constexpr (C == 0) {
     return hipErrorInvalidValue;
   } else {
     if (a.ntiles == 0) return hipSuccess;
     const size_t pad = blocked_lds_pad<M, T, TB, C>(a);
     const dim3 grid(a.ntiles);
-    if (a.dilute) {
-      if (a.walls)
+    const int64_t no_record = 0;
+    if (a.walls) {
+      // walled instantiations only up to their own (smaller) window
+      if constexpr (!blocked_walls_ok(M, TB, (int)sizeof(T))) {
+        return hipErrorInvalidValue;
+      } else if (a.dilute) {
         hipLaunchKernelGGL((k_batch_step_blocked_dilute<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.insts,
-                           a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
-      else
-        hipLaunchKernelGGL((k_batch_step_blocked_dilute<M, T, TB, C, false>), grid, dim3(C), pad, a.stream,
-                           a.insts, a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
-    } else {
-      if (a.walls)
+                           a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal, no_record);
+      } else {
         hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, true>), grid, dim3(C), pad, a.stream, a.insts, a.tiles,
-                           a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
-      else
-        hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.insts, a.tiles,
-                           a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal);
+                           a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal, no_record);
+      }
+    } else if (a.dilute) {
+      hipLaunchKernelGGL((k_batch_step_blocked_dilute<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.insts,
+                         a.tiles, a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal, no_record);
+    } else {
+      hipLaunchKernelGGL((k_batch_step_blocked<M, T, TB, C, false>), grid, dim3(C), pad, a.stream, a.insts, a.tiles,
+                         a.tile_begin, a.ws, a.cur, a.seg_rows, a.nontemporal, no_record);
     }
     return hipSuccess;
   }

@@ -310,9 +310,9 @@ def test_separate_handles_reference_matches_oracle():
 def test_remainder_passes_match_oracle(steps):
     """Calls whose length is not a multiple of a class's steps per pass: full
     blocked passes, then one shorter pass for a remainder of two or more steps
-    (a remainder of one is a single step).  Six, five and three steps per pass
-    for the classes of 2, 3 and 4 evolved species; every mixture matches the
-    oracle after each call."""
+    (a remainder of one is a single step).  Six, five and four steps per pass
+    for the classes of 2, 3 and 4 evolved species (the last one periodic);
+    every mixture matches the oracle after each call."""
     rng = np.random.default_rng(78)
     specs, fields = _specs("D2Q5", rng)
     b = _batch("D2Q5", "f32", specs, fields)
@@ -327,4 +327,29 @@ def test_remainder_passes_match_oracle(steps):
         p = oracle_problem("D2Q5", sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"], relax=sp["relax"],
                            trt_magic=sp["trt_magic"])
         assert_parity(got[i], oracle_run(p, f, t), "f32", f"remainder {steps}: mixture {i}")
+    b.close()
+
+
+@pytest.mark.parametrize("walled", [False, True])
+def test_quinary_class_steps_per_pass(walled):
+    """A class of five-species mixtures over several column tiles: four steps per
+    pass when every member is periodic, three when one has an x wall (the class
+    then launches the walled kernel); ragged widths, remainder passes, graph
+    replay, against the oracle."""
+    rng = np.random.default_rng(79 + int(walled))
+    shapes = [(300, 40), (261, 33), (90, 70)]
+    specs = []
+    for j, shape in enumerate(shapes):
+        bc = (("zero_flux", "dirichlet"), ("periodic", "periodic")) if (walled and j == 1) else None
+        walls = {(0, 1): rand_field(rng, 5, ())} if bc else None
+        specs.append(dict(D=rand_D(rng, 5), shape=shape, bc=bc, xi_wall=walls))
+    fields = [smooth_field(rng, 5, sp["shape"][::-1], 0.1) for sp in specs]
+    b = _batch("D2Q5", "f32", specs, fields)
+    b.set_schedule(temporal=6, seg_rows=8)
+    for n in (1, 8, 7):
+        b.step(n)
+    got = _read_all(b)
+    for i, (sp, f) in enumerate(zip(specs, fields)):
+        p = oracle_problem("D2Q5", sp["D"], sp["shape"], bc=sp["bc"], xi_wall=sp["xi_wall"])
+        assert_parity(got[i], oracle_run(p, f, 16), "f32", f"quinary class walled={walled}: mixture {i}")
     b.close()
