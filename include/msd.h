@@ -338,9 +338,10 @@ typedef struct msd_launch {
                                levels of a few rows on chip; the blocked adjoint pass is
                                D2Q5-only).  The library takes the largest count up
                                to this one whose on-chip window fits the species count and
-                               precision (FP32: m <= 2 up to 6, m = 3 up to 5, m = 4 up to 4
-                               when x and y are periodic and up to 3 otherwise; FP64: m = 1 up
-                               to 6, m = 2 up to 3; else one step per pass).
+                               precision (FP32 with x and y periodic: m <= 3 up to 6, m = 4
+                               up to 5; FP32 with an x or y wall: m <= 2 up to 6, m = 3 up to
+                               5, m = 4 up to 3; FP64: m = 1 up to 6, m = 2 up to 3; else one
+                               step per pass).
                                D2Q5 FP32 problems with nx >= 6144 use 512-column tiles for
                                full passes (m <= 2 at six steps; m = 3 at five steps when x
                                and y are periodic), all other passes 256-column tiles.
@@ -433,8 +434,8 @@ typedef struct msd_schedule {
   int32_t nontemporal;      /* streaming-hint mask, as in msd_launch */
   int32_t temporal;         /* D2Q5: at most this many steps (2..6) per pass over HBM with the
                                temporally blocked sweep, as in msd_launch (each class of equal
-                               N takes the largest count its on-chip window allows, m = 4 up
-                               to 3 at any faces; classes
+                               N takes the largest count its on-chip window allows, the
+                               walled limits if any member has an x or y wall; classes
                                then launch separately whatever `mode` says, and block_x,
                                block_y, order apply to their single steps); 0 or 1: one step
                                per launch.  Default 6 for D2Q5, 0 otherwise */

@@ -312,9 +312,16 @@ BlockedPlan blocked_plan(const msd_sim* s, bool adjoint = false) {
       break;
     }
   if (tb == 0) return pl;
-  if (d2q5 && !adjoint && !s->prob.dilute && msd::blocked_wide_ok(s->m, tb, s->prob.precision) &&
-      (!xy_walls || msd::blocked_wide_walls_ok(s->m)) && s->prob.nx >= msd::kWideMinNx)
-    pl.cols = msd::kBlockedColsWide;
+  // wide domains: the 512-column tile where one exists, at its own steps per
+  // pass if that is fewer (m = 3: five steps on 512 columns beat six on 256)
+  if (d2q5 && !adjoint && !s->prob.dilute && (!xy_walls || msd::blocked_wide_walls_ok(s->m)) &&
+      s->prob.nx >= msd::kWideMinNx)
+    for (int t = tb; t >= 2; --t)
+      if (msd::blocked_wide_ok(s->m, t, s->prob.precision)) {
+        tb = t;
+        pl.cols = msd::kBlockedColsWide;
+        break;
+      }
   const int64_t W = pl.cols - 2 * tb;
   const int64_t tiles_x = (s->prob.nx + W - 1) / W;
   auto groups = [&](int64_t seg) { return tiles_x * ((s->prob.ny + seg - 1) / seg); };

@@ -108,18 +108,21 @@ struct LaunchArgs {
 // workgroups per CU), so each lane may hold up to 256 VGPRs: the per-thread
 // register window (7m values per time level plus the input rows) and the
 // collision's temporaries.  The largest tb that stays within that was read off
-// the compiled kernels: FP32 m = 1, 2: 6, m = 3: 5, m = 4: 4 where x and y are
-// periodic and 3 otherwise (the walled D2Q5 instantiation, and the batched one
-// at any faces, would spill at 4); FP64 m = 1: 6, m = 2: 3; FP64 m >= 3: none.
-// The LDS exchange of the x-directions takes (tb - 1) levels * 2 rows * 2
+// the compiled kernels (single and batched alike): FP32 with x and y periodic
+// m <= 3: 6, m = 4: 5 (236 VGPRs on D2Q5); with an x or y wall the face code
+// costs registers: m <= 2: 6, m = 3: 5, m = 4: 3 (the walled instantiations
+// would spill one step further); FP64 m = 1: 6, m = 2: 3, m >= 3: none.  The
+// LDS exchange of the x-directions takes (tb - 1) levels * 2 rows * 2
 // directions * m * cols values (<= 64 KiB here).
 constexpr int kBlockedCols = 256;
 constexpr int kMaxStepsPerPass = 6;
 constexpr int blocked_max_tb(int m, int bytes) {
-  return bytes == 4 ? (m <= 2 ? 6 : m == 3 ? 5 : m == 4 ? 4 : 0) : (m == 1 ? 6 : m == 2 ? 3 : 0);
+  return bytes == 4 ? (m <= 3 ? 6 : m == 4 ? 5 : 0) : (m == 1 ? 6 : m == 2 ? 3 : 0);
 }
-// The limit of the walled instantiations and of the batched sweep.
-constexpr int blocked_max_tb_walls(int m, int bytes) { return (bytes == 4 && m == 4) ? 3 : blocked_max_tb(m, bytes); }
+// The limit of the walled instantiations.
+constexpr int blocked_max_tb_walls(int m, int bytes) {
+  return bytes == 4 ? (m <= 2 ? 6 : m == 3 ? 5 : m == 4 ? 3 : 0) : blocked_max_tb(m, bytes);
+}
 constexpr bool blocked_walls_ok(int m, int tb, int bytes) { return tb <= blocked_max_tb_walls(m, bytes); }
 constexpr int blocked_cols(int m, int tb, int bytes) {
   return (tb >= 2 && tb <= kMaxStepsPerPass && tb <= blocked_max_tb(m, bytes) &&

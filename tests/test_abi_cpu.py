@@ -194,13 +194,14 @@ def test_blocked_plan_limits_without_device():
     cases = [
         ("D2Q5", 3, "f32", (16384, 16384), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f32", (32768, 32768), dict(seg_rows=16), 1),
-        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 5),
+        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16), 6),
+        ("D2Q5", 4, "f32", (4096, 1024), dict(seg_rows=16, bc=(("zero_flux", "zero_flux"), ("periodic", "periodic"))), 5),
         ("D2Q5", 4, "f32", (8192, 1024), dict(seg_rows=16), 5),
-        # m = 4: four steps with x and y periodic, three with walls
-        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 4),
+        # m = 4: five steps with x and y periodic, three with walls
+        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16), 5),
         ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16, bc=(("zero_flux", "zero_flux"), ("periodic", "periodic"))), 3),
         ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16, bc=(("periodic", "periodic"), ("dirichlet", "zero_flux"))), 3),
-        ("D2Q4", 5, "f32", (4096, 1024), dict(seg_rows=16), 4),
+        ("D2Q4", 5, "f32", (4096, 1024), dict(seg_rows=16), 5),
         ("D2Q5", 6, "f32", (4096, 1024), dict(seg_rows=16), 1),
         ("D2Q5", 2, "f64", (4096, 1024), dict(seg_rows=16), 6),
         ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16), 3),
@@ -228,7 +229,7 @@ def test_blocked_plan_limits_without_device():
         ("D3Q15", 3, "f32", (64, 64, 64), dict(seg_rows=16), 1),
         # the dilute-species mode has its own blocked kernel with the same limits
         ("D2Q5", 3, "f32", (4096, 1024), dict(seg_rows=16, dilute=True), 6),
-        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16, dilute=True), 4),
+        ("D2Q5", 5, "f32", (4096, 1024), dict(seg_rows=16, dilute=True), 5),
         ("D2Q5", 3, "f64", (4096, 1024), dict(seg_rows=16, dilute=True), 3),
     ]
     for lattice, N, prec, shape, launch, want in cases:

@@ -310,9 +310,10 @@ def test_separate_handles_reference_matches_oracle():
 def test_remainder_passes_match_oracle(steps):
     """Calls whose length is not a multiple of a class's steps per pass: full
     blocked passes, then one shorter pass for a remainder of two or more steps
-    (a remainder of one is a single step).  Six, five and four steps per pass
-    for the classes of 2, 3 and 4 evolved species (the last one periodic);
-    every mixture matches the oracle after each call."""
+    (a remainder of one is a single step).  Six, six and five steps per pass
+    for the classes of 2, 3 and 4 evolved species (walled members hold the
+    class of 3 at five and of 4 at three); every mixture matches the oracle
+    after each call."""
     rng = np.random.default_rng(78)
     specs, fields = _specs("D2Q5", rng)
     b = _batch("D2Q5", "f32", specs, fields)
@@ -332,7 +333,7 @@ def test_remainder_passes_match_oracle(steps):
 
 @pytest.mark.parametrize("walled", [False, True])
 def test_quinary_class_steps_per_pass(walled):
-    """A class of five-species mixtures over several column tiles: four steps per
+    """A class of five-species mixtures over several column tiles: five steps per
     pass when every member is periodic, three when one has an x wall (the class
     then launches the walled kernel); ragged widths, remainder passes, graph
     replay, against the oracle."""

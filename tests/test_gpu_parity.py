@@ -488,8 +488,9 @@ def test_steps_per_pass_plan():
         (3, "f32", (4096, 512), {}, 6),
         (3, "f32", (4096, 4096), dict(temporal=4, seg_rows=0), 4),
         (2, "f64", (2048, 512), {}, 6),
-        (4, "f32", (2048, 1024), {}, 5),
-        (5, "f32", (2048, 1024), {}, 4),
+        (4, "f32", (2048, 1024), {}, 6),
+        (4, "f32", (2048, 1024), dict(bc=(("zero_flux", "zero_flux"), ("periodic", "periodic"))), 5),
+        (5, "f32", (2048, 1024), {}, 5),
         (5, "f32", (2048, 1024), dict(bc=(("zero_flux", "zero_flux"), ("periodic", "periodic"))), 3),
         (3, "f64", (2048, 1024), {}, 3),
         (4, "f64", (2048, 1024), {}, 1),
@@ -595,10 +596,10 @@ def test_temporally_blocked_sweep_d2q4(case, tb, N, precision):
     xi0 = smooth_field(rng, N, shape[::-1], 0.15)
     steps = 23
     orc = oracle_run(oracle_problem("D2Q4", D, shape, bc=bc, xi_wall=walls), xi0, steps)
-    # FP32: m <= 2 up to six steps, m = 4 up to four with x and y periodic and three otherwise;
+    # FP32: m <= 2 up to six steps, m = 4 up to five with x and y periodic and three otherwise;
     # FP64: m = 1 up to six, m = 2 up to three, m = 4 one
     periodic = all(kind == "periodic" for pair in bc for kind in pair)
-    want = {2: min(tb, 6), 3: min(tb, 6), 5: min(tb, 4 if periodic else 3)}[N] if precision == "f32" else \
+    want = {2: min(tb, 6), 3: min(tb, 6), 5: min(tb, 5 if periodic else 3)}[N] if precision == "f32" else \
         {2: min(tb, 6), 3: min(tb, 3), 5: 1}[N]
     for seg in (5, 32):
         launch = dict(temporal=tb, seg_rows=seg, lds_resident=0)
@@ -646,9 +647,9 @@ def test_blocked_sweep_last_tile_wave_boundary(tb, k, xbc, precision):
 @pytest.mark.parametrize("lattice", ["D2Q5", "D2Q4"])
 @pytest.mark.parametrize("shape", [(301, 29), (600, 41), (90, 130)])
 @pytest.mark.parametrize("dilute", [False, True])
-def test_blocked_sweep_quinary_four_steps(lattice, shape, dilute):
-    """Five species in FP32 on a periodic domain: four steps per pass (three with walls), over
-    several column tiles and ragged segments, calls of 1, 4, 4, 3 and 2 steps."""
+def test_blocked_sweep_quinary_periodic_passes(lattice, shape, dilute):
+    """Five species in FP32 on a periodic domain: five steps per pass (three with walls), over
+    several column tiles and ragged segments, calls of 1, 5, 4, 3 and 2 steps."""
     from paper_1808_06787_amd.sim import Sim
 
     N = 5
@@ -656,12 +657,12 @@ def test_blocked_sweep_quinary_four_steps(lattice, shape, dilute):
     D = rand_D(rng, N)
     bc = (("periodic", "periodic"), ("periodic", "periodic"))
     xi0 = smooth_field(rng, N, shape[::-1], 0.15)
-    split = [1, 4, 4, 3, 2]
+    split = [1, 5, 4, 3, 2]
     orc = oracle_run(oracle_problem(lattice, D, shape, bc=bc, dilute=dilute), xi0, sum(split))
     launch = dict(seg_rows=7, lds_resident=0)
     probe = Sim(lattice, D, shape, "f32", bc=bc, dilute=dilute)
     probe.set_launch(**launch)
-    assert probe.steps_per_pass() == 4, (lattice, shape)
+    assert probe.steps_per_pass() == 5, (lattice, shape)
     probe.close()
     walled = Sim(lattice, D, shape, "f32", bc=(("zero_flux", "zero_flux"), ("periodic", "periodic")),
                  dilute=dilute)
@@ -669,4 +670,4 @@ def test_blocked_sweep_quinary_four_steps(lattice, shape, dilute):
     assert walled.steps_per_pass() == 3, (lattice, shape)
     walled.close()
     gpu = gpu_run(lattice, D, shape, "f32", xi0, sum(split), bc=bc, launch=launch, split=split, dilute=dilute)
-    assert_parity(gpu, orc, "f32", f"quinary four steps {lattice} {shape} dilute={dilute}")
+    assert_parity(gpu, orc, "f32", f"quinary periodic passes {lattice} {shape} dilute={dilute}")
