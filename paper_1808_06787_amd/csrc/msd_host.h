@@ -103,7 +103,7 @@ int time_candidates(hipStream_t stream, int n, int steps, double budget_ms, Appl
     if (ms[i] >= 0) top.push_back(i);
   std::sort(top.begin(), top.end(), [&](int a, int b) { return ms[a] < ms[b]; });
   if ((int)top.size() > refine) top.resize((size_t)std::max(refine, 0));
-  for (int round = 0; round < 2 && st == MSD_OK && top.size() > 1; ++round)
+  for (int again = 0; again < 2 && st == MSD_OK && top.size() > 1; ++again)
     for (int i : top) {
       if (st != MSD_OK || (budget_ms > 0 && spent >= 2 * budget_ms)) break;
       double t = -1.0;
