@@ -133,6 +133,58 @@ def test_largest_blocked_planes_sampled():
     sim.close()
 
 
+@pytest.mark.parametrize("n,N", [(32768, 3), (46340, 2)])
+def test_planes_of_4_gib_and_more_sampled(n, N):
+    """Planes of 4 GiB and more in FP32: 32768^2 ternary (2^30 nodes, planes of
+    exactly 4 GiB, 80 GiB of state) and 46340^2 binary (the largest square under
+    the 2^31-node limit, planes of 8 GiB, ragged last tiles).  The blocked sweep's
+    32-bit plane offsets do not reach, so every step is a single-step pass through
+    the 64-bit kernels (init, sweep, read, diagnostics); sampled nodes after 5
+    steps against the oracle on light cones, corners included."""
+    from paper_1808_06787_amd.sim import Sim
+
+    steps = 5
+    rng = np.random.default_rng(11)
+    Dm = np.ones((N, N))
+    for i in range(N):
+        for j in range(i + 1, N):
+            Dm[i, j] = Dm[j, i] = float(np.exp(rng.uniform(np.log(0.05), np.log(0.5))))
+    dev = torch.device("cuda", 0)
+    xi0 = torch.empty((N - 1, n, n), dtype=torch.float64, device=dev)
+    xs = torch.arange(n, dtype=torch.float64, device=dev)
+    for r0 in range(0, n, 2048):
+        r1 = min(n, r0 + 2048)
+        yy, xx = torch.meshgrid(torch.arange(r0, r1, dtype=torch.float64, device=dev), xs, indexing="ij")
+        comps = _wave_field(xx, yy, n, N, torch)
+        for i in range(N - 1):
+            xi0[i, r0:r1] = comps[i]
+        del yy, xx, comps
+    sim = Sim("D2Q5", Dm, (n, n), "f32")
+    assert sim.steps_per_pass() == 1
+    sim.init(xi0)
+    sim.step(steps)
+    torch.cuda.synchronize()
+    del xi0
+    sim._xi0 = None
+    sim.diagnostics()
+    xi, J, _ = sim.read(torch.float32, grad=False)
+    h = steps + 1
+    nodes = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(8)]
+    nodes += [(0, 0), (n - 1, n - 1), (n - 1, 0), (n - 3, n // 2)]
+    for (x, y) in nodes:
+        ix = np.arange(x - h, x + h + 1) % n
+        iy = np.arange(y - h, y + h + 1) % n
+        X, Y = np.meshgrid(ix.astype(np.float64), iy.astype(np.float64))
+        sub = np.stack(_wave_field(X, Y, n, N, np))
+        p = lbm.Problem("D2Q5", Dm, (2 * h + 1, 2 * h + 1), bc=((lbm.ZERO_FLUX, lbm.ZERO_FLUX),) * 2)
+        oxi, _, oJ = lbm.observables(p, lbm.run(p, sub, steps))
+        assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= 1e-5, (n, x, y)
+        assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= 2e-6, (n, x, y)
+    del xi, J
+    sim.close()
+    torch.cuda.empty_cache()
+
+
 def test_quaternary_3d_full_size_sampled():
     w = workloads.quaternary_3d()
     print("worst |dxi|", _sampled_parity(w, 3, 16, 2))
