@@ -1,11 +1,13 @@
 """Hand-written adjoint of the sweep (through the C ABI) against the autograd
 twin of the oracle and against central finite differences of the GPU forward
 run in FP64."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
 
-from gpu_cases import oracle_problem, rand_D, rand_field, smooth_field
+from gpu_cases import assert_parity, oracle_problem, oracle_run, rand_D, rand_field, smooth_field
 from oracle import twin
 
 pytestmark = pytest.mark.gpu
@@ -320,3 +322,54 @@ def test_adjoint_with_wide_tile_recomputation_fp32():
     ref = twin.misfit_gradients(oracle_problem("D2Q5", D, shape), xi0, target, steps)
     _compare(ref, wide, 2e-4, "wide-tile recomputation vs twin")
     _compare(narrow, wide, 2e-5, "wide vs 256-column recomputation")
+
+
+RECORD_CASES = [
+    ((300, 24), (("periodic", "periodic"), ("periodic", "periodic"))),
+    ((250, 21), (("dirichlet", "zero_flux"), ("periodic", "periodic"))),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RECORD_CASES)))
+@pytest.mark.parametrize("precision,N,tb", [("f32", 3, 6), ("f32", 3, 4), ("f64", 2, 3)])
+def test_record_slots_match_oracle(case, precision, N, tb):
+    """msd_record through blocked passes (full passes and a shorter remainder,
+    8-row segments over two column tiles) stores the state after every step:
+    each slot, restored into a second handle at its time, reads back the
+    oracle's moments at that time; the recording handle ends on the last slot.
+    Periodic domains take the recording instantiation, walled ones the general
+    blocked kernel."""
+    from paper_1808_06787_amd import _ffi as F
+    from paper_1808_06787_amd.sim import Sim
+
+    rng = np.random.default_rng(500 + 10 * case + tb)
+    shape, bc = RECORD_CASES[case]
+    D = rand_D(rng, N)
+    walls = {(0, 0): rand_field(rng, N, ())} if bc[0][0] == "dirichlet" else {}
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    launch = dict(temporal=tb, seg_rows=8, lds_resident=0)
+    sim = Sim("D2Q5", D, shape, precision, bc=bc, xi_wall=walls)
+    sim.set_launch(**launch)
+    assert sim.steps_per_pass() == tb
+    sim.init(torch.from_numpy(xi0))
+    sim.step(1)
+    n = 2 * tb + 2
+    sb = sim.state_bytes()
+    stack = torch.empty(n * sb, dtype=torch.uint8, device=sim.device)
+    torch.cuda.synchronize()
+    F.check(sim.lib.msd_record(sim._h, n, C.c_void_p(stack.data_ptr())), "msd_record")
+    torch.cuda.synchronize()
+    assert sim.time == 1 + n
+    last = sim.read(torch.float64)
+    other = Sim("D2Q5", D, shape, precision, bc=bc, xi_wall=walls)
+    other.init(torch.from_numpy(xi0))
+    p = oracle_problem("D2Q5", D, shape, bc=bc, xi_wall=walls)
+    for j in range(n):
+        other.restore(stack[j * sb:(j + 1) * sb], 2 + j)
+        got = [a.cpu().numpy() for a in other.read(torch.float64)]
+        assert_parity(got, oracle_run(p, xi0, 2 + j), precision, f"slot {j} ({precision}, tb {tb}, case {case})")
+    got = [a.cpu().numpy() for a in other.read(torch.float64)]
+    for a, b in zip(got, last):
+        np.testing.assert_array_equal(a, b.cpu().numpy())
+    other.close()
+    sim.close()
