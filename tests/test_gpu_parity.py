@@ -671,3 +671,30 @@ def test_blocked_sweep_quinary_periodic_passes(lattice, shape, dilute):
     walled.close()
     gpu = gpu_run(lattice, D, shape, "f32", xi0, sum(split), bc=bc, launch=launch, split=split, dilute=dilute)
     assert_parity(gpu, orc, "f32", f"quinary periodic passes {lattice} {shape} dilute={dilute}")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("launch", [None, dict(temporal=6, seg_rows=8, lds_resident=0)])
+def test_absent_species_reduces_to_the_binary_mixture(precision, launch):
+    """A ternary mixture whose second species is absent everywhere (xi_2 = 0):
+    the row of B for that species is diagonal (Eq. (2-10)), so it stays absent
+    and the others evolve as the binary mixture with D = D_13.  The ternary run
+    (m = 2 kernels) matches the oracle and the binary run (m = 1 kernels), one
+    step per pass and through six-step blocked passes."""
+    rng = np.random.default_rng(88)
+    shape = (300, 24)
+    bc = (("periodic", "periodic"), ("zero_flux", "zero_flux"))
+    D3 = rand_D(rng, 3, 0.05, 0.5)
+    D2 = np.array([[1.0, D3[0, 2]], [D3[0, 2], 1.0]])
+    two = smooth_field(rng, 2, shape[::-1], 0.1)
+    three = np.stack([two[0], np.zeros(shape[::-1]), two[1]])
+    steps = 25
+    got3 = gpu_run("D2Q5", D3, shape, precision, three, steps, bc=bc, launch=launch)
+    got2 = gpu_run("D2Q5", D2, shape, precision, two, steps, bc=bc, launch=launch)
+    assert_parity(got3, oracle_run(oracle_problem("D2Q5", D3, shape, bc=bc), three, steps), precision, "ternary")
+    tol = 1e-13 if precision == "f64" else 2e-6
+    assert np.abs(got3[0][1]).max() <= (1e-15 if precision == "f64" else 1e-7)
+    assert np.abs(got3[1][1]).max() <= (1e-15 if precision == "f64" else 1e-7)
+    np.testing.assert_allclose(got3[0][0], got2[0][0], rtol=0, atol=tol)
+    np.testing.assert_allclose(got3[0][2], got2[0][1], rtol=0, atol=tol)
+    np.testing.assert_allclose(got3[1][0], got2[1][0], rtol=0, atol=tol)

@@ -332,3 +332,32 @@ def test_diagonal_lattice_dirichlet_walls_reach_linear_steady_state(name):
     x = np.arange(n) + 0.5
     expect = lo + (hi - lo) * x / n
     np.testing.assert_allclose(xi, np.broadcast_to(expect, xi.shape), rtol=0, atol=1e-3)
+
+
+@pytest.mark.parametrize("lattice,shape,bc", [
+    ("D2Q5", (24, 20), ((lbm.PERIODIC, lbm.PERIODIC), (lbm.ZERO_FLUX, lbm.ZERO_FLUX))),
+    ("D1Q3", (64,), ((lbm.ZERO_FLUX, lbm.ZERO_FLUX),)),
+])
+def test_absent_species_reduces_to_the_binary_mixture(lattice, shape, bc):
+    """Eq. (2-10): with xi_2 = 0 everywhere the row of B for species 2 has only
+    its diagonal, so species 2 stays absent, and species 1 sees
+    B_11 = (xi_1 + xi_3)/D_13 = 1/D_13: the ternary run equals the binary
+    mixture of species 1 and 3 with D = D_13 (Remark I).  Fails for a B that
+    mixes up D_12 and D_13 or drops the xi_i factor of the off-diagonal terms."""
+    rng = np.random.default_rng(61)
+    D3 = _rand_D(rng, 3, 0.05, 0.5)
+    nodes = tuple(reversed(shape))
+    two = _rand_field(rng, 2, nodes)
+    three = np.stack([two[0], np.zeros(nodes), two[1]])
+    steps = 40
+    pt = lbm.Problem(lattice, D3, shape, bc=bc)
+    pb = lbm.Problem(lattice, np.array([[1.0, D3[0, 2]], [D3[0, 2], 1.0]]), shape, bc=bc)
+    xt, _, Jt = lbm.observables(pt, lbm.run(pt, three, steps))
+    xb, _, Jb = lbm.observables(pb, lbm.run(pb, two, steps))
+    assert np.abs(xt[1]).max() <= 1e-15
+    assert np.abs(Jt[1]).max() <= 1e-15
+    np.testing.assert_allclose(xt[0], xb[0], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(xt[2], xb[1], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(Jt[0], Jb[0], rtol=0, atol=1e-13)
+    # the binary field is not stationary: the test compares evolved states
+    assert np.abs(xb[0] - two[0]).max() > 1e-3
