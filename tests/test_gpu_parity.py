@@ -698,3 +698,27 @@ def test_absent_species_reduces_to_the_binary_mixture(precision, launch):
     np.testing.assert_allclose(got3[0][0], got2[0][0], rtol=0, atol=tol)
     np.testing.assert_allclose(got3[0][2], got2[0][1], rtol=0, atol=tol)
     np.testing.assert_allclose(got3[1][0], got2[1][0], rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("N", [4, 5, 8])
+def test_equal_diffusivities_decouple_the_species(N, precision):
+    """Remark II: with every D_ij equal, B = I/D (Eq. (2-15)), so the small
+    inverse of the collision (cofactors for three and four evolved species,
+    pivoted elimination for seven) is diagonal and each species evolves as the
+    binary mixture (xi_i, 1 - xi_i) with the same D.  The N-species run matches
+    the oracle and, species by species, the binary kernels."""
+    rng = np.random.default_rng(90 + N)
+    shape = (90, 40)
+    d = 0.12
+    xi0 = smooth_field(rng, N, shape[::-1], 0.1)
+    steps = 30
+    got = gpu_run("D2Q5", np.full((N, N), d), shape, precision, xi0, steps)
+    assert_parity(got, oracle_run(oracle_problem("D2Q5", np.full((N, N), d), shape), xi0, steps), precision,
+                  f"N={N}")
+    tol = 1e-13 if precision == "f64" else 2e-6
+    for i in range(N - 1):
+        pair = np.stack([xi0[i], 1.0 - xi0[i]])
+        bin_ = gpu_run("D2Q5", np.full((2, 2), d), shape, precision, pair, steps)
+        np.testing.assert_allclose(got[0][i], bin_[0][0], rtol=0, atol=tol, err_msg=f"xi_{i}")
+        np.testing.assert_allclose(got[1][i], bin_[1][0], rtol=0, atol=tol, err_msg=f"J_{i}")
