@@ -342,8 +342,47 @@ def test_absent_species_reduces_to_the_binary_mixture(lattice, shape, bc):
     """Eq. (2-10): with xi_2 = 0 everywhere the row of B for species 2 has only
     its diagonal, so species 2 stays absent, and species 1 sees
     B_11 = (xi_1 + xi_3)/D_13 = 1/D_13: the ternary run equals the binary
-    mixture of species 1 and 3 with D = D_13 (Remark I).  Fails for a B that
-    mixes up D_12 and D_13 or drops the xi_i factor of the off-diagonal terms."""
+    mixture of species 1 and 3 with D = D_13 (Remark I)."""
+    _absent_species_check(lattice, shape, bc)
+
+
+def _ms_B_without_xi_factor(xi, D):
+    B = _ORIGINAL_MS_B(xi, D)
+    n = D.shape[0]
+    for i in range(n - 1):
+        for j in range(n - 1):
+            if i != j:
+                B[..., i, j] = 1.0 / D[i, n - 1] - 1.0 / D[i, j]
+    return B
+
+
+def _ms_B_transposed(xi, D):
+    return np.swapaxes(_ORIGINAL_MS_B(xi, D), -1, -2).copy()
+
+
+def _ms_B_wrong_last_species(xi, D):
+    # the diagonal's own term divided by D_i,N-1 instead of D_iN
+    B = _ORIGINAL_MS_B(xi, D)
+    n = D.shape[0]
+    for i in range(n - 1):
+        B[..., i, i] += xi[..., i] * (1.0 / D[i, n - 2 if i != n - 2 else n - 3] - 1.0 / D[i, n - 1])
+    return B
+
+
+_ORIGINAL_MS_B = ms.ms_B
+
+
+@pytest.mark.parametrize("mistake", [_ms_B_without_xi_factor, _ms_B_transposed, _ms_B_wrong_last_species])
+def test_absent_species_pin_catches_planted_mistakes(monkeypatch, mistake):
+    """The absent-species pin fails when B of Eq. (2-10) in the oracle carries
+    a plausible mistake: the off-diagonal terms without their xi_i factor, B
+    transposed, or the diagonal's own term over the wrong pair's D."""
+    monkeypatch.setattr(ms, "ms_B", mistake)
+    with pytest.raises(AssertionError):
+        _absent_species_check("D1Q3", (64,), ((lbm.ZERO_FLUX, lbm.ZERO_FLUX),))
+
+
+def _absent_species_check(lattice, shape, bc):
     rng = np.random.default_rng(61)
     D3 = _rand_D(rng, 3, 0.05, 0.5)
     nodes = tuple(reversed(shape))
