@@ -185,6 +185,57 @@ def test_planes_of_4_gib_and_more_sampled(n, N):
     torch.cuda.empty_cache()
 
 
+def test_3d_planes_of_4_gib_sampled():
+    """A 1024^3 binary D3Q7 FP32 lattice (2^30 nodes, planes of exactly 4 GiB,
+    56 GiB of state): the two-step 3D march's 32-bit plane offsets do not reach,
+    so every step is a single-step pass with 64-bit offsets along z; sampled
+    nodes (corners included) after 4 steps against the oracle on light cones."""
+    from paper_1808_06787_amd.sim import Sim
+
+    n, N, steps = 1024, 2, 4
+    rng = np.random.default_rng(13)
+    d12 = float(np.exp(rng.uniform(np.log(0.05), np.log(0.5))))
+    Dm = np.array([[1.0, d12], [d12, 1.0]])
+    dev = torch.device("cuda", 0)
+
+    def field(x, y, z, xp):
+        return (0.5 + 0.1 * xp.cos(2 * np.pi * (x / n + 2 * y / n + 3 * z / n))
+                + 0.05 * xp.sin(2 * np.pi * (5 * x / n - z / n) + 0.4) + 0.04 * xp.cos(2 * np.pi * 7 * y / n))
+
+    xi0 = torch.empty((1, n, n, n), dtype=torch.float64, device=dev)
+    ax = torch.arange(n, dtype=torch.float64, device=dev)
+    for z0 in range(0, n, 64):
+        zz, yy, xx = torch.meshgrid(torch.arange(z0, z0 + 64, dtype=torch.float64, device=dev), ax, ax,
+                                    indexing="ij")
+        xi0[0, z0:z0 + 64] = field(xx, yy, zz, torch)
+        del zz, yy, xx
+    sim = Sim("D3Q7", Dm, (n, n, n), "f32")
+    assert sim.steps_per_pass() == 1
+    sim.init(xi0)
+    sim.step(steps)
+    torch.cuda.synchronize()
+    del xi0
+    sim._xi0 = None
+    xi, J, _ = sim.read(torch.float32, grad=False)
+    h = steps + 1
+    nodes = [tuple(int(rng.integers(0, n)) for _ in range(3)) for _ in range(6)]
+    nodes += [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, n - 1)]
+    for node in nodes:
+        idx = [np.arange(c - h, c + h + 1) % n for c in node]
+        Z, Y, X = np.meshgrid(idx[2].astype(np.float64), idx[1].astype(np.float64), idx[0].astype(np.float64),
+                              indexing="ij")
+        a = field(X, Y, Z, np)
+        sub = np.stack([a, 1.0 - a])
+        p = lbm.Problem("D3Q7", Dm, (2 * h + 1,) * 3, bc=((lbm.ZERO_FLUX, lbm.ZERO_FLUX),) * 3)
+        oxi, _, oJ = lbm.observables(p, lbm.run(p, sub, steps))
+        x, y, z = node
+        assert np.abs(xi[:, z, y, x].cpu().numpy() - oxi[:, h, h, h]).max() <= 1e-5, node
+        assert np.abs(J[:, :, z, y, x].cpu().numpy() - oJ[:, :, h, h, h]).max() <= 2e-6, node
+    del xi, J
+    sim.close()
+    torch.cuda.empty_cache()
+
+
 def test_quaternary_3d_full_size_sampled():
     w = workloads.quaternary_3d()
     print("worst |dxi|", _sampled_parity(w, 3, 16, 2))
