@@ -189,6 +189,11 @@ class Sim:
             F.check(self.lib.msd_init(self._h, C.c_void_p(_dptr(t)), prec), "msd_init")
         t.record_stream(self.stream)
 
+    def release_inputs(self):
+        """Drop the reference to the initial field (after the init kernel has run)."""
+        self.stream.synchronize()
+        self._xi0 = None
+
     def step(self, n: int = 1):
         F.check(self.lib.msd_step(self._h, int(n)), "msd_step")
 

@@ -165,7 +165,7 @@ def test_planes_of_4_gib_and_more_sampled(n, N):
     sim.step(steps)
     torch.cuda.synchronize()
     del xi0
-    sim._xi0 = None
+    sim.release_inputs()
     sim.diagnostics()
     xi, J, _ = sim.read(torch.float32, grad=False)
     h = steps + 1
@@ -215,7 +215,7 @@ def test_3d_planes_of_4_gib_sampled():
     sim.step(steps)
     torch.cuda.synchronize()
     del xi0
-    sim._xi0 = None
+    sim.release_inputs()
     xi, J, _ = sim.read(torch.float32, grad=False)
     h = steps + 1
     nodes = [tuple(int(rng.integers(0, n)) for _ in range(3)) for _ in range(6)]
