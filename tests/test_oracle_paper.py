@@ -270,3 +270,24 @@ def test_small_amplitude_nonlinear_decay_matches_linearised_theory():
     amp = 2 * np.mean((xi - xbar[:2, None]) * np.cos(k * x)[None], axis=1)
     expect = expm(-k * k * np.linalg.inv(ms.ms_B(xbar, D)) * steps) @ a0
     np.testing.assert_allclose(amp, expect, rtol=0, atol=5e-3 * np.abs(a0).max())
+
+
+_ORIGINAL_LAMBDA2 = ms.lambda2_from_lambda1
+
+
+def _lambda2_rule_dropped(L1, rule=ms.RELAX_PAPER, magic=ms.MAGIC_PAPER):
+    return np.array(L1, dtype=np.float64, copy=True)
+
+
+def _lambda2_wrong_product(L1, rule=ms.RELAX_PAPER, magic=ms.MAGIC_PAPER):
+    return _ORIGINAL_LAMBDA2(L1, ms.RELAX_TRT if rule == ms.RELAX_PAPER else rule, 0.25)
+
+
+@pytest.mark.parametrize("mistake", [_lambda2_rule_dropped, _lambda2_wrong_product])
+def test_table_I_pin_catches_planted_mistakes(monkeypatch, mistake):
+    """The Table I pin of the MRT model fails when the oracle's Lambda_2 carries a
+    plausible mistake: Eq. (3-16) dropped (Lambda_2 = Lambda_1, the SRT model), or
+    the product rule taken with 1/4 instead of 3/16."""
+    monkeypatch.setattr(ms, "lambda2_from_lambda1", mistake)
+    with pytest.raises(AssertionError):
+        test_table_I_errors("MRT", ms.RELAX_PAPER)
