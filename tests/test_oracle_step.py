@@ -10,6 +10,8 @@
   relabelling the eliminated species is invisible under SRT;
 * conservation of every species' total (Eq. (2-1)) and the steady state.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -400,3 +402,20 @@ def _absent_species_check(lattice, shape, bc):
     np.testing.assert_allclose(Jt[0], Jb[0], rtol=0, atol=1e-13)
     # the binary field is not stationary: the test compares evolved states
     assert np.abs(xb[0] - two[0]).max() > 1e-3
+
+
+_ORIGINAL_STREAM = lbm.stream
+
+
+def _stream_wall_term_without_factor_two(prob, fpost):
+    # the anti-bounce-back wall term w_kbar xi_b instead of 2 w_kbar xi_b
+    halved = dataclasses.replace(prob, xi_wall={k: 0.5 * np.asarray(v) for k, v in prob.xi_wall.items()})
+    return _ORIGINAL_STREAM(halved, fpost)
+
+
+def test_dirichlet_pin_catches_a_planted_mistake(monkeypatch):
+    """The antisymmetric-extension pin fails when the oracle's anti-bounce-back
+    (Sec. 4) takes its wall term without the factor 2."""
+    monkeypatch.setattr(lbm, "stream", _stream_wall_term_without_factor_two)
+    with pytest.raises(AssertionError):
+        test_dirichlet_wall_equals_antisymmetric_extension_linear("D1Q3")
