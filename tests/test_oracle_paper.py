@@ -291,3 +291,21 @@ def test_table_I_pin_catches_planted_mistakes(monkeypatch, mistake):
     monkeypatch.setattr(ms, "lambda2_from_lambda1", mistake)
     with pytest.raises(AssertionError):
         test_table_I_errors("MRT", ms.RELAX_PAPER)
+
+
+_ORIGINAL_LAMBDA1 = ms.lambda1_from_fick
+
+
+def _lambda1_with_one_third_on_d3q7(Dt, cs2, dt=1.0):
+    # Eq. (3-26) inverted with c_s^2 = 1/3 where the D3Q7 lattice has 1/4
+    return _ORIGINAL_LAMBDA1(Dt, 1.0 / 3.0 if cs2 == 0.25 else cs2, dt)
+
+
+def test_continuum_decay_pin_catches_a_planted_sound_speed(monkeypatch):
+    """The continuum-decay pin on D3Q7 fails when the oracle inverts Eq. (3-26)
+    with the c_s^2 = 1/3 of the other lattices instead of the D3Q7 lattice's own
+    second moment of the weights, 1/4."""
+    monkeypatch.setattr(ms, "lambda1_from_fick", _lambda1_with_one_third_on_d3q7)
+    with pytest.raises(AssertionError):
+        test_binary_fourier_decay_matches_continuum("D3Q7")
+    test_binary_fourier_decay_matches_continuum("D2Q5")   # lattices with 1/3 are unaffected
