@@ -309,3 +309,18 @@ def test_continuum_decay_pin_catches_a_planted_sound_speed(monkeypatch):
     with pytest.raises(AssertionError):
         test_binary_fourier_decay_matches_continuum("D3Q7")
     test_binary_fourier_decay_matches_continuum("D2Q5")   # lattices with 1/3 are unaffected
+
+
+_ORIGINAL_FICK = ms.fick_matrix
+
+
+def _fick_matrix_transposed(B):
+    return np.swapaxes(_ORIGINAL_FICK(B), -1, -2).copy()
+
+
+def test_linearised_decay_pin_catches_a_transposed_fick_matrix(monkeypatch):
+    """The linearised-decay pin fails when the oracle's D~ = B^-1 of Eq. (2-11)
+    is transposed (the cross terms then couple the wrong pairs)."""
+    monkeypatch.setattr(ms, "fick_matrix", _fick_matrix_transposed)
+    with pytest.raises(AssertionError):
+        test_linearised_multicomponent_decay_matches_eigen_decomposition("D2Q5", ms.RELAX_PAPER)
