@@ -133,11 +133,12 @@ def test_largest_blocked_planes_sampled():
     sim.close()
 
 
-@pytest.mark.parametrize("n,N", [(32768, 3), (46340, 2)])
-def test_planes_of_4_gib_and_more_sampled(n, N):
-    """Planes of 4 GiB and more in FP32: 32768^2 ternary (2^30 nodes, planes of
-    exactly 4 GiB, 80 GiB of state) and 46340^2 binary (the largest square under
-    the 2^31-node limit, planes of 8 GiB, ragged last tiles).  The blocked sweep's
+@pytest.mark.parametrize("n,N,precision", [(32768, 3, "f32"), (46340, 2, "f32"), (23171, 2, "f64")])
+def test_planes_of_4_gib_and_more_sampled(n, N, precision):
+    """Planes of 4 GiB and more: 32768^2 ternary FP32 (2^30 nodes, planes of
+    exactly 4 GiB, 80 GiB of state), 46340^2 binary FP32 (the largest square under
+    the 2^31-node limit, planes of 8 GiB, ragged last tiles) and 23171^2 binary
+    FP64 (planes just over 4 GiB, odd extents).  The blocked sweep's
     32-bit plane offsets do not reach, so every step is a single-step pass through
     the 64-bit kernels (init, sweep, read, diagnostics); sampled nodes after 5
     steps against the oracle on light cones, corners included."""
@@ -159,7 +160,7 @@ def test_planes_of_4_gib_and_more_sampled(n, N):
         for i in range(N - 1):
             xi0[i, r0:r1] = comps[i]
         del yy, xx, comps
-    sim = Sim("D2Q5", Dm, (n, n), "f32")
+    sim = Sim("D2Q5", Dm, (n, n), precision)
     assert sim.steps_per_pass() == 1
     sim.init(xi0)
     sim.step(steps)
@@ -167,7 +168,8 @@ def test_planes_of_4_gib_and_more_sampled(n, N):
     del xi0
     sim.release_inputs()
     sim.diagnostics()
-    xi, J, _ = sim.read(torch.float32, grad=False)
+    xi, J, _ = sim.read(torch.float32 if precision == "f32" else torch.float64, grad=False)
+    tol_xi, tol_j = (1e-5, 2e-6) if precision == "f32" else (1e-12, 1e-12)
     h = steps + 1
     nodes = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(8)]
     nodes += [(0, 0), (n - 1, n - 1), (n - 1, 0), (n - 3, n // 2)]
@@ -178,8 +180,8 @@ def test_planes_of_4_gib_and_more_sampled(n, N):
         sub = np.stack(_wave_field(X, Y, n, N, np))
         p = lbm.Problem("D2Q5", Dm, (2 * h + 1, 2 * h + 1), bc=((lbm.ZERO_FLUX, lbm.ZERO_FLUX),) * 2)
         oxi, _, oJ = lbm.observables(p, lbm.run(p, sub, steps))
-        assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= 1e-5, (n, x, y)
-        assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= 2e-6, (n, x, y)
+        assert np.abs(xi[:, y, x].cpu().numpy() - oxi[:, h, h]).max() <= tol_xi, (n, x, y)
+        assert np.abs(J[:, :, y, x].cpu().numpy() - oJ[:, :, h, h]).max() <= tol_j, (n, x, y)
     del xi, J
     sim.close()
     torch.cuda.empty_cache()
